@@ -1,0 +1,418 @@
+"""Pins of the CPU oracle against things other than itself: hand-derived fixtures,
+brute-force boundary-condition assemblies (Section 2), closed forms, invariants the paper
+fixes (preserved polynomials, eigenvalue z(0)), and agreement of two independent routes
+to the Tikhonov solution (eqs. freg vs nerebl) and to GCV (eqs. gcv vs gcv2)."""
+
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import bc, tikhonov as tk, transforms as tr, twod
+from paper_0906_2704_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+KINDS_SYM = ["AR", "C", "DST2", "DST3"]
+
+
+def _frac(s):
+    return float(Fraction(s))
+
+
+def _expr(s):
+    return float(eval(s, {"sqrt": math.sqrt, "__builtins__": {}}))
+
+
+def _parse_ar_golden():
+    cases, cur = {}, None
+    for line in open(os.path.join(GOLDEN, "ar_bc_small.txt")):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("["):
+            cur = {"rows": []}
+            cases[line.strip("[]")] = cur
+            continue
+        key, rest = line.split(" ", 1)
+        if key == "psf":
+            cur["psf"] = np.array([_frac(v) for v in rest.split()])
+        elif key == "row":
+            cur["rows"].append([_frac(v) for v in rest.split()])
+        elif key == "eig":
+            cur["eig"] = np.array([_expr(v) for v in rest.split(";")])
+    return cases
+
+
+def rand_sym_psf(rng, m):
+    h = rng.random(m + 1) + 0.1
+    full = np.concatenate([h[:0:-1], h])
+    return full / full.sum(), m
+
+
+def rand_psf(rng, m, center=None):
+    h = rng.random(2 * m + 1) + 0.05
+    return h / h.sum(), (m if center is None else center)
+
+
+# ------------------------------------------------------------------ hand fixtures
+
+def test_golden_antireflective_matrices():
+    for name, case in _parse_ar_golden().items():
+        n = len(case["rows"])
+        h = case["psf"]
+        c = (len(h) - 1) // 2
+        want = np.array(case["rows"])
+        A_bc = bc.blur_matrix_bc("antireflective", n, h, c)
+        assert np.abs(A_bc - want).max() < 1e-15, name
+        A_sp = tr.blur_matrix("AR", n, h, c).astype(np.float64)
+        assert np.abs(A_sp - want).max() < 1e-14, name
+        d = tr.blur_eigs("AR", n, h, c)
+        assert np.abs(d - case["eig"]).max() < 1e-15, name
+
+
+def test_golden_polynomial_columns():
+    vals = {}
+    for line in open(os.path.join(GOLDEN, "poly_columns_n5.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            key, rest = line.split(" ", 1)
+            vals[key] = np.array([_expr(v) for v in rest.split()])
+    assert np.abs(tr.ar_p(5).astype(float) - vals["p"]).max() < 4e-16
+    assert np.abs(tr.quad_q("C", 5).astype(float) - vals["qC"]).max() < 4e-16
+    assert np.abs(tr.quad_q("F", 5).astype(float) - vals["qF"]).max() < 4e-16
+    for kind, key in (("AR", "p"), ("C", "qC"), ("F", "qF")):
+        T = tr.transform_matrix(kind, 5)
+        assert np.abs(T[:, 0].astype(complex) - vals[key]).max() < 4e-16
+        assert np.abs(T[:, 4].astype(complex) - vals[key][::-1]).max() < 4e-16
+
+
+@pytest.mark.parametrize("n", [5, 6, 17, 64, 257, 1000])
+def test_p_closed_form_norm(n):
+    """R1: the printed factor sqrt(n(2n-1)/(6(n-1))) is ||(1-(i-1)/(n-1))_i||_2."""
+    p = tr.ar_p(n)
+    assert abs(float(np.sum(p * p)) - 1.0) < 1e-15
+    assert abs(float(p[0]) - 1.0 / math.sqrt(n * (2 * n - 1) / (6.0 * (n - 1)))) < 1e-15
+    for kind in ("C", "F"):
+        q = tr.quad_q(kind, n)
+        assert abs(float(np.sum(q * q)) - 1.0) < 1e-15
+        assert q[-1] == 0  # q_n = 0: the decoupling used by Theorem th:inv
+
+
+# --------------------------------------------------- brute-force boundary conditions
+
+@pytest.mark.parametrize("n,m", [(7, 2), (12, 3), (24, 5), (41, 8), (64, 30)])
+def test_antireflective_spectral_equals_bc(n, m):
+    rng = np.random.default_rng(n * 100 + m)
+    h, c = rand_sym_psf(rng, m)
+    A_bc = bc.blur_matrix_bc("antireflective", n, h, c)
+    A_sp = tr.blur_matrix("AR", n, h, c).astype(np.float64)
+    assert np.abs(A_bc - A_sp).max() < 1e-14
+
+
+@pytest.mark.parametrize("n", [6, 13, 40])
+def test_second_difference_spectral_equals_stencil(n):
+    L = bc.second_difference_ar(n)
+    Ls = tr.smoothing_matrix("AR", n, "D2").astype(np.float64)
+    assert np.abs(L - Ls).max() < 1e-14
+
+
+@pytest.mark.parametrize("n,m", [(9, 2), (16, 4), (33, 7)])
+def test_reflective_and_periodic_comparators(n, m):
+    rng = np.random.default_rng(n)
+    hs, cs = rand_sym_psf(rng, m)
+    A_R = bc.blur_matrix_bc("reflective", n, hs, cs)
+    C = tr.dct2_matrix(n).astype(np.float64)
+    d = tr.blur_eigs("R", n, hs, cs)
+    assert np.abs(C.T @ np.diag(d) @ C - A_R).max() < 1e-14          # eq. refm
+    hn, cn = rand_psf(rng, m, center=m - 1)                           # nonsymmetric
+    A_P = bc.blur_matrix_bc("periodic", n, hn, cn)
+    F = tr.dft_matrix(n).astype(np.complex128)
+    dP = tr.blur_eigs("P", n, hn, cn)
+    assert np.abs(F.conj().T @ np.diag(dP) @ F - A_P).max() < 1e-14  # eq. permat (R4)
+    e1 = np.zeros(n)
+    e1[0] = 1.0
+    lam = (F @ (A_P @ e1)) / (F @ e1)        # the paper's first-column formula
+    assert np.abs(lam - dP).max() < 1e-14
+
+
+@pytest.mark.parametrize("n,m", [(10, 2), (20, 5), (37, 8)])
+def test_TC_core_eigenvalues_are_reflective_of_order_n_minus_2(n, m):
+    rng = np.random.default_rng(n + 1)
+    h, c = rand_sym_psf(rng, m)
+    N = n - 2
+    A_R = bc.blur_matrix_bc("reflective", N, h, c)
+    C = tr.dct2_matrix(N).astype(np.float64)
+    lam = np.diag(C @ A_R @ C.T)
+    assert np.abs(C @ A_R @ C.T - np.diag(lam)).max() < 1e-14
+    d = tr.blur_eigs("C", n, h, c)
+    assert np.abs(d[1:n - 1] - lam).max() < 1e-14
+    assert d[0] == d[-1] == pytest.approx(1.0, abs=1e-15)
+
+
+@pytest.mark.parametrize("n,m", [(10, 2), (21, 5), (40, 9)])
+def test_TF_core_eigenvalues_are_periodic_of_order_n_minus_2(n, m):
+    """Pins R2 (grid /(n-2)) and R4 (conj z under convolution) for T_F's core."""
+    rng = np.random.default_rng(n + 2)
+    h, c = rand_psf(rng, m, center=m + 1 if m > 2 else m)
+    N = n - 2
+    A_P = bc.blur_matrix_bc("periodic", N, h, c)
+    F = tr.dft_matrix(N).astype(np.complex128)
+    M = F @ A_P @ F.conj().T
+    assert np.abs(M - np.diag(np.diag(M))).max() < 1e-14
+    d = tr.blur_eigs("F", n, h, c)
+    assert np.abs(d[1:n - 1] - np.diag(M)).max() < 1e-14
+
+
+@pytest.mark.parametrize("n", [5, 8, 19, 64])
+def test_transform_structure(n):
+    """The middle blocks are the printed cores; the boundary rows are c_a, c_b (eqs. Tc,
+    Tf) and the zero rows of eq. ART."""
+    N = n - 2
+    T = tr.transform_matrix("AR", n).astype(np.float64)
+    assert np.abs(T[1:n - 1, 1:n - 1] - tr.dst1_matrix(N).astype(np.float64)).max() < 1e-16
+    assert np.all(T[0, 1:n - 1] == 0) and np.all(T[n - 1, 1:n - 1] == 0)
+    TC = tr.transform_matrix("C", n).astype(np.float64)
+    C = tr.dct2_matrix(N).astype(np.float64)
+    assert np.abs(TC[1:n - 1, 1:n - 1] - C.T).max() < 1e-16
+    j = np.arange(1, N + 1)
+    a = -math.pi / (2 * n - 4)
+    ca = np.sqrt((2.0 - (j == 1)) / N) * np.cos((j - 1) * a)
+    assert np.abs(TC[0, 1:n - 1] - ca).max() < 1e-15
+    assert np.abs(TC[n - 1, 1:n - 1] - (-1.0) ** (j - 1) * ca).max() < 1e-15
+    TF = tr.transform_matrix("F", n).astype(np.complex128)
+    F = tr.dft_matrix(N).astype(np.complex128)
+    assert np.abs(TF[1:n - 1, 1:n - 1] - F.conj().T).max() < 1e-16
+    aF = -2 * math.pi / N
+    assert np.abs(TF[0, 1:n - 1] - np.exp(1j * (j - 1) * aF) / math.sqrt(N)).max() < 1e-15
+    assert np.abs(TF[n - 1, 1:n - 1] - 1 / math.sqrt(N)).max() < 1e-15
+
+
+# --------------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("kind", KINDS_SYM + ["F"])
+@pytest.mark.parametrize("n", [12, 31, 64])
+def test_polynomials_preserved(kind, n):
+    rng = np.random.default_rng(n)
+    if kind == "F":
+        h, c = rand_psf(rng, 3, center=2)
+    else:
+        h, c = rand_sym_psf(rng, 3)
+    A = tr.blur_matrix(kind, n, h, c).astype(np.complex128)
+    x = np.linspace(-1.0, 1.5, n)
+    deg = tr.degree_of(kind)
+    for k in range(deg + 1):
+        assert np.abs(A @ x ** k - x ** k).max() < 1e-12
+    # one degree higher is not preserved
+    assert np.abs(A @ x ** (deg + 1) - x ** (deg + 1)).max() > 1e-6
+    # and the smoothing operator annihilates the preserved space
+    L = tr.smoothing_matrix(kind, n, "D2").astype(np.complex128)
+    for k in range(deg + 1):
+        assert np.abs(L @ x ** k).max() < 1e-11
+
+
+@pytest.mark.parametrize("kind", KINDS_SYM + ["F", "P", "R"])
+def test_delta_psf_gives_identity(kind):
+    n = 16
+    A = tr.blur_matrix(kind, n, np.array([1.0]), 0).astype(np.complex128)
+    assert np.abs(A - np.eye(n)).max() < 1e-14
+
+
+def test_AF_real_for_real_psf_only_with_grid_over_n_minus_2():
+    """R2: with x_i = (i-2) 2pi/(n-2) the model A_F is real for a real PSF; the printed
+    grid (i-2) 2pi/n would make it complex."""
+    n = 30
+    h, c = rand_psf(np.random.default_rng(3), 4, center=3)
+    A = tr.blur_matrix("F", n, h, c)
+    assert np.abs(A.imag).max() < 1e-15
+    T = tr.transform_matrix("F", n)
+    d_alt = tr.blur_eigs("F", n, h, c).copy()
+    i = np.arange(2, n)
+    d_alt[1:n - 1] = tr.symbol(h, c, -2 * (i - 2), n)[:].astype(np.complex128)
+    A_alt = (T * d_alt[None, :]) @ tr._dense_inverse("F", n)
+    assert np.abs(A_alt.imag).max() > 1e-3
+
+
+@pytest.mark.parametrize("kind", ["AR", "C", "F", "DST3"])
+@pytest.mark.parametrize("n", [9, 64, 255])
+def test_inverse_roundtrip(kind, n):
+    rng = np.random.default_rng(n)
+    y = rng.standard_normal(n)
+    x = tr.inverse(kind, y)
+    assert np.abs(tr.forward(kind, x) - y).max() < 1e-14 * np.abs(y).max() * n
+    if not tr.is_complex(kind):
+        assert np.isrealobj(x)
+
+
+def test_F_coefficients_of_real_signal_are_hermitian():
+    n = 40
+    y = np.random.default_rng(1).standard_normal(n)
+    x = tr.inverse("F", y)
+    core = x[1:n - 1]
+    assert abs(x[0].imag) < 1e-15 and abs(x[-1].imag) < 1e-15
+    assert np.abs(core[1:] - np.conj(core[1:][::-1])).max() < 1e-14
+
+
+# --------------------------------------------------------- restoration: two routes
+
+@pytest.mark.parametrize("kind", KINDS_SYM + ["F"])
+@pytest.mark.parametrize("norm", ["I", "D2"])
+@pytest.mark.parametrize("mu", [1e-4, 1e-2])
+def test_spectral_filter_solves_reblurred_normal_equations(kind, norm, mu):
+    n = 48
+    rng = np.random.default_rng(7)
+    h, c = rand_psf(rng, 3, center=2) if kind == "F" else rand_sym_psf(rng, 3)
+    g = rng.standard_normal(n)
+    f1 = tk.restore_spectral(kind, g, h, c, norm, mu)
+    f2 = tk.restore_normal_equations(kind, g, h, c, norm, mu)
+    assert np.abs(f1 - f2).max() < 1e-9 * np.abs(f1).max()
+    if kind == "AR":
+        # fully independent route: A from the boundary conditions, L from eq. L
+        A = bc.blur_matrix_bc("antireflective", n, h, c)
+        L = bc.second_difference_ar(n) if norm == "D2" else np.eye(n)
+        f3 = tk.solve_normal_equations(A.astype(np.longdouble), A.astype(np.longdouble),
+                                       L.astype(np.longdouble), g, mu).astype(np.float64)
+        assert np.abs(f1 - f3).max() < 1e-9 * np.abs(f1).max()
+
+
+@pytest.mark.parametrize("kind", KINDS_SYM + ["F"])
+def test_noise_free_polynomial_restored_exactly(kind):
+    """A preserved polynomial is a fixed point of the filter with L = D2, for every mu."""
+    n = 64
+    rng = np.random.default_rng(11)
+    h, c = rand_psf(rng, 4, center=3) if kind == "F" else rand_sym_psf(rng, 4)
+    x = np.linspace(0.0, 1.0, n)
+    P = np.polyval(rng.standard_normal(tr.degree_of(kind) + 1), x)
+    for mu in (1e-6, 1e-1, 10.0):
+        f = tk.restore_spectral(kind, P, h, c, "D2", mu)
+        assert np.abs(f - P).max() < 1e-12 * np.abs(P).max()
+
+
+# ----------------------------------------------------------------------------- GCV
+
+@pytest.mark.parametrize("norm", ["I", "D2"])
+def test_gcv_formula_equals_exact_gcv_for_periodic(norm):
+    """For the unitary periodic basis eq. gcv2 is exact (Section 4.2): the oracle's
+    spectral G equals ||g - A f||^2 / trace(I - A (A'A + mu L'L)^{-1} A')^2 assembled
+    densely from the periodic boundary conditions."""
+    n = 32
+    rng = np.random.default_rng(5)
+    h, c = rand_psf(rng, 3, center=4)
+    A = bc.blur_matrix_bc("periodic", n, h, c)
+    if norm == "D2":
+        L = 2 * np.eye(n) - np.roll(np.eye(n), 1, axis=1) - np.roll(np.eye(n), -1, axis=1)
+    else:
+        L = np.eye(n)
+    g = rng.standard_normal(n)
+    d = tr.blur_eigs("P", n, h, c)
+    s = tr.smooth_eigs("P", n, norm)
+    ghat = tr.inverse("P", g)
+    for mu in (1e-3, 1e-1):
+        M = A.T @ A + mu * L.T @ L
+        H = A @ np.linalg.solve(M, A.T)
+        f = np.linalg.solve(M, A.T @ g)
+        exact = np.sum((g - A @ f) ** 2) / np.trace(np.eye(n) - H) ** 2
+        G = tk.gcv_values(ghat, d, s, [mu])[0]
+        assert abs(G - exact) < 1e-10 * exact
+
+
+@pytest.mark.parametrize("kind", ["AR", "C", "F", "DST3"])
+def test_gcv_trace_identity(kind):
+    """R8: trace(I - A T Phi D^{-1} T^{-1}) = sum_i mu sigma_i."""
+    n = 30
+    rng = np.random.default_rng(9)
+    h, c = rand_psf(rng, 3, center=2) if kind == "F" else rand_sym_psf(rng, 3)
+    mu = 3e-3
+    T = tr.transform_matrix(kind, n)
+    Tinv = tr._dense_inverse(kind, n)
+    A = tr.blur_matrix(kind, n, h, c)
+    d = tr.blur_eigs(kind, n, h, c).astype(np.clongdouble)
+    s = tr.smooth_eigs(kind, n, "D2").astype(np.longdouble)
+    H = A @ (T * (np.conj(d) / ((d * np.conj(d)).real + mu * s * s))[None, :]) @ Tinv
+    lhs = complex(np.trace(np.eye(n) - H))
+    sigma = s * s / ((d * np.conj(d)).real + mu * s * s)
+    assert abs(lhs - float(mu * np.sum(sigma))) < 1e-12 * abs(lhs)
+
+
+def test_gcv_brute_force_and_argmin_rules():
+    rng = np.random.default_rng(2)
+    n = 20
+    ghat = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    d = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    s = rng.random(n)
+    mus = [1e-3, 1e-2, 1e-1]
+    G = tk.gcv_values(ghat, d, s, mus)
+    for k, mu in enumerate(mus):
+        num = den = 0.0
+        for i in range(n):
+            sig = s[i] ** 2 / (abs(d[i]) ** 2 + mu * s[i] ** 2)
+            num += abs(sig * ghat[i]) ** 2
+            den += sig
+        assert abs(G[k] - num / den ** 2) < 1e-13 * G[k]
+    assert tk.gcv_argmin([3.0, 1.0, 2.0, 1.0]) == 1
+    with pytest.raises(FloatingPointError):
+        tk.gcv_argmin([1.0, float("nan")])
+
+
+def test_gcv_picks_reasonable_mu_on_config0():
+    """Sanity of the whole chain on the 1D workload: mu_GCV restores far better than
+    the extreme grid ends."""
+    p = synth.config0(0)
+    kind = "C"
+    n = p.g.size
+    d = tr.blur_eigs(kind, n, p.h, p.center)
+    s = tr.smooth_eigs(kind, n, "D2")
+    ghat = tr.inverse(kind, p.g)
+    G, k, mu = tk.gcv_scan(ghat, d, s, p.mus)
+    rre = lambda mu_: np.linalg.norm(tk.restore_spectral(kind, p.g, p.h, p.center, "D2", mu_)
+                                     - p.f_true) / np.linalg.norm(p.f_true)
+    assert rre(mu) < rre(p.mus[0]) and rre(mu) < rre(p.mus[-1])
+
+
+# ------------------------------------------------------------------------------ 2D
+
+def _ar_extend_2d(F, m):
+    """Extend an image by the antireflective rule along axis 0, then axis 1."""
+    def ext1(v):
+        n = v.shape[0]
+        out = np.empty((n + 2 * m,) + v.shape[1:])
+        out[m:m + n] = v
+        for j in range(1, m + 1):
+            out[m - j] = 2 * v[0] - v[j]
+            out[m + n - 1 + j] = 2 * v[n - 1] - v[n - 1 - j]
+        return out
+    E = ext1(F)
+    return ext1(E.T).T
+
+
+def test_2d_antireflective_brute_force_equals_kronecker():
+    n0, n1, m = 7, 8, 2
+    rng = np.random.default_rng(4)
+    h0, c0 = rand_sym_psf(rng, m)
+    h1, c1 = rand_sym_psf(rng, m)
+    A = np.zeros((n0 * n1, n0 * n1))
+    for col in range(n0 * n1):
+        E = np.zeros(n0 * n1)
+        E[col] = 1.0
+        X = _ar_extend_2d(E.reshape(n0, n1), m)
+        G = synth.observe_2d(X, h0, c0, h1, c1, (n0, n1))
+        A[:, col] = G.ravel()
+    K = np.kron(bc.blur_matrix_bc("antireflective", n0, h0, c0),
+                bc.blur_matrix_bc("antireflective", n1, h1, c1))
+    assert np.abs(A - K).max() < 1e-14
+    T2 = twod.kron_transform("AR", "AR", n0, n1).astype(np.float64)
+    D = twod.eigs2d_separable("AR", "AR", n0, n1, h0, c0, h1, c1).ravel()
+    assert np.abs(T2 @ np.diag(D) @ np.linalg.inv(T2) - A).max() < 1e-13
+
+
+@pytest.mark.parametrize("k0,k1", [("F", "F"), ("C", "C"), ("AR", "DST3")])
+def test_2d_axis_passes_equal_kronecker(k0, k1):
+    n0, n1 = 9, 11
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((n0, n1))
+    K = twod.kron_transform(k0, k1, n0, n1).astype(np.complex128)
+    Y = twod.forward2d(k0, k1, X)
+    assert np.abs(Y.ravel() - K @ X.ravel()).max() < 1e-14
+    Z = twod.inverse2d(k0, k1, X)
+    assert np.abs(K @ Z.ravel() - X.ravel()).max() < 1e-13
