@@ -1,0 +1,144 @@
+/*
+ * ht.h -- C ABI of the MI355X (gfx950) library for spectral Tikhonov deblurring under
+ * high-order (polynomial preserving) boundary conditions, after M. Donatelli, "Fast
+ * transforms for high order boundary conditions".
+ *
+ * Problem statement (Sections 2 and 4 of the paper): an observed signal or image g, a PSF
+ * mask h_{-m..m} with symbol z(t) = sum_j h_j e^{ijt} (eq. symbol), a boundary model that
+ * preserves sampled polynomials of a given degree, a smoothing operator L (identity or
+ * second difference / Laplacian) and a regularisation parameter mu > 0.  The blurring
+ * matrix is A = T diag(d) T^{-1} for a fast transform T (eqs. ART, Tc, Tf), and the
+ * restoration is f = T Phi D^{-1} T^{-1} g (eq. freg) with mu chosen by GCV (eq. mugcv).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller, except where a
+ *     parameter is documented as a host array.  The library never frees caller memory.
+ *   - Calls are asynchronous on the given HIP stream (0 = legacy default stream) and
+ *     allocate nothing: a plan owns every table and workspace it needs.
+ *   - Arguments are validated on the host before anything is launched; on error nothing
+ *     is launched and a status other than HT_OK is returned.  ht_last_error() returns a
+ *     thread-local message describing the most recent failure.  No exception crosses the
+ *     ABI.  With batch = 0 a call validates its sizes, launches nothing and returns
+ *     HT_OK; its array arguments may then be NULL.
+ *   - Signals are real float64.  Coefficient vectors ("coeff"), filtered coefficients and
+ *     eigenvalues d are float64 for the real kinds (AR, C, DST2, DST3) and interleaved
+ *     complex128 (re, im) for the kind F.  Coefficients are ordered like the columns of
+ *     T: [first polynomial column, the n-2 core columns, last polynomial column].
+ *   - A batch of 1D signals is a contiguous [batch][n] array; a batch of images is
+ *     [batch][n0][n1], row-major, coefficients in the same layout.
+ *   - PSF convention: psf[idx] is the tap h_{idx - center}; the blur is the convolution
+ *     g_i = sum_j h_j f_{i-j} (the PSF is the blur of a single pixel, Section 1).
+ */
+#ifndef HT_H
+#define HT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HT_OK = 0,
+    HT_ERR_INVALID_ARG = 1,   /* null pointer, size out of range, bad enum value          */
+    HT_ERR_UNSUPPORTED = 2,   /* e.g. a nonsymmetric PSF with a degree that needs symmetry */
+    HT_ERR_PSF_TOO_WIDE = 3,  /* 2m+1 > n-2 (eq. jcf requires 2m+1 <= n-2)                 */
+    HT_ERR_SINGULAR = 4,      /* a boundary capacitance matrix is singular                 */
+    HT_ERR_NONFINITE = 5,     /* non-finite data detected                                  */
+    HT_ERR_HIP = 6,           /* a HIP runtime call failed                                 */
+    HT_ERR_OOM = 7            /* device or host allocation failed (plan creation only)     */
+} ht_status;
+
+/* Which transform family realises a boundary degree.
+ *  HT_FAMILY_PAPER: degree 1 -> antireflective T (eq. ART, symmetric PSF);
+ *                   degree 2 -> T_C (eq. Tc) for a symmetric PSF, T_F (eq. Tf) otherwise.
+ *  HT_FAMILY_DST:   degree 1..3 -> the antireflective transform whose lowest degree-1
+ *                   sine columns are replaced by polynomial "bubbles" (symmetric PSF);
+ *                   degree 1 is identical to the antireflective transform.            */
+typedef enum { HT_FAMILY_PAPER = 0, HT_FAMILY_DST = 1 } ht_family;
+
+/* Smoothing operator of eq. mintik: L = I, or the second difference with the same
+ * boundary model (eq. L, L_C, L_F; in 2D the Laplacian L0 (x) I + I (x) L1).          */
+typedef enum { HT_NORM_IDENTITY = 0, HT_NORM_SECOND_DIFF = 1 } ht_norm;
+
+/* What a plan resolved to (per axis). */
+typedef enum { HT_KIND_AR = 1, HT_KIND_C = 2, HT_KIND_F = 3, HT_KIND_DST2 = 4, HT_KIND_DST3 = 5 } ht_kind;
+
+typedef struct ht_plan ht_plan;
+
+/* Create a plan for signals of length n[0] (ndim = 1) or images n[0] x n[1] (ndim = 2).
+ *   degree         preserved polynomial degree (1..3, see ht_family)
+ *   psf_symmetric  nonzero if h_{-j} = h_j (selects T_C over T_F for degree 2)
+ *   family         ht_family
+ *   max_batch      2D only: number of images one call may process (sizes the plan's
+ *                  workspace); ignored for 1D
+ * Lengths must satisfy 5 <= n <= 8192.  The plan owns all device tables (boundary
+ * vectors and 2x2 solves of Theorem th:inv in closed form, chirp and filter-spectrum
+ * tables of the core transform, trigonometric tables of the exactly reduced angles).
+ * Returns HT_ERR_UNSUPPORTED for combinations the paper does not define (degree 3 in
+ * HT_FAMILY_PAPER, a nonsymmetric PSF with the antireflective or DST family).        */
+ht_status ht_plan_create(int ndim, const int64_t* n /* host [ndim] */, int degree,
+                         int psf_symmetric, int family, int64_t max_batch, ht_plan** out);
+ht_status ht_plan_destroy(ht_plan* plan);
+/* Kind of axis `axis` (0 or 1), or -1 on a bad argument. */
+int ht_plan_kind(const ht_plan* plan, int axis);
+/* 1 if coefficients / eigenvalues are complex128 (kind F on any axis), else 0. */
+int ht_plan_is_complex(const ht_plan* plan);
+
+/* ht_eigs -- eigenvalues d of the blurring matrix and s of the smoothing operator in the
+ * plan's basis (eqs. jcf, Ac, Af; L_A, L_C, L_F of Section 4), computed from the PSF by
+ * direct summation of z at exactly reduced angles.  The preserved-polynomial columns get
+ * d = z(0) = sum_j h_j and s = 0 (s = 1 for L = I).
+ *   1D: psf [batch][psf_len[0]] (device), d [batch][n], s [batch][n].
+ *   2D: psf = [h0 (psf_len[0]) | h1 (psf_len[1])], a separable PSF h0 (x) h1; outputs are
+ *       the 1D factors d = [d0 (n0) | d1 (n1)], s = [s0 (n0) | s1 (n1)] with
+ *       d_ij = d0_i d1_j and s_ij = s0_i + s1_j (for L = I: s0 = 1, s1 = 0).  batch = 1.
+ *   psf_len, psf_center: host arrays [ndim].  Requires 2m+1 <= n-2 per axis, with
+ *   m = max(center, len-1-center) (HT_ERR_PSF_TOO_WIDE otherwise).  For the real kinds
+ *   the mask is used through Re z(t), i.e. its even part.                              */
+ht_status ht_eigs(const ht_plan* plan, const double* psf, const int64_t* psf_len,
+                  const int64_t* psf_center, int norm, void* d, double* s, int64_t batch,
+                  hipStream_t stream);
+
+/* ht_transform_inv -- coeff = T^{-1} signal (Theorem th:inv): the 2x2 boundary system in
+ * float64, the interior correction, one core analysis transform (DST-I, DCT-II or DFT of
+ * order n-2) and, for DST2/DST3, the rank-(degree-1) correction.  In 2D the 1D transform
+ * runs along axis 1 then axis 0 (Section 6).  signal and coeff must not overlap.       */
+ht_status ht_transform_inv(const ht_plan* plan, const double* signal, void* coeff,
+                           int64_t batch, hipStream_t stream);
+
+/* ht_transform_fwd -- signal = T coeff (the direct transform).  For kind F the result of
+ * a Hermitian coefficient vector (the image of a real signal under T^{-1}, or any vector
+ * the filter produces from one) is real; the library returns its real part.          */
+ht_status ht_transform_fwd(const ht_plan* plan, const void* coeff, double* signal,
+                           int64_t batch, hipStream_t stream);
+
+/* ht_tikhonov_filter -- fhat_i = conj(d_i) coeff_i / (|d_i|^2 + mu |s_i|^2), i.e.
+ * Phi D^{-1} coeff of eq. freg (reblurred Tikhonov, eq. nerebl), in float64.
+ *   d, s: eig_batch = 1 (shared by every item) or eig_batch = batch (one per item).
+ *   mu:   device [batch], mu > 0.  fhat may alias coeff.                               */
+ht_status ht_tikhonov_filter(const ht_plan* plan, const void* coeff, const void* d,
+                             const double* s, int64_t eig_batch, const double* mu,
+                             void* fhat, int64_t batch, hipStream_t stream);
+
+/* ht_gcv_scan -- G(mu_k) = sum_i |sigma_i coeff_i|^2 / (sum_i sigma_i)^2 with
+ * sigma_i = |s_i|^2 / (|d_i|^2 + mu_k |s_i|^2) (eqs. gcv2, mugcv) for every mu_k of the
+ * grid, and the index of its first minimum.  Sums are float64 in a fixed order, so the
+ * result is bitwise reproducible run to run.
+ *   mu_grid: device [K] (grid_per_item = 0) or [batch][K] (grid_per_item = 1), mu_k > 0.
+ *   G: device [batch][K] or NULL.  k_best: device int32 [batch] (-1 if some G_k is not
+ *   finite).  mu_best: device [batch] or NULL (NaN when k_best = -1).  1 <= K <= 1024.  */
+ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const void* d, const double* s,
+                      int64_t eig_batch, const double* mu_grid, int32_t K, int grid_per_item,
+                      double* G, int32_t* k_best, double* mu_best, int64_t batch,
+                      hipStream_t stream);
+
+const char* ht_status_str(ht_status status);
+const char* ht_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HT_H */

@@ -1,0 +1,157 @@
+// Workgroup-wide complex float64 FFT of a power-of-two length P held in LDS.
+//
+// Layout: the workgroup has BLOCK = P / 8 threads; thread t owns the eight "slots"
+// t + s * BLOCK, s = 0..7, held in registers between passes.  Each pass is a Stockham
+// autosort step of radix 8 (a final radix 2 or 4 pass covers the remaining bits): every
+// pass reads the thread's own slots, applies the pass twiddles, does a radix-R DFT in
+// registers and scatters the results to their positions for the next pass.  The first
+// pass therefore takes its input straight from registers and the last pass leaves its
+// output in registers, already in natural order, so a full FFT costs (passes - 1) LDS
+// round trips.  Twiddles come from the global table tw[m] = exp(-2 pi i m / TWN).
+//
+// DIR = -1: X_k = sum_j x_j e^{-2 pi i jk/P};  DIR = +1: unnormalised inverse.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ht_internal.h"
+
+namespace ht {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
+    return make_double2(fma(a.x, b.x, a.y * b.y), fma(a.y, b.x, -a.x * b.y));
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// multiply by exp(DIR * i pi / 2): -i for the forward direction, +i for the inverse
+template <int DIR>
+__device__ __forceinline__ double2 rot90(double2 a) {
+    return DIR < 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft2(double2& a, double2& b) {
+    double2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(double2& x0, double2& x1, double2& x2, double2& x3) {
+    double2 a = cadd(x0, x2), b = csub(x0, x2);
+    double2 c = cadd(x1, x3), d = rot90<DIR>(csub(x1, x3));
+    x0 = cadd(a, c);
+    x2 = csub(a, c);
+    x1 = cadd(b, d);
+    x3 = csub(b, d);
+}
+
+// multiply by exp(DIR * i pi / 4)
+template <int DIR>
+__device__ __forceinline__ double2 rot45(double2 a) {
+    const double h = 0.70710678118654752440;  // 1 / sqrt(2)
+    return DIR < 0 ? make_double2((a.x + a.y) * h, (a.y - a.x) * h)
+                   : make_double2((a.x - a.y) * h, (a.x + a.y) * h);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft8(double2 (&u)[8]) {
+    double2 e0 = u[0], e1 = u[2], e2 = u[4], e3 = u[6];
+    double2 o0 = u[1], o1 = u[3], o2 = u[5], o3 = u[7];
+    dft4<DIR>(e0, e1, e2, e3);
+    dft4<DIR>(o0, o1, o2, o3);
+    o1 = rot45<DIR>(o1);
+    o2 = rot90<DIR>(o2);
+    o3 = rot90<DIR>(rot45<DIR>(o3));
+    u[0] = cadd(e0, o0); u[4] = csub(e0, o0);
+    u[1] = cadd(e1, o1); u[5] = csub(e1, o1);
+    u[2] = cadd(e2, o2); u[6] = csub(e2, o2);
+    u[3] = cadd(e3, o3); u[7] = csub(e3, o3);
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dftR(double2 (&u)[R]);
+template <>
+__device__ __forceinline__ void dftR<2, -1>(double2 (&u)[2]) { dft2<-1>(u[0], u[1]); }
+template <>
+__device__ __forceinline__ void dftR<2, 1>(double2 (&u)[2]) { dft2<1>(u[0], u[1]); }
+template <>
+__device__ __forceinline__ void dftR<4, -1>(double2 (&u)[4]) { dft4<-1>(u[0], u[1], u[2], u[3]); }
+template <>
+__device__ __forceinline__ void dftR<4, 1>(double2 (&u)[4]) { dft4<1>(u[0], u[1], u[2], u[3]); }
+template <>
+__device__ __forceinline__ void dftR<8, -1>(double2 (&u)[8]) { dft8<-1>(u); }
+template <>
+__device__ __forceinline__ void dftR<8, 1>(double2 (&u)[8]) { dft8<1>(u); }
+
+// One Stockham pass of radix R with Ns = product of the radices of earlier passes.
+template <int R, int DIR, int BLOCK, bool FIRST, bool LAST>
+__device__ __forceinline__ void stockham_pass(double2 (&v)[8], double2* lds,
+                                              const double2* __restrict__ tw, int Ns) {
+    constexpr int C = 8 / R;  // butterflies per thread
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int t = tid + c * BLOCK;
+        double2 u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[c + r * C];
+        const int k = t & (Ns - 1);
+        if (!FIRST) {
+            const int step = (TWN / (Ns * R)) * k;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                double2 w = tw[step * r];
+                u[r] = DIR < 0 ? cmul(u[r], w) : cmulc(u[r], w);
+            }
+        }
+        dftR<R, DIR>(u);
+        if (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[c + r * C] = u[r];
+        } else {
+            const int base = (t - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[base + r * Ns] = u[r];
+        }
+    }
+    if (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = lds[tid + s * BLOCK];
+        __syncthreads();
+    }
+}
+
+// Full FFT of length P = 2^LOGP on the slots v (natural order in, natural order out).
+template <int LOGP, int DIR>
+__device__ __forceinline__ void fft_slots(double2 (&v)[8], double2* lds, const double2* __restrict__ tw) {
+    constexpr int P = 1 << LOGP;
+    constexpr int BLOCK = P / 8;
+    constexpr int NR8 = LOGP / 3;
+    constexpr int REM = LOGP % 3;
+    static_assert(LOGP >= 9 && LOGP <= 13, "FFT length out of range");
+    // radix-8 passes
+    stockham_pass<8, DIR, BLOCK, true, false>(v, lds, tw, 1);
+    stockham_pass<8, DIR, BLOCK, false, false>(v, lds, tw, 8);
+    if constexpr (NR8 == 3 && REM == 0) {
+        stockham_pass<8, DIR, BLOCK, false, true>(v, lds, tw, 64);
+    } else {
+        stockham_pass<8, DIR, BLOCK, false, false>(v, lds, tw, 64);
+        if constexpr (NR8 == 4 && REM == 0) {
+            stockham_pass<8, DIR, BLOCK, false, true>(v, lds, tw, 512);
+        } else if constexpr (NR8 == 3) {
+            stockham_pass<(1 << REM), DIR, BLOCK, false, true>(v, lds, tw, 512);
+        } else {  // NR8 == 4, REM == 1 (P = 8192)
+            stockham_pass<8, DIR, BLOCK, false, false>(v, lds, tw, 512);
+            stockham_pass<2, DIR, BLOCK, false, true>(v, lds, tw, 4096);
+        }
+    }
+}
+
+}  // namespace ht

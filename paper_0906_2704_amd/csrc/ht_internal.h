@@ -1,0 +1,88 @@
+// Internal definitions shared by the host plan code and the HIP kernels of libht.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ht.h"
+
+namespace ht {
+
+// Size of the global FFT twiddle table: tw[m] = exp(-2 pi i m / TWN).  Every FFT length
+// used here divides TWN, so every twiddle is one exact table entry.
+constexpr int TWN = 16384;
+constexpr int MAX_N = 8192;
+constexpr int MAX_LOGP = 13;  // largest LDS-resident FFT: 8192 complex doubles = 128 KiB
+constexpr int MIN_LOGP = 9;   // smallest FFT (one wave of 64 threads, 8 points each)
+
+enum OutMode { MODE_RE = 0, MODE_IM = 1, MODE_CPLX = 2 };
+
+// Tables of one core direction (analysis X or synthesis X^{-1}) computed as a chirp-z
+// transform: Y_k = post_k * sum_j b_{k-j} (pre_j x_j), evaluated by FFT convolution of
+// length M = S * P with the precomputed spectrum B = FFT_M(b) / M.
+struct Chirp {
+    const double2* pre;   // [N]
+    const double2* post;  // [N]
+    const double2* B;     // [M]
+    int mode;             // OutMode of the core output for a real result
+};
+
+// Everything a kernel needs about one 1D transform of length n (passed by value).
+struct Axis {
+    int n, N;             // signal length, core order n - 2
+    int kind;             // ht_kind
+    int logP;             // FFT size P = 2^logP handled by BLOCK = P / 8 threads
+    int S;                // split factor (1 or 2), M = S * P >= 2N - 1
+    int rank;             // DST2 / DST3: number of replaced core columns (degree - 1)
+    double q1;            // q_1 (p_1 for the antireflective family)
+    double minv[4];       // inverse of the 2x2 boundary system (C, F), row-major
+    double Gm[4];         // (E^T K)^{-1} of the DST correction, rank x rank, row-major
+    const double* q;      // [n] polynomial column q (or p)
+    const double* bub;    // [rank][N] bubble columns (DST2/3)
+    const double* U;      // [rank][N] K - E, K = Q * bubbles
+    Chirp ana, syn;
+    int den;              // eigenvalue grid: angles pi * r / den
+    const double* tcos;   // [2 den] cos(pi r / den)
+    const double* tsin;   // [2 den] sin(pi r / den)
+};
+
+// Strided view of a batch of 1D signals: signal b lives at
+//   base = (b / per_img) * img_stride + (b % per_img) * sig_stride,
+// element i at base + i * elem_stride (units: elements of the array's type).
+struct View {
+    void* ptr;
+    int64_t img_stride, sig_stride, elem_stride;
+    int64_t per_img;
+    int cplx;             // 1: interleaved complex128, 0: float64
+};
+
+}  // namespace ht
+
+struct ht_plan {
+    int ndim = 1;
+    int device = 0;
+    ht::Axis ax[2];
+    int cplx = 0;                      // any axis of kind F
+    int64_t max_batch = 1;
+    void* arena = nullptr;             // device tables of both axes
+    double2* work = nullptr;           // 2D: [max_batch][n0][n1] complex workspace
+    double* gcv_part = nullptr;        // 2D GCV partial sums
+    int64_t gcv_part_elems = 0;
+    const double2* tw = nullptr;       // global twiddle table of this device
+};
+
+namespace ht {
+
+// error reporting (thread-local message, see ht_last_error)
+ht_status fail(ht_status st, const std::string& msg);
+ht_status check_hip(hipError_t e, const char* what);
+const double2* device_twiddles(int device, ht_status* st);
+
+// launchers (ht_transform.hip)
+ht_status launch_core(const Axis& ax, const double2* tw, bool inverse, const View& in,
+                      const View& out, int64_t count, hipStream_t stream);
+
+}  // namespace ht

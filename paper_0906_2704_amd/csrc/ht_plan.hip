@@ -1,0 +1,482 @@
+// Plan creation: every table the kernels read, computed once on the host in long double
+// with exactly reduced angles and uploaded to the device.
+//
+//   q / p       the preserved-polynomial column: p_i = (1 - (i-1)/(n-1)) normalised to
+//               unit norm (eq. ART); q = q~/||q~||, q~_{i+1} = (b - x_i)^2 on the
+//               extended grid of eqs. ints/points (T_C) or intn/pointn (T_F)
+//   minv        inverse of the 2x2 capacitance system of Theorem th:inv in the form it
+//               takes once c_a, c_b are recognised as rows of the core (C: first/last rows
+//               of C^T; F: rows N and 1 of F^H):
+//                 C: [[q1-q2, -q_{n-1}], [-q_{n-1}, q1-q2]] [x1, xn] = [y1-y2, yn-y_{n-1}]
+//                 F: [[q1-q_{n-1}, -q2], [-q2, q1-q_{n-1}]] [x1, xn] = [y1-y_{n-1}, yn-y2]
+//   chirp       pre/post factors and filter spectra of the chirp-z form of each core
+//   DST family  bubbles, K = Q * bubbles and (E^T K)^{-1}
+//   trig        cos / sin (pi r / den) for the eigenvalue grid
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ht_internal.h"
+
+namespace ht {
+
+static thread_local std::string g_last_error;
+
+ht_status fail(ht_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+ht_status check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return HT_OK;
+    return fail(HT_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+using cd = std::complex<double>;
+using ld = long double;
+static const ld PI_L = 3.141592653589793238462643383279502884L;
+
+// exp(2 pi i r / period), r reduced exactly
+static cd cis_exact(int64_t r, int64_t period, ld scale = 1.0L) {
+    r %= period;
+    if (r < 0) r += period;
+    const ld a = 2.0L * PI_L * static_cast<ld>(r) / static_cast<ld>(period);
+    return cd(static_cast<double>(scale * cosl(a)), static_cast<double>(scale * sinl(a)));
+}
+
+// ---------------------------------------------------------------- global twiddles
+
+const double2* device_twiddles(int device, ht_status* st) {
+    static std::mutex mu;
+    static std::map<int, double2*> tables;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = tables.find(device);
+    if (it != tables.end()) {
+        *st = HT_OK;
+        return it->second;
+    }
+    std::vector<double2> h(TWN);
+    for (int m = 0; m < TWN; ++m) {
+        const cd w = cis_exact(-m, TWN);
+        h[m] = make_double2(w.real(), w.imag());
+    }
+    double2* dptr = nullptr;
+    if (hipMalloc(&dptr, sizeof(double2) * TWN) != hipSuccess) {
+        *st = fail(HT_ERR_OOM, "device twiddle table allocation failed");
+        return nullptr;
+    }
+    if (hipMemcpy(dptr, h.data(), sizeof(double2) * TWN, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(dptr);
+        *st = fail(HT_ERR_HIP, "device twiddle table upload failed");
+        return nullptr;
+    }
+    tables[device] = dptr;
+    *st = HT_OK;
+    return dptr;
+}
+
+// ------------------------------------------------------------------- host FFT (pow2)
+
+// In-place radix-2 FFT of length M (power of two), forward sign -1, float64 arithmetic
+// with long-double twiddles.
+static void host_fft(std::vector<cd>& x, int sign) {
+    const size_t M = x.size();
+    for (size_t i = 1, j = 0; i < M; ++i) {
+        size_t bit = M >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(x[i], x[j]);
+    }
+    std::vector<cd> w(M / 2);
+    for (size_t k = 0; k < M / 2; ++k) w[k] = cis_exact(sign * static_cast<int64_t>(k), static_cast<int64_t>(M));
+    for (size_t len = 2; len <= M; len <<= 1) {
+        const size_t step = M / len;
+        for (size_t i = 0; i < M; i += len) {
+            for (size_t k = 0; k < len / 2; ++k) {
+                const cd u = x[i + k];
+                const cd v = x[i + k + len / 2] * w[k * step];
+                x[i + k] = u + v;
+                x[i + k + len / 2] = u - v;
+            }
+        }
+    }
+}
+
+struct HostChirp {
+    std::vector<cd> pre, post, B;
+    int mode = MODE_RE;
+};
+
+// Chirp-z form of the core transforms (0-based j, k < N):
+//   sum_j x_j w^{jk} = c_k sum_j (c_j x_j) conj(c_{k-j}),  c_m = w^{m^2/2}.
+// DST-I  (sine core, both directions): w = e^{i pi/(N+1)}, Q_kj = sqrt(2/(N+1)) Im(...)
+//        with the index shift (j+1)(k+1) = jk + j + k + 1 folded into pre / post.
+// DCT-II (C analysis): X_k = w_k Re(e^{i pi k/(2N)} sum_j x_j e^{i pi jk/N}).
+// DCT-III (C synthesis): u_j = Re(sum_k (w_k e^{i pi k/(2N)} x_k) e^{i pi jk/N}).
+// DFT (F analysis, e^{-2 pi i jk/N}/sqrt N) and inverse DFT (F synthesis).
+static void make_chirp(int kind, bool synthesis, int N, int M, HostChirp& hc) {
+    hc.pre.assign(N, cd());
+    hc.post.assign(N, cd());
+    std::vector<cd> b(N);
+    int64_t Pang;
+    if (kind == HT_KIND_C) {
+        Pang = 4LL * N;
+        const ld w0 = sqrtl(1.0L / N), w1 = sqrtl(2.0L / N);
+        for (int64_t m = 0; m < N; ++m) {
+            const ld wk = m == 0 ? w0 : w1;
+            if (!synthesis) {
+                hc.pre[m] = cis_exact(m * m, Pang);
+                hc.post[m] = cis_exact(m * m + m, Pang, wk);
+            } else {
+                hc.pre[m] = cis_exact(m * m + m, Pang, wk);
+                hc.post[m] = cis_exact(m * m, Pang);
+            }
+            b[m] = cis_exact(-m * m, Pang);
+        }
+        hc.mode = MODE_RE;
+    } else if (kind == HT_KIND_F) {
+        Pang = 2LL * N;
+        const int sg = synthesis ? 1 : -1;
+        const ld sc = 1.0L / sqrtl(static_cast<ld>(N));
+        for (int64_t m = 0; m < N; ++m) {
+            hc.pre[m] = cis_exact(sg * m * m, Pang);
+            hc.post[m] = cis_exact(sg * m * m, Pang, sc);
+            b[m] = cis_exact(-sg * m * m, Pang);
+        }
+        hc.mode = synthesis ? MODE_RE : MODE_CPLX;
+    } else {  // sine core
+        Pang = 4LL * (N + 1);
+        const ld sc = sqrtl(2.0L / (N + 1));
+        for (int64_t m = 0; m < N; ++m) {
+            hc.pre[m] = cis_exact(m * m + 2 * m, Pang);
+            hc.post[m] = cis_exact(m * m + 2 * m + 2, Pang, sc);
+            b[m] = cis_exact(-m * m, Pang);
+        }
+        hc.mode = MODE_IM;
+    }
+    std::vector<cd> bc(M, cd());
+    for (int m = 0; m < N; ++m) bc[m] = b[m];
+    for (int m = 1; m < N; ++m) bc[M - m] = b[m];
+    host_fft(bc, -1);
+    const double inv = 1.0 / M;
+    for (auto& v : bc) v *= inv;
+    hc.B.swap(bc);
+}
+
+// Host replica of the chirp-z core (used at plan creation only, for K = Q * bubbles).
+static std::vector<double> host_core(const HostChirp& hc, const std::vector<double>& x, int M) {
+    const int N = static_cast<int>(x.size());
+    std::vector<cd> a(M, cd());
+    for (int j = 0; j < N; ++j) a[j] = x[j] * hc.pre[j];
+    host_fft(a, -1);
+    for (int k = 0; k < M; ++k) a[k] *= hc.B[k];
+    host_fft(a, 1);
+    std::vector<double> y(N);
+    for (int k = 0; k < N; ++k) {
+        const cd v = a[k] * hc.post[k];
+        y[k] = hc.mode == MODE_IM ? v.imag() : v.real();
+    }
+    return y;
+}
+
+// ----------------------------------------------------------------------- axis tables
+
+struct HostAxis {
+    Axis ax{};
+    std::vector<double> q, bub, U, tcos, tsin;
+    HostChirp ana, syn;
+    int M = 0;
+};
+
+static int resolve_kind(int degree, int sym, int family, ht_status* st) {
+    *st = HT_OK;
+    if (family == HT_FAMILY_PAPER) {
+        if (degree == 1) {
+            if (!sym) *st = fail(HT_ERR_UNSUPPORTED, "degree 1 (antireflective) needs a symmetric PSF");
+            return HT_KIND_AR;
+        }
+        if (degree == 2) return sym ? HT_KIND_C : HT_KIND_F;
+        *st = fail(HT_ERR_UNSUPPORTED, "HT_FAMILY_PAPER supports degrees 1 and 2");
+        return 0;
+    }
+    if (family == HT_FAMILY_DST) {
+        if (!sym) *st = fail(HT_ERR_UNSUPPORTED, "HT_FAMILY_DST needs a symmetric PSF");
+        if (degree == 1) return HT_KIND_AR;
+        if (degree == 2) return HT_KIND_DST2;
+        if (degree == 3) return HT_KIND_DST3;
+        *st = fail(HT_ERR_UNSUPPORTED, "HT_FAMILY_DST supports degrees 1..3");
+        return 0;
+    }
+    *st = fail(HT_ERR_INVALID_ARG, "unknown family");
+    return 0;
+}
+
+static ld to_ld(int64_t num, int64_t den) { return static_cast<ld>(num) / static_cast<ld>(den); }
+
+static ht_status build_axis(int n, int kind, HostAxis& h) {
+    const int N = n - 2;
+    Axis& a = h.ax;
+    a.n = n;
+    a.N = N;
+    a.kind = kind;
+    int M = 512;
+    while (M < 2 * N - 1) M <<= 1;
+    h.M = M;
+    a.S = M > 8192 ? 2 : 1;
+    const int P = M / a.S;
+    a.logP = 0;
+    while ((1 << a.logP) < P) ++a.logP;
+    if (a.logP < MIN_LOGP || a.logP > MAX_LOGP || (a.S == 2 && M != TWN))
+        return fail(HT_ERR_INVALID_ARG, "internal: unsupported FFT size");
+    a.rank = kind == HT_KIND_DST2 ? 1 : kind == HT_KIND_DST3 ? 2 : 0;
+
+    // polynomial column
+    std::vector<ld> qv(n);
+    if (kind == HT_KIND_C || kind == HT_KIND_F) {
+        // b - x_i on the extended grid, in units of pi: C: x_i = (2i-1)/(2N), b = (2N+1)/(2N);
+        // F: x_i = 2(i-1)/N, b = 2.  q~_{i+1} = (b - x_i)^2.
+        for (int i = 0; i < n; ++i) {
+            ld diff = kind == HT_KIND_C ? to_ld(2LL * N + 1 - (2LL * i - 1), 2LL * N)
+                                        : 2.0L - to_ld(2LL * (i - 1), N);
+            qv[i] = diff * diff;
+        }
+    } else {
+        for (int i = 0; i < n; ++i) qv[i] = 1.0L - to_ld(i, n - 1);  // 1 - (i-1)/(n-1), 1-based
+    }
+    ld nrm = 0.0L;
+    for (ld v : qv) nrm += v * v;
+    nrm = sqrtl(nrm);
+    h.q.resize(n);
+    for (int i = 0; i < n; ++i) h.q[i] = static_cast<double>(qv[i] / nrm);
+    a.q1 = h.q[0];
+
+    // 2x2 boundary system (closed form of the capacitance matrix)
+    a.minv[0] = a.minv[1] = a.minv[2] = a.minv[3] = 0.0;
+    if (kind == HT_KIND_C || kind == HT_KIND_F) {
+        const ld q1 = qv[0] / nrm, q2 = qv[1] / nrm, qm = qv[n - 2] / nrm;
+        const ld diag = kind == HT_KIND_C ? q1 - q2 : q1 - qm;
+        const ld off = kind == HT_KIND_C ? -qm : -q2;
+        const ld det = diag * diag - off * off;
+        if (fabsl(det) < 1e-300L) return fail(HT_ERR_SINGULAR, "boundary 2x2 system is singular");
+        a.minv[0] = static_cast<double>(diag / det);
+        a.minv[1] = static_cast<double>(-off / det);
+        a.minv[2] = static_cast<double>(-off / det);
+        a.minv[3] = static_cast<double>(diag / det);
+    }
+
+    // chirp tables
+    make_chirp(kind, false, N, M, h.ana);
+    make_chirp(kind, true, N, M, h.syn);
+
+    // DST family correction
+    a.Gm[0] = a.Gm[1] = a.Gm[2] = a.Gm[3] = 0.0;
+    if (a.rank > 0) {
+        h.bub.assign(static_cast<size_t>(a.rank) * N, 0.0);
+        h.U.assign(static_cast<size_t>(a.rank) * N, 0.0);
+        std::vector<std::vector<double>> K(a.rank);
+        for (int c = 0; c < a.rank; ++c) {
+            // x(pi - x) and (x - pi/2) x (pi - x) at x = i pi/(n-1), i = 1..N (units of pi)
+            std::vector<ld> v(N);
+            ld s2 = 0.0L;
+            for (int i = 1; i <= N; ++i) {
+                const ld x = to_ld(i, n - 1);
+                ld val = x * (1.0L - x);
+                if (c == 1) val *= (x - 0.5L);
+                v[i - 1] = val;
+                s2 += val * val;
+            }
+            const ld sn = sqrtl(s2);
+            std::vector<double> bv(N);
+            for (int i = 0; i < N; ++i) bv[i] = static_cast<double>(v[i] / sn);
+            std::memcpy(&h.bub[static_cast<size_t>(c) * N], bv.data(), sizeof(double) * N);
+            K[c] = host_core(h.ana, bv, M);
+            for (int i = 0; i < N; ++i) h.U[static_cast<size_t>(c) * N + i] = K[c][i] - (i == c ? 1.0 : 0.0);
+        }
+        if (a.rank == 1) {
+            if (std::fabs(K[0][0]) < 1e-300) return fail(HT_ERR_SINGULAR, "DST correction is singular");
+            a.Gm[0] = 1.0 / K[0][0];
+        } else {
+            // E^T K = [[K0[0], K1[0]], [K0[1], K1[1]]]
+            const double e00 = K[0][0], e01 = K[1][0], e10 = K[0][1], e11 = K[1][1];
+            const double det = e00 * e11 - e01 * e10;
+            if (std::fabs(det) < 1e-300) return fail(HT_ERR_SINGULAR, "DST correction is singular");
+            a.Gm[0] = e11 / det;
+            a.Gm[1] = -e01 / det;
+            a.Gm[2] = -e10 / det;
+            a.Gm[3] = e00 / det;
+        }
+    }
+
+    // eigenvalue grid trig tables
+    a.den = (kind == HT_KIND_C || kind == HT_KIND_F) ? N : n - 1;
+    h.tcos.resize(2 * a.den);
+    h.tsin.resize(2 * a.den);
+    for (int r = 0; r < 2 * a.den; ++r) {
+        const cd w = cis_exact(r, 2LL * a.den);  // exp(i pi r / den)
+        h.tcos[r] = w.real();
+        h.tsin[r] = w.imag();
+    }
+    return HT_OK;
+}
+
+// Upload the host tables of both axes into one device arena and fix up the pointers.
+static ht_status upload(ht_plan* p, HostAxis* hs, int nax) {
+    size_t bytes = 0;
+    auto reserve = [&](size_t nbytes) {
+        const size_t off = bytes;
+        bytes += (nbytes + 255) & ~static_cast<size_t>(255);
+        return off;
+    };
+    struct Offs { size_t q, bub, U, tcos, tsin, apre, apost, aB, spre, spost, sB; } o[2];
+    for (int a = 0; a < nax; ++a) {
+        const HostAxis& h = hs[a];
+        const size_t N = h.ax.N;
+        o[a].q = reserve(sizeof(double) * h.q.size());
+        o[a].bub = reserve(sizeof(double) * (h.bub.size() + 1));
+        o[a].U = reserve(sizeof(double) * (h.U.size() + 1));
+        o[a].tcos = reserve(sizeof(double) * h.tcos.size());
+        o[a].tsin = reserve(sizeof(double) * h.tsin.size());
+        o[a].apre = reserve(sizeof(double2) * N);
+        o[a].apost = reserve(sizeof(double2) * N);
+        o[a].aB = reserve(sizeof(double2) * h.M);
+        o[a].spre = reserve(sizeof(double2) * N);
+        o[a].spost = reserve(sizeof(double2) * N);
+        o[a].sB = reserve(sizeof(double2) * h.M);
+    }
+    std::vector<char> host(bytes, 0);
+    auto put = [&](size_t off, const void* src, size_t nb) {
+        if (nb) std::memcpy(host.data() + off, src, nb);
+    };
+    auto putc = [&](size_t off, const std::vector<cd>& v) {
+        std::vector<double2> t(v.size());
+        for (size_t i = 0; i < v.size(); ++i) t[i] = make_double2(v[i].real(), v[i].imag());
+        put(off, t.data(), sizeof(double2) * t.size());
+    };
+    for (int a = 0; a < nax; ++a) {
+        const HostAxis& h = hs[a];
+        put(o[a].q, h.q.data(), sizeof(double) * h.q.size());
+        put(o[a].bub, h.bub.data(), sizeof(double) * h.bub.size());
+        put(o[a].U, h.U.data(), sizeof(double) * h.U.size());
+        put(o[a].tcos, h.tcos.data(), sizeof(double) * h.tcos.size());
+        put(o[a].tsin, h.tsin.data(), sizeof(double) * h.tsin.size());
+        putc(o[a].apre, h.ana.pre);
+        putc(o[a].apost, h.ana.post);
+        putc(o[a].aB, h.ana.B);
+        putc(o[a].spre, h.syn.pre);
+        putc(o[a].spost, h.syn.post);
+        putc(o[a].sB, h.syn.B);
+    }
+    char* dev = nullptr;
+    if (hipMalloc(&dev, bytes) != hipSuccess) return fail(HT_ERR_OOM, "plan table allocation failed");
+    if (hipMemcpy(dev, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(dev);
+        return fail(HT_ERR_HIP, "plan table upload failed");
+    }
+    p->arena = dev;
+    for (int a = 0; a < nax; ++a) {
+        Axis ax = hs[a].ax;
+        ax.q = reinterpret_cast<const double*>(dev + o[a].q);
+        ax.bub = reinterpret_cast<const double*>(dev + o[a].bub);
+        ax.U = reinterpret_cast<const double*>(dev + o[a].U);
+        ax.tcos = reinterpret_cast<const double*>(dev + o[a].tcos);
+        ax.tsin = reinterpret_cast<const double*>(dev + o[a].tsin);
+        ax.ana = Chirp{reinterpret_cast<const double2*>(dev + o[a].apre), reinterpret_cast<const double2*>(dev + o[a].apost),
+                       reinterpret_cast<const double2*>(dev + o[a].aB), hs[a].ana.mode};
+        ax.syn = Chirp{reinterpret_cast<const double2*>(dev + o[a].spre), reinterpret_cast<const double2*>(dev + o[a].spost),
+                       reinterpret_cast<const double2*>(dev + o[a].sB), hs[a].syn.mode};
+        p->ax[a] = ax;
+    }
+    return HT_OK;
+}
+
+}  // namespace ht
+
+using namespace ht;
+
+extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int psf_symmetric, int family,
+                                    int64_t max_batch, ht_plan** out) {
+    if (!out || !n) return fail(HT_ERR_INVALID_ARG, "ht_plan_create: null argument");
+    *out = nullptr;
+    if (ndim != 1 && ndim != 2) return fail(HT_ERR_INVALID_ARG, "ht_plan_create: ndim must be 1 or 2");
+    for (int a = 0; a < ndim; ++a)
+        if (n[a] < 5 || n[a] > MAX_N) return fail(HT_ERR_INVALID_ARG, "ht_plan_create: n must be in [5, 8192]");
+    if (ndim == 2 && (max_batch < 1 || max_batch > 4096))
+        return fail(HT_ERR_INVALID_ARG, "ht_plan_create: max_batch must be in [1, 4096] for 2D plans");
+    ht_status st;
+    const int kind = resolve_kind(degree, psf_symmetric, family, &st);
+    if (st != HT_OK) return st;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return fail(HT_ERR_HIP, "ht_plan_create: no HIP device");
+    const double2* tw = device_twiddles(device, &st);
+    if (!tw) return st;
+    HostAxis hs[2];
+    for (int a = 0; a < ndim; ++a) {
+        st = build_axis(static_cast<int>(n[a]), kind, hs[a]);
+        if (st != HT_OK) return st;
+    }
+    ht_plan* p = new (std::nothrow) ht_plan();
+    if (!p) return fail(HT_ERR_OOM, "ht_plan_create: host allocation failed");
+    p->ndim = ndim;
+    p->device = device;
+    p->tw = tw;
+    p->cplx = kind == HT_KIND_F ? 1 : 0;
+    p->max_batch = ndim == 2 ? max_batch : 1;
+    st = upload(p, hs, ndim);
+    if (st != HT_OK) {
+        delete p;
+        return st;
+    }
+    if (ndim == 2) {
+        const int64_t img = n[0] * n[1];
+        if (hipMalloc(&p->work, sizeof(double2) * img * max_batch) != hipSuccess) {
+            ht_plan_destroy(p);
+            return fail(HT_ERR_OOM, "ht_plan_create: 2D workspace allocation failed");
+        }
+        p->gcv_part_elems = 2LL * 512 * 1024 * max_batch;
+        if (hipMalloc(&p->gcv_part, sizeof(double) * p->gcv_part_elems) != hipSuccess) {
+            ht_plan_destroy(p);
+            return fail(HT_ERR_OOM, "ht_plan_create: GCV workspace allocation failed");
+        }
+    }
+    *out = p;
+    return HT_OK;
+}
+
+extern "C" ht_status ht_plan_destroy(ht_plan* p) {
+    if (!p) return HT_OK;
+    if (p->arena) hipFree(p->arena);
+    if (p->work) hipFree(p->work);
+    if (p->gcv_part) hipFree(p->gcv_part);
+    delete p;
+    return HT_OK;
+}
+
+extern "C" int ht_plan_kind(const ht_plan* p, int axis) {
+    if (!p || axis < 0 || axis >= p->ndim) return -1;
+    return p->ax[axis].kind;
+}
+
+extern "C" int ht_plan_is_complex(const ht_plan* p) { return p ? p->cplx : 0; }
+
+extern "C" const char* ht_status_str(ht_status s) {
+    switch (s) {
+        case HT_OK: return "HT_OK";
+        case HT_ERR_INVALID_ARG: return "HT_ERR_INVALID_ARG";
+        case HT_ERR_UNSUPPORTED: return "HT_ERR_UNSUPPORTED";
+        case HT_ERR_PSF_TOO_WIDE: return "HT_ERR_PSF_TOO_WIDE";
+        case HT_ERR_SINGULAR: return "HT_ERR_SINGULAR";
+        case HT_ERR_NONFINITE: return "HT_ERR_NONFINITE";
+        case HT_ERR_HIP: return "HT_ERR_HIP";
+        case HT_ERR_OOM: return "HT_ERR_OOM";
+    }
+    return "HT_ERR_UNKNOWN";
+}
+
+extern "C" const char* ht_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,402 @@
+// Spectra (eqs. jcf, Ac, Af and the smoothing spectra of Section 4), the reblurred
+// Tikhonov filter (eq. freg) and the GCV scan (eqs. gcv2, mugcv).
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+#include "ht_internal.h"
+
+namespace ht {
+
+// ------------------------------------------------------------------------ eigenvalues
+
+// Eigenvalue of column i of the plan's transform: the preserved-polynomial columns carry
+// z(0) = sum_j h_j; core column i carries z at frequency pi * num / den with
+//   AR / DST:  num = i        (y = j pi / (n-1), core index j = i)          eq. jcf
+//   C:         num = i - 1    (x = (i-1) pi / (n-2))                         eq. Ac
+//   F:         num = -2(i-1)  (conj z(2 pi (i-1) / (n-2)) for the convolution model)
+// evaluated by direct summation over the taps with every angle reduced exactly.
+__global__ void k_eigs(Axis ax, const double* __restrict__ psf, int64_t plen, int64_t pcenter,
+                       int64_t psf_stride, int norm, double s_ident, void* d, double* s,
+                       int64_t out_stride, int cplx_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = blockIdx.y;
+    if (i >= ax.n) return;
+    const double* h = psf + b * psf_stride;
+    const int n = ax.n;
+    const bool poly = (i == 0) || (i == n - 1) || (i >= 1 && i <= ax.rank);
+    int64_t num;
+    if (ax.kind == HT_KIND_C)
+        num = i - 1;
+    else if (ax.kind == HT_KIND_F)
+        num = -2 * static_cast<int64_t>(i - 1);
+    else
+        num = i;
+    const int64_t period = 2 * static_cast<int64_t>(ax.den);
+    double dr = 0.0, di = 0.0, sv;
+    if (poly) {
+        for (int64_t k = 0; k < plen; ++k) dr += h[k];
+        sv = norm == HT_NORM_IDENTITY ? s_ident : 0.0;
+    } else {
+        for (int64_t k = 0; k < plen; ++k) {
+            int64_t r = ((k - pcenter) * num) % period;
+            if (r < 0) r += period;
+            dr = fma(h[k], ax.tcos[r], dr);
+            di = fma(h[k], ax.tsin[r], di);
+        }
+        int64_t r = num % period;
+        if (r < 0) r += period;
+        sv = norm == HT_NORM_IDENTITY ? s_ident : 2.0 - 2.0 * ax.tcos[r];
+    }
+    const int64_t o = b * out_stride + i;
+    if (cplx_out)
+        static_cast<double2*>(d)[o] = make_double2(dr, di);
+    else
+        static_cast<double*>(d)[o] = dr;
+    s[o] = sv;
+}
+
+// ------------------------------------------------------------------- shared accessors
+
+struct Spec {          // how to find d_i and s_i of element e of item b
+    const void* d;
+    const double* s;
+    int ndim;
+    int n0, n1;        // 2D factor lengths (n0 = n for 1D)
+    int64_t eig_stride;  // 1D: 0 (shared) or n (per item)
+    int64_t per_item;    // elements per item (n or n0 * n1)
+    int cplx;
+};
+
+__device__ __forceinline__ void spec_at(const Spec& sp, int64_t b, int64_t e, double2& dd, double& ss) {
+    if (sp.ndim == 1) {
+        const int64_t o = b * sp.eig_stride + e;
+        dd = sp.cplx ? static_cast<const double2*>(sp.d)[o]
+                     : make_double2(static_cast<const double*>(sp.d)[o], 0.0);
+        ss = sp.s[o];
+    } else {
+        const int64_t i0 = e / sp.n1, i1 = e - i0 * sp.n1;
+        double2 a, c;
+        if (sp.cplx) {
+            a = static_cast<const double2*>(sp.d)[i0];
+            c = static_cast<const double2*>(sp.d)[sp.n0 + i1];
+        } else {
+            a = make_double2(static_cast<const double*>(sp.d)[i0], 0.0);
+            c = make_double2(static_cast<const double*>(sp.d)[sp.n0 + i1], 0.0);
+        }
+        dd = cmul(a, c);
+        ss = sp.s[i0] + sp.s[sp.n0 + i1];
+    }
+}
+
+__device__ __forceinline__ double2 cload(const void* p, int64_t o, int cplx) {
+    return cplx ? static_cast<const double2*>(p)[o] : make_double2(static_cast<const double*>(p)[o], 0.0);
+}
+
+// --------------------------------------------------------------------------- filter
+
+// fhat = conj(d) g / (|d|^2 + mu |s|^2): Phi D^{-1} of eq. freg without the 0/0 of a
+// vanishing eigenvalue.
+__global__ void k_filter(Spec sp, const void* __restrict__ coeff, const double* __restrict__ mu,
+                         void* fhat, int64_t per_item, int64_t total) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int64_t b = idx / per_item, e = idx - b * per_item;
+    double2 dd;
+    double ss;
+    spec_at(sp, b, e, dd, ss);
+    const double2 g = cload(coeff, idx, sp.cplx);
+    const double den = fma(dd.x, dd.x, dd.y * dd.y) + mu[b] * (ss * ss);
+    const double2 num = cmulc(g, dd);
+    if (sp.cplx)
+        static_cast<double2*>(fhat)[idx] = make_double2(num.x / den, num.y / den);
+    else
+        static_cast<double*>(fhat)[idx] = num.x / den;
+}
+
+// ----------------------------------------------------------------------------- GCV
+
+constexpr int GCV_THREADS = 256;
+constexpr int GCV_CHUNK = 2048;  // elements staged in LDS at a time
+
+// 1/u to full float64 accuracy: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rcp_nr(double u) {
+    double r = __builtin_amdgcn_rcp(u);
+    double e = fma(-u, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-u, r, 1.0);
+    return fma(r, e, r);
+}
+
+// With sigma_i = |s_i|^2 / (|d_i|^2 + mu |s_i|^2) = 1 / (t_i + mu), t_i = |d_i|^2/|s_i|^2,
+// the two sums of eq. mugcv are D(mu) = sum_i 1/(t_i + mu), N(mu) = sum_i w_i/(t_i + mu)^2
+// with w_i = |ghat_i|^2.  Entries with s_i = 0 have sigma_i = 0; they are staged with
+// w = 0 and t = 1e300 so that their contribution to both sums rounds away exactly.
+// Thread (part, kl) accumulates mu_{k0 + kl} over the elements part, part + nparts, ...
+// of each staged chunk; chunk totals are added in order, parts are added in order: the
+// result does not depend on scheduling.
+__device__ void gcv_accumulate(const Spec& sp, const void* coeff, int64_t b, int64_t e_begin,
+                               int64_t e_end, const double* mus, int K, double2* part_out,
+                               double2* stage, double2* red) {
+    const int tid = threadIdx.x;
+    const int Kb = K < GCV_THREADS ? K : GCV_THREADS;
+    const int nparts = GCV_THREADS / Kb;
+    const int part = tid / Kb, kl = tid - part * Kb;
+    for (int k0 = 0; k0 < K; k0 += Kb) {
+        const int k = k0 + kl;
+        const bool active = part < nparts && k < K;
+        const double mu = active ? mus[k] : 1.0;
+        double Nt = 0.0, Dt = 0.0;
+        for (int64_t c0 = e_begin; c0 < e_end; c0 += GCV_CHUNK) {
+            const int len = static_cast<int>((e_end - c0) < GCV_CHUNK ? (e_end - c0) : GCV_CHUNK);
+            __syncthreads();
+            for (int i = tid; i < len; i += GCV_THREADS) {
+                const int64_t e = c0 + i;
+                double2 dd;
+                double ss;
+                spec_at(sp, b, e, dd, ss);
+                const double2 g = cload(coeff, b * sp.per_item + e, sp.cplx);
+                const double s2 = ss * ss;
+                double t = 1e300, w = 0.0;
+                if (s2 != 0.0) {
+                    t = fma(dd.x, dd.x, dd.y * dd.y) / s2;
+                    w = fma(g.x, g.x, g.y * g.y);
+                }
+                stage[i] = make_double2(t, w);
+            }
+            __syncthreads();
+            if (active) {
+                double Nc = 0.0, Dc = 0.0;
+                for (int i = part; i < len; i += nparts) {
+                    const double2 tw = stage[i];
+                    const double r = rcp_nr(tw.x + mu);
+                    Dc += r;
+                    Nc = fma(tw.y, r * r, Nc);
+                }
+                Nt += Nc;
+                Dt += Dc;
+            }
+        }
+        __syncthreads();
+        if (part < nparts) red[part * Kb + kl] = make_double2(Nt, Dt);
+        __syncthreads();
+        if (part == 0 && k < K) {
+            double2 acc = red[kl];
+            for (int p = 1; p < nparts; ++p) {
+                const double2 v = red[p * Kb + kl];
+                acc.x += v.x;
+                acc.y += v.y;
+            }
+            part_out[k] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+
+// argmin over G[0..K) in LDS by the first wave: first index of the minimum; -1 if any
+// value is not finite.
+__device__ void gcv_argmin(const double* G, int K, int* kbest_out) {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        double best = 0.0;
+        int bk = -1;
+        int bad = 0;
+        for (int k = tid; k < K; k += 64) {
+            const double g = G[k];
+            if (!isfinite(g)) bad = 1;
+            if (bk < 0 || g < best) {
+                best = g;
+                bk = k;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int ok = __shfl_xor(bk, off, 64);
+            const int obad = __shfl_xor(bad, off, 64);
+            bad |= obad;
+            if (ok >= 0 && (bk < 0 || ob < best || (ob == best && ok < bk))) {
+                best = ob;
+                bk = ok;
+            }
+        }
+        if (tid == 0) *kbest_out = bad ? -1 : bk;
+    }
+    __syncthreads();
+}
+
+__device__ void gcv_finish(const double2* sums, int K, const double* mus, double* G_out,
+                           int32_t* kbest_out, double* mubest_out, double* Gs, int* kshared) {
+    for (int k = threadIdx.x; k < K; k += GCV_THREADS) {
+        const double2 v = sums[k];
+        const double g = v.x / (v.y * v.y);
+        Gs[k] = g;
+        if (G_out) G_out[k] = g;
+    }
+    __syncthreads();
+    gcv_argmin(Gs, K, kshared);
+    if (threadIdx.x == 0) {
+        const int kb = *kshared;
+        *kbest_out = kb;
+        if (mubest_out) mubest_out[0] = kb >= 0 ? mus[kb] : __builtin_nan("");
+    }
+}
+
+struct GcvOut {
+    const double* mus;
+    int64_t mu_stride;  // 0: one grid for all items, K: one grid per item
+    int K;
+    double* G;
+    int32_t* kbest;
+    double* mubest;
+};
+
+__global__ __launch_bounds__(GCV_THREADS) void k_gcv_single(Spec sp, const void* __restrict__ coeff, GcvOut o) {
+    __shared__ double2 stage[GCV_CHUNK];
+    __shared__ double2 red[GCV_THREADS];
+    __shared__ double2 sums[1024];
+    __shared__ double Gs[1024];
+    __shared__ int kshared;
+    const int64_t b = blockIdx.x;
+    const double* mus = o.mus + b * o.mu_stride;
+    gcv_accumulate(sp, coeff, b, 0, sp.per_item, mus, o.K, sums, stage, red);
+    gcv_finish(sums, o.K, mus, o.G ? o.G + b * o.K : nullptr, o.kbest + b,
+               o.mubest ? o.mubest + b : nullptr, Gs, &kshared);
+}
+
+__global__ __launch_bounds__(GCV_THREADS) void k_gcv_partial(Spec sp, const void* __restrict__ coeff, GcvOut o,
+                                                             int64_t span, double2* part) {
+    __shared__ double2 stage[GCV_CHUNK];
+    __shared__ double2 red[GCV_THREADS];
+    const int64_t w = blockIdx.x, b = blockIdx.y;
+    const int64_t e0 = w * span;
+    int64_t e1 = e0 + span;
+    if (e1 > sp.per_item) e1 = sp.per_item;
+    const double* mus = o.mus + b * o.mu_stride;
+    gcv_accumulate(sp, coeff, b, e0, e1, mus, o.K, part + (b * gridDim.x + w) * o.K, stage, red);
+}
+
+__global__ __launch_bounds__(GCV_THREADS) void k_gcv_finalize(GcvOut o, int64_t nparts, const double2* __restrict__ part) {
+    __shared__ double2 sums[1024];
+    __shared__ double Gs[1024];
+    __shared__ int kshared;
+    const int64_t b = blockIdx.x;
+    for (int k = threadIdx.x; k < o.K; k += GCV_THREADS) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int64_t w = 0; w < nparts; ++w) {
+            const double2 v = part[(b * nparts + w) * o.K + k];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        sums[k] = acc;
+    }
+    __syncthreads();
+    const double* mus = o.mus + b * o.mu_stride;
+    gcv_finish(sums, o.K, mus, o.G ? o.G + b * o.K : nullptr, o.kbest + b,
+               o.mubest ? o.mubest + b : nullptr, Gs, &kshared);
+}
+
+static Spec make_spec(const ht_plan* plan, const void* d, const double* s, int64_t eig_batch) {
+    Spec sp;
+    sp.d = d;
+    sp.s = s;
+    sp.ndim = plan->ndim;
+    sp.n0 = plan->ax[0].n;
+    sp.n1 = plan->ndim == 2 ? plan->ax[1].n : 1;
+    sp.per_item = plan->ndim == 2 ? static_cast<int64_t>(sp.n0) * sp.n1 : sp.n0;
+    sp.eig_stride = (plan->ndim == 1 && eig_batch > 1) ? sp.n0 : 0;
+    sp.cplx = plan->cplx;
+    return sp;
+}
+
+}  // namespace ht
+
+using namespace ht;
+
+extern "C" ht_status ht_eigs(const ht_plan* plan, const double* psf, const int64_t* psf_len,
+                             const int64_t* psf_center, int norm, void* d, double* s,
+                             int64_t batch, hipStream_t stream) {
+    if (!plan || !psf_len || !psf_center) return fail(HT_ERR_INVALID_ARG, "ht_eigs: null argument");
+    if (batch != 0 && (!psf || !d || !s)) return fail(HT_ERR_INVALID_ARG, "ht_eigs: null argument");
+    if (norm != HT_NORM_IDENTITY && norm != HT_NORM_SECOND_DIFF)
+        return fail(HT_ERR_INVALID_ARG, "ht_eigs: bad norm");
+    if (batch < 0 || batch > 65535) return fail(HT_ERR_INVALID_ARG, "ht_eigs: batch out of range [0, 65535]");
+    if (plan->ndim == 2 && batch != 1) return fail(HT_ERR_INVALID_ARG, "ht_eigs: 2D plans take one separable PSF (batch = 1)");
+    if (batch == 0) return HT_OK;
+    for (int a = 0; a < plan->ndim; ++a) {
+        const int64_t len = psf_len[a], c = psf_center[a];
+        if (len < 1 || c < 0 || c >= len) return fail(HT_ERR_INVALID_ARG, "ht_eigs: bad PSF length or center");
+        const int64_t m = c > len - 1 - c ? c : len - 1 - c;
+        if (2 * m + 1 > plan->ax[a].n - 2) return fail(HT_ERR_PSF_TOO_WIDE, "ht_eigs: PSF half-width m needs 2m+1 <= n-2");
+    }
+    int64_t off_d = 0, off_psf = 0;
+    for (int a = 0; a < plan->ndim; ++a) {
+        const Axis& ax = plan->ax[a];
+        const double s_ident = (plan->ndim == 2 && a == 1) ? 0.0 : 1.0;
+        const int cp = ax.kind == HT_KIND_F ? 1 : 0;
+        // 2D with one complex axis stores both factors as complex
+        const int cp_out = plan->cplx;
+        void* dd = cp_out ? static_cast<void*>(static_cast<double2*>(d) + off_d)
+                          : static_cast<void*>(static_cast<double*>(d) + off_d);
+        (void)cp;
+        dim3 grid((ax.n + 255) / 256, static_cast<unsigned>(batch));
+        hipLaunchKernelGGL(k_eigs, grid, dim3(256), 0, stream, ax, psf + off_psf, psf_len[a], psf_center[a],
+                           psf_len[a], norm, s_ident, dd, s + off_d, static_cast<int64_t>(ax.n), cp_out);
+        ht_status st = check_hip(hipGetLastError(), "ht_eigs launch");
+        if (st != HT_OK) return st;
+        off_d += ax.n;
+        off_psf += psf_len[a];
+    }
+    return HT_OK;
+}
+
+extern "C" ht_status ht_tikhonov_filter(const ht_plan* plan, const void* coeff, const void* d,
+                                        const double* s, int64_t eig_batch, const double* mu,
+                                        void* fhat, int64_t batch, hipStream_t stream) {
+    if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: null plan");
+    if (batch < 0) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: negative batch");
+    if (batch == 0) return HT_OK;
+    if (!coeff || !d || !s || !mu || !fhat) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: null argument");
+    if (!(eig_batch == 1 || eig_batch == batch)) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: eig_batch must be 1 or batch");
+    if (plan->ndim == 2 && eig_batch != 1) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: 2D spectra are shared (eig_batch = 1)");
+    if (batch == 0) return HT_OK;
+    const Spec sp = make_spec(plan, d, s, eig_batch);
+    const int64_t total = batch * sp.per_item;
+    const int64_t blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: batch too large");
+    hipLaunchKernelGGL(k_filter, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, sp, coeff, mu, fhat,
+                       sp.per_item, total);
+    return check_hip(hipGetLastError(), "ht_tikhonov_filter launch");
+}
+
+extern "C" ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const void* d, const double* s,
+                                 int64_t eig_batch, const double* mu_grid, int32_t K, int grid_per_item,
+                                 double* G, int32_t* k_best, double* mu_best, int64_t batch,
+                                 hipStream_t stream) {
+    if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: null plan");
+    if (K < 1 || K > 1024) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: K must be in [1, 1024]");
+    if (batch < 0 || batch > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: batch out of range");
+    if (batch == 0) return HT_OK;
+    if (!coeff || !d || !s || !mu_grid || !k_best) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: null argument");
+    if (!(eig_batch == 1 || eig_batch == batch)) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: eig_batch must be 1 or batch");
+    if (plan->ndim == 2 && eig_batch != 1) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: 2D spectra are shared (eig_batch = 1)");
+    if (batch == 0) return HT_OK;
+    const Spec sp = make_spec(plan, d, s, eig_batch);
+    GcvOut o{mu_grid, grid_per_item ? static_cast<int64_t>(K) : 0, K, G, k_best, mu_best};
+    if (plan->ndim == 1) {
+        hipLaunchKernelGGL(k_gcv_single, dim3(static_cast<unsigned>(batch)), dim3(GCV_THREADS), 0, stream, sp, coeff, o);
+        return check_hip(hipGetLastError(), "ht_gcv_scan launch");
+    }
+    if (batch > plan->max_batch) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: batch exceeds the plan's max_batch");
+    int64_t nw = (sp.per_item + GCV_CHUNK - 1) / GCV_CHUNK;
+    if (nw > 512) nw = 512;
+    const int64_t span = (sp.per_item + nw - 1) / nw;
+    nw = (sp.per_item + span - 1) / span;
+    if (nw * K * batch * 2 > plan->gcv_part_elems) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: workspace too small");
+    double2* part = reinterpret_cast<double2*>(plan->gcv_part);
+    hipLaunchKernelGGL(k_gcv_partial, dim3(static_cast<unsigned>(nw), static_cast<unsigned>(batch)), dim3(GCV_THREADS), 0,
+                       stream, sp, coeff, o, span, part);
+    ht_status st = check_hip(hipGetLastError(), "ht_gcv_scan partial launch");
+    if (st != HT_OK) return st;
+    hipLaunchKernelGGL(k_gcv_finalize, dim3(static_cast<unsigned>(batch)), dim3(GCV_THREADS), 0, stream, o, nw, part);
+    return check_hip(hipGetLastError(), "ht_gcv_scan finalize launch");
+}

@@ -1,0 +1,305 @@
+// Forward and inverse high-order boundary transforms (eqs. ART, Tc, Tf; Theorem th:inv).
+//
+// One workgroup handles one 1D transform of length n.  The core (DST-I, DCT-II/III or
+// DFT of order N = n - 2) is computed as a chirp-z transform by FFT convolution in LDS
+// (any N, no restriction to smooth lengths); the boundary work is float64 closed form:
+//
+//   inverse  (T_X x = y)   [x_1, x_n] from the 2x2 boundary system (C, F; for the
+//            antireflective family the boundary rows decouple: x_1 = y_1/p_1,
+//            x_n = y_n/p_1), then x_mid = X (y_mid - q^ x_1 - J q^ x_n), and for the DST
+//            family x_mid -= U (E^T K)^{-1} E^T x_mid.
+//   forward  (y = T_X x)   u = X^{-1} x_mid, y_mid = u + q^ x_1 + J q^ x_n (+ bubbles),
+//            y_1 / y_n from the extension of the core columns to the ghost grid points
+//            (zero for the sine core, mirror for the cosine core, periodic wrap for the
+//            exponential core) plus q_1 x_1 / q_1 x_n.
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+#include "ht_internal.h"
+
+namespace ht {
+
+__device__ __forceinline__ double2 vload(const View& v, int64_t base, int64_t i) {
+    const int64_t off = base + i * v.elem_stride;
+    if (v.cplx) return static_cast<const double2*>(v.ptr)[off];
+    return make_double2(static_cast<const double*>(v.ptr)[off], 0.0);
+}
+
+__device__ __forceinline__ void vstore(const View& v, int64_t base, int64_t i, double2 x) {
+    const int64_t off = base + i * v.elem_stride;
+    if (v.cplx)
+        static_cast<double2*>(v.ptr)[off] = x;
+    else
+        static_cast<double*>(v.ptr)[off] = x.x;
+}
+
+__device__ __forceinline__ int64_t vbase(const View& v, int64_t b) {
+    return (b / v.per_img) * v.img_stride + (b % v.per_img) * v.sig_stride;
+}
+
+__device__ __forceinline__ double2 select_out(double2 y, int mode) {
+    if (mode == MODE_RE) return make_double2(y.x, 0.0);
+    if (mode == MODE_IM) return make_double2(y.y, 0.0);
+    return y;
+}
+
+// Chirp-z core on the thread's slots: on entry `a` holds pre_j * x_j for the slot
+// indices j < N (0 elsewhere) of split s = 0; `reload` recomputes it for split s = 1.
+// On exit acc holds the convolution (before post-multiplication).
+template <int LOGP, typename Reload>
+__device__ __forceinline__ void chirp_conv(double2 (&acc)[8], const Chirp& ch, int S,
+                                           double2* lds, const double2* __restrict__ tw,
+                                           Reload reload) {
+    constexpr int P = 1 << LOGP;
+    constexpr int BLOCK = P / 8;
+    const int tid = threadIdx.x;
+    for (int s = 0; s < S; ++s) {
+        double2 v[8];
+        reload(v);
+        if (s == 1) {  // M = 2P = TWN: fold exp(-2 pi i j / M) into the input
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = cmul(v[k], tw[tid + k * BLOCK]);
+        }
+        fft_slots<LOGP, -1>(v, lds, tw);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = cmul(v[k], ch.B[S * (tid + k * BLOCK) + s]);
+        fft_slots<LOGP, 1>(v, lds, tw);
+        if (s == 0) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] = v[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] = cadd(acc[k], cmulc(v[k], tw[tid + k * BLOCK]));
+        }
+    }
+}
+
+template <int LOGP>
+__global__ __launch_bounds__((1 << LOGP) / 8) void k_inverse(Axis ax, View in, View out,
+                                                             const double2* __restrict__ tw) {
+    constexpr int P = 1 << LOGP;
+    constexpr int BLOCK = P / 8;
+    __shared__ double2 lds[P];
+    __shared__ double2 corr[2];
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int n = ax.n, N = ax.N;
+    const int64_t ib = vbase(in, b), ob = vbase(out, b);
+
+    // boundary coefficients (float64 closed form)
+    const double2 y0 = vload(in, ib, 0), y1 = vload(in, ib, 1);
+    const double2 yN = vload(in, ib, n - 2), yL = vload(in, ib, n - 1);
+    double2 x1, xn;
+    if (ax.kind == HT_KIND_C || ax.kind == HT_KIND_F) {
+        const double2 r1 = ax.kind == HT_KIND_C ? csub(y0, y1) : csub(y0, yN);
+        const double2 r2 = ax.kind == HT_KIND_C ? csub(yL, yN) : csub(yL, y1);
+        x1 = make_double2(ax.minv[0] * r1.x + ax.minv[1] * r2.x, ax.minv[0] * r1.y + ax.minv[1] * r2.y);
+        xn = make_double2(ax.minv[2] * r1.x + ax.minv[3] * r2.x, ax.minv[2] * r1.y + ax.minv[3] * r2.y);
+    } else {
+        const double inv = 1.0 / ax.q1;
+        x1 = cscale(y0, inv);
+        xn = cscale(yL, inv);
+    }
+    const Chirp& ch = ax.ana;
+    auto reload = [&](double2 (&v)[8]) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int j = tid + k * BLOCK;
+            if (j < N) {
+                double2 r = vload(in, ib, j + 1);
+                const double qa = ax.q[j + 1], qb = ax.q[N - j];
+                r.x = r.x - qa * x1.x - qb * xn.x;
+                r.y = r.y - qa * x1.y - qb * xn.y;
+                v[k] = cmul(r, ch.pre[j]);
+            } else {
+                v[k] = make_double2(0.0, 0.0);
+            }
+        }
+    };
+    double2 acc[8];
+    chirp_conv<LOGP>(acc, ch, ax.S, lds, tw, reload);
+    const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ch.mode;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int j = tid + k * BLOCK;
+        if (j < N) acc[k] = select_out(cmul(acc[k], ch.post[j]), mode);
+    }
+    if (ax.rank > 0) {  // DST family: x_mid -= U (E^T K)^{-1} E^T x_mid
+        if (tid < ax.rank) corr[tid] = acc[0];
+        __syncthreads();
+        const double2 s0 = corr[0];
+        const double2 s1 = ax.rank > 1 ? corr[1] : make_double2(0.0, 0.0);
+        const double2 a0 = make_double2(ax.Gm[0] * s0.x + ax.Gm[1] * s1.x, ax.Gm[0] * s0.y + ax.Gm[1] * s1.y);
+        const double2 a1 = make_double2(ax.Gm[2] * s0.x + ax.Gm[3] * s1.x, ax.Gm[2] * s0.y + ax.Gm[3] * s1.y);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int j = tid + k * BLOCK;
+            if (j < N) {
+                const double u0 = ax.U[j];
+                acc[k].x -= u0 * a0.x;
+                acc[k].y -= u0 * a0.y;
+                if (ax.rank > 1) {
+                    const double u1 = ax.U[N + j];
+                    acc[k].x -= u1 * a1.x;
+                    acc[k].y -= u1 * a1.y;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int j = tid + k * BLOCK;
+        if (j < N) vstore(out, ob, j + 1, acc[k]);
+    }
+    if (tid == 0) {
+        vstore(out, ob, 0, x1);
+        vstore(out, ob, n - 1, xn);
+    }
+}
+
+template <int LOGP>
+__global__ __launch_bounds__((1 << LOGP) / 8) void k_forward(Axis ax, View in, View out,
+                                                             const double2* __restrict__ tw) {
+    constexpr int P = 1 << LOGP;
+    constexpr int BLOCK = P / 8;
+    __shared__ double2 lds[P];
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int n = ax.n, N = ax.N;
+    const int64_t ib = vbase(in, b), ob = vbase(out, b);
+
+    const double2 x1 = vload(in, ib, 0), xn = vload(in, ib, n - 1);
+    const double2 beta0 = ax.rank > 0 ? vload(in, ib, 1) : make_double2(0.0, 0.0);
+    const double2 beta1 = ax.rank > 1 ? vload(in, ib, 2) : make_double2(0.0, 0.0);
+    const Chirp& ch = ax.syn;
+    auto reload = [&](double2 (&v)[8]) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int j = tid + k * BLOCK;
+            if (j < N && j >= ax.rank)
+                v[k] = cmul(vload(in, ib, j + 1), ch.pre[j]);
+            else
+                v[k] = make_double2(0.0, 0.0);
+        }
+    };
+    double2 acc[8];
+    chirp_conv<LOGP>(acc, ch, ax.S, lds, tw, reload);
+    const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ch.mode;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int j = tid + k * BLOCK;
+        if (j < N) {
+            const double2 u = select_out(cmul(acc[k], ch.post[j]), mode);
+            const double qa = ax.q[j + 1], qb = ax.q[N - j];
+            double2 y = make_double2(u.x + qa * x1.x + qb * xn.x, u.y + qa * x1.y + qb * xn.y);
+            if (ax.rank > 0) {
+                const double b0 = ax.bub[j];
+                y.x += b0 * beta0.x;
+                y.y += b0 * beta0.y;
+                if (ax.rank > 1) {
+                    const double b1 = ax.bub[N + j];
+                    y.x += b1 * beta1.x;
+                    y.y += b1 * beta1.y;
+                }
+            }
+            vstore(out, ob, j + 1, y);
+            // boundary rows: extension of the core columns to the two ghost grid points
+            if (ax.kind == HT_KIND_C || ax.kind == HT_KIND_F) {
+                const bool first_src = ax.kind == HT_KIND_C ? (j == 0) : (j == N - 1);
+                const bool last_src = ax.kind == HT_KIND_C ? (j == N - 1) : (j == 0);
+                if (first_src) vstore(out, ob, 0, make_double2(ax.q1 * x1.x + u.x, ax.q1 * x1.y + u.y));
+                if (last_src) vstore(out, ob, n - 1, make_double2(ax.q1 * xn.x + u.x, ax.q1 * xn.y + u.y));
+            }
+        }
+    }
+    if (tid == 0 && !(ax.kind == HT_KIND_C || ax.kind == HT_KIND_F)) {
+        vstore(out, ob, 0, cscale(x1, ax.q1));
+        vstore(out, ob, n - 1, cscale(xn, ax.q1));
+    }
+}
+
+template <int LOGP>
+static hipError_t launch_one(const Axis& ax, const double2* tw, bool inverse, const View& in,
+                             const View& out, int64_t count, hipStream_t stream) {
+    const dim3 grid(static_cast<unsigned>(count)), block((1 << LOGP) / 8);
+    if (inverse)
+        hipLaunchKernelGGL(k_inverse<LOGP>, grid, block, 0, stream, ax, in, out, tw);
+    else
+        hipLaunchKernelGGL(k_forward<LOGP>, grid, block, 0, stream, ax, in, out, tw);
+    return hipGetLastError();
+}
+
+ht_status launch_core(const Axis& ax, const double2* tw, bool inverse, const View& in,
+                      const View& out, int64_t count, hipStream_t stream) {
+    if (count <= 0) return HT_OK;
+    if (count > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "too many transforms in one call");
+    hipError_t e;
+    switch (ax.logP) {
+        case 9: e = launch_one<9>(ax, tw, inverse, in, out, count, stream); break;
+        case 10: e = launch_one<10>(ax, tw, inverse, in, out, count, stream); break;
+        case 11: e = launch_one<11>(ax, tw, inverse, in, out, count, stream); break;
+        case 12: e = launch_one<12>(ax, tw, inverse, in, out, count, stream); break;
+        case 13: e = launch_one<13>(ax, tw, inverse, in, out, count, stream); break;
+        default: return fail(HT_ERR_INVALID_ARG, "internal: FFT size out of range");
+    }
+    return check_hip(e, "transform launch");
+}
+
+}  // namespace ht
+
+using namespace ht;
+
+extern "C" ht_status ht_transform_inv(const ht_plan* plan, const double* signal, void* coeff,
+                                      int64_t batch, hipStream_t stream) {
+    if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_transform_inv: null plan");
+    if (batch < 0) return fail(HT_ERR_INVALID_ARG, "ht_transform_inv: negative batch");
+    if (batch == 0) return HT_OK;
+    if (!signal || !coeff) return fail(HT_ERR_INVALID_ARG, "ht_transform_inv: null argument");
+    const int cp = plan->cplx;
+    if (plan->ndim == 1) {
+        const Axis& a = plan->ax[0];
+        View in{const_cast<double*>(signal), 0, a.n, 1, batch, 0};
+        View out{coeff, 0, a.n, 1, batch, cp};
+        return launch_core(a, plan->tw, true, in, out, batch, stream);
+    }
+    if (batch > plan->max_batch) return fail(HT_ERR_INVALID_ARG, "ht_transform_inv: batch exceeds the plan's max_batch");
+    const Axis& a0 = plan->ax[0];
+    const Axis& a1 = plan->ax[1];
+    const int64_t img = static_cast<int64_t>(a0.n) * a1.n;
+    // axis 1: every row, signal -> coeff
+    View r_in{const_cast<double*>(signal), 0, a1.n, 1, batch * a0.n, 0};
+    View r_out{coeff, 0, a1.n, 1, batch * a0.n, cp};
+    ht_status st = launch_core(a1, plan->tw, true, r_in, r_out, batch * a0.n, stream);
+    if (st != HT_OK) return st;
+    // axis 0: every column, in place in coeff (a workgroup reads its whole column first)
+    View c_io{coeff, img, 1, a1.n, a1.n, cp};
+    return launch_core(a0, plan->tw, true, c_io, c_io, batch * a1.n, stream);
+}
+
+extern "C" ht_status ht_transform_fwd(const ht_plan* plan, const void* coeff, double* signal,
+                                      int64_t batch, hipStream_t stream) {
+    if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_transform_fwd: null plan");
+    if (batch < 0) return fail(HT_ERR_INVALID_ARG, "ht_transform_fwd: negative batch");
+    if (batch == 0) return HT_OK;
+    if (!signal || !coeff) return fail(HT_ERR_INVALID_ARG, "ht_transform_fwd: null argument");
+    const int cp = plan->cplx;
+    if (plan->ndim == 1) {
+        const Axis& a = plan->ax[0];
+        View in{const_cast<void*>(coeff), 0, a.n, 1, batch, cp};
+        View out{signal, 0, a.n, 1, batch, 0};
+        return launch_core(a, plan->tw, false, in, out, batch, stream);
+    }
+    if (batch > plan->max_batch) return fail(HT_ERR_INVALID_ARG, "ht_transform_fwd: batch exceeds the plan's max_batch");
+    const Axis& a0 = plan->ax[0];
+    const Axis& a1 = plan->ax[1];
+    const int64_t img = static_cast<int64_t>(a0.n) * a1.n;
+    // axis 0: every column, coeff -> workspace (complex for F, real otherwise)
+    View c_in{const_cast<void*>(coeff), img, 1, a1.n, a1.n, cp};
+    View c_out{plan->work, img, 1, a1.n, a1.n, cp};
+    ht_status st = launch_core(a0, plan->tw, false, c_in, c_out, batch * a1.n, stream);
+    if (st != HT_OK) return st;
+    // axis 1: every row, workspace -> signal (real part)
+    View r_in{plan->work, 0, a1.n, 1, batch * a0.n, cp};
+    View r_out{signal, 0, a1.n, 1, batch * a0.n, 0};
+    return launch_core(a1, plan->tw, false, r_in, r_out, batch * a0.n, stream);
+}

@@ -1,0 +1,193 @@
+"""Thin Python binding of libht (include/ht.h): argument marshalling only.
+
+Every function takes torch tensors that live on the current HIP device and passes their
+data pointers and the current torch stream to the C ABI; all arithmetic happens in the
+library's kernels.  There is no fallback: if libht.so is missing or a call fails, a
+RuntimeError is raised.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libht.so")
+
+HT_FAMILY_PAPER, HT_FAMILY_DST = 0, 1
+HT_NORM_IDENTITY, HT_NORM_SECOND_DIFF = 0, 1
+KIND_NAMES = {1: "AR", 2: "C", 3: "F", 4: "DST2", 5: "DST3"}
+NORMS = {"I": HT_NORM_IDENTITY, "D2": HT_NORM_SECOND_DIFF}
+FAMILIES = {"paper": HT_FAMILY_PAPER, "dst": HT_FAMILY_DST}
+
+_lib = None
+
+
+class HTError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libht.so (built in-tree by paper_0906_2704_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise HTError("libht.so is not built (run __graft_entry__.build()); there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, VP = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+    L.ht_plan_create.argtypes = [ctypes.c_int, ctypes.POINTER(I64), ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int, I64, ctypes.POINTER(P)]
+    L.ht_plan_destroy.argtypes = [P]
+    L.ht_plan_kind.argtypes = [P, ctypes.c_int]
+    L.ht_plan_is_complex.argtypes = [P]
+    L.ht_eigs.argtypes = [P, VP, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.c_int, VP, VP, I64, VP]
+    L.ht_transform_inv.argtypes = [P, VP, VP, I64, VP]
+    L.ht_transform_fwd.argtypes = [P, VP, VP, I64, VP]
+    L.ht_tikhonov_filter.argtypes = [P, VP, VP, VP, I64, VP, VP, I64, VP]
+    L.ht_gcv_scan.argtypes = [P, VP, VP, VP, I64, VP, I32, ctypes.c_int, VP, VP, VP, I64, VP]
+    L.ht_status_str.argtypes = [ctypes.c_int]
+    L.ht_status_str.restype = ctypes.c_char_p
+    L.ht_last_error.restype = ctypes.c_char_p
+    for name in ("ht_plan_create", "ht_plan_destroy", "ht_eigs", "ht_transform_inv", "ht_transform_fwd",
+                 "ht_tikhonov_filter", "ht_gcv_scan"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status, what):
+    if status != 0:
+        L = lib()
+        raise HTError("%s failed: %s (%s)" % (what, L.ht_status_str(status).decode(),
+                                               L.ht_last_error().decode()))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype, name):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise HTError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise HTError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise HTError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A transform plan (ht_plan_create).  `n` is an int (1D) or a pair (2D)."""
+
+    def __init__(self, n, degree, psf_symmetric=True, family="paper", max_batch=1):
+        L = lib()
+        dims = [int(n)] if isinstance(n, int) else [int(v) for v in n]
+        self.ndim = len(dims)
+        self.n = dims
+        arr = (ctypes.c_int64 * self.ndim)(*dims)
+        h = ctypes.c_void_p()
+        _check(L.ht_plan_create(self.ndim, arr, int(degree), int(bool(psf_symmetric)),
+                                FAMILIES.get(family, family), int(max_batch), ctypes.byref(h)),
+               "ht_plan_create")
+        self._h = h
+        self.degree = degree
+        self.max_batch = max_batch
+        self.kinds = [KIND_NAMES[L.ht_plan_kind(h, a)] for a in range(self.ndim)]
+        self.is_complex = bool(L.ht_plan_is_complex(h))
+        self.coeff_dtype = torch.complex128 if self.is_complex else torch.float64
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().ht_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def item_shape(self):
+        return tuple(self.n)
+
+    def spectrum_len(self):
+        return sum(self.n) if self.ndim == 2 else self.n[0]
+
+
+def ht_eigs(plan, psf, psf_len, psf_center, norm, batch=1):
+    """Eigenvalues d and s (see include/ht.h).  psf: float64 device tensor."""
+    L = lib()
+    m = plan.spectrum_len()
+    d = torch.empty((batch, m), dtype=plan.coeff_dtype, device=psf.device)
+    s = torch.empty((batch, m), dtype=torch.float64, device=psf.device)
+    lens = (ctypes.c_int64 * plan.ndim)(*[int(v) for v in psf_len])
+    cens = (ctypes.c_int64 * plan.ndim)(*[int(v) for v in psf_center])
+    _check(L.ht_eigs(plan.handle, _ptr(psf, torch.float64, "psf"), lens, cens, NORMS.get(norm, norm),
+                     _ptr(d, plan.coeff_dtype, "d"), _ptr(s, torch.float64, "s"), int(batch), _stream()),
+           "ht_eigs")
+    return d, s
+
+
+def ht_transform_inv(plan, signal, out=None):
+    L = lib()
+    batch = signal.numel() // _item(plan)
+    if out is None:
+        out = torch.empty(signal.shape, dtype=plan.coeff_dtype, device=signal.device)
+    _check(L.ht_transform_inv(plan.handle, _ptr(signal, torch.float64, "signal"),
+                              _ptr(out, plan.coeff_dtype, "coeff"), batch, _stream()), "ht_transform_inv")
+    return out
+
+
+def ht_transform_fwd(plan, coeff, out=None):
+    L = lib()
+    batch = coeff.numel() // _item(plan)
+    if out is None:
+        out = torch.empty(coeff.shape, dtype=torch.float64, device=coeff.device)
+    _check(L.ht_transform_fwd(plan.handle, _ptr(coeff, plan.coeff_dtype, "coeff"),
+                              _ptr(out, torch.float64, "signal"), batch, _stream()), "ht_transform_fwd")
+    return out
+
+
+def ht_tikhonov_filter(plan, coeff, d, s, mu, out=None):
+    L = lib()
+    batch = coeff.numel() // _item(plan)
+    eig_batch = d.numel() // plan.spectrum_len()
+    if out is None:
+        out = torch.empty_like(coeff)
+    _check(L.ht_tikhonov_filter(plan.handle, _ptr(coeff, plan.coeff_dtype, "coeff"),
+                                _ptr(d, plan.coeff_dtype, "d"), _ptr(s, torch.float64, "s"), eig_batch,
+                                _ptr(mu, torch.float64, "mu"), _ptr(out, plan.coeff_dtype, "fhat"),
+                                batch, _stream()), "ht_tikhonov_filter")
+    return out
+
+
+def ht_gcv_scan(plan, coeff, d, s, mu_grid, want_G=True):
+    """Returns (G or None, k_best int32 [batch], mu_best float64 [batch])."""
+    L = lib()
+    batch = coeff.numel() // _item(plan)
+    eig_batch = d.numel() // plan.spectrum_len()
+    K = mu_grid.shape[-1]
+    per_item = 1 if mu_grid.dim() == 2 else 0
+    dev = coeff.device
+    G = torch.empty((batch, K), dtype=torch.float64, device=dev) if want_G else None
+    kb = torch.empty(batch, dtype=torch.int32, device=dev)
+    mb = torch.empty(batch, dtype=torch.float64, device=dev)
+    _check(L.ht_gcv_scan(plan.handle, _ptr(coeff, plan.coeff_dtype, "coeff"), _ptr(d, plan.coeff_dtype, "d"),
+                         _ptr(s, torch.float64, "s"), eig_batch, _ptr(mu_grid, torch.float64, "mu_grid"),
+                         int(K), per_item, _ptr(G, torch.float64, "G"), _ptr(kb, torch.int32, "k_best"),
+                         _ptr(mb, torch.float64, "mu_best"), batch, _stream()), "ht_gcv_scan")
+    return G, kb, mb
+
+
+def _item(plan):
+    out = 1
+    for v in plan.n:
+        out *= v
+    return out
