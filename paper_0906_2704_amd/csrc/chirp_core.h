@@ -1,0 +1,68 @@
+// Chirp-z evaluation of the trigonometric cores on the LDS FFT (device code).
+//
+// Every core (DST-I, DCT-II, DCT-III, DFT, inverse DFT of order N) is written as
+//   Y_k = post_k * sum_j b_{k-j} (pre_j x_j),  k < N,
+// a circular convolution of length M >= 2N - 1 done as FFT, pointwise product with the
+// precomputed spectrum B = FFT_M(b) / M, inverse FFT.  M = S * P with P = 2^LOGP held in
+// LDS; for S = 2 (M = 16384 = TWN) the length-M transforms are split by even / odd
+// frequency into two length-P halves (the input occupies the first P points only, and
+// only the first N <= P outputs are kept).  The first half's finished values are parked
+// by the caller (in its output buffer) and added back after the second half, so only
+// the eight slot values are live across an FFT.
+#pragma once
+
+#include "fft_lds.h"
+
+namespace ht {
+
+__device__ __forceinline__ double2 select_out(double2 y, int mode) {
+    if (mode == MODE_RE) return make_double2(y.x, 0.0);
+    if (mode == MODE_IM) return make_double2(y.y, 0.0);
+    return y;
+}
+
+// in(j) returns x_j (j < N); result goes to out[k] for the slot j = tid + k * BLOCK < N.
+// The workgroup has fft_block_for(LOGP) threads.
+template <int LOGP, int S, class In, class Park, class Unpark>
+__device__ __forceinline__ void chirp_core(double2 (&out)[fft_slots_for(LOGP)], const Chirp& ch, int mode, int N,
+                                           double2* lds, const double2* __restrict__ tw, In in,
+                                           Park park, Unpark unpark) {
+    constexpr int SL = fft_slots_for(LOGP);
+    constexpr int BLOCK = fft_block_for(LOGP);
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        double2 v[SL];
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int j = tid + k * BLOCK;
+            v[k] = j < N ? cmul(in(j), ch.pre[j]) : make_double2(0.0, 0.0);
+            if (s == 1) v[k] = cmul(v[k], tw[j]);  // exp(-2 pi i j / M)
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        fft_slots<LOGP, -1>(v, lds, tw);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < SL; ++k) v[k] = cmul(v[k], ch.B[S * (tid + k * BLOCK) + s]);
+        __builtin_amdgcn_sched_barrier(0);
+        fft_slots<LOGP, 1>(v, lds, tw);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int j = tid + k * BLOCK;
+            if (j < N) {
+                double2 c = v[k];
+                if (s == 1) c = cmulc(c, tw[j]);  // exp(+2 pi i j / M)
+                const double2 y = select_out(cmul(c, ch.post[j]), mode);
+                if (S == 2 && s == 0)
+                    park(j, y);
+                else if (S == 2)
+                    out[k] = cadd(y, unpark(j));
+                else
+                    out[k] = y;
+            }
+        }
+    }
+}
+
+}  // namespace ht

@@ -1,7 +1,7 @@
 // Workgroup-wide complex float64 FFT of a power-of-two length P held in LDS.
 //
-// Layout: the workgroup has BLOCK = P / 8 threads; thread t owns the eight "slots"
-// t + s * BLOCK, s = 0..7, held in registers between passes.  Each pass is a Stockham
+// Layout: the workgroup has BLOCK = P / SLOTS threads (SLOTS = 8 or 16); thread t owns
+// the "slots" t + s * BLOCK, s = 0..SLOTS-1, held in registers between passes.  Each pass is a Stockham
 // autosort step of radix 8 (a final radix 2 or 4 pass covers the remaining bits): every
 // pass reads the thread's own slots, applies the pass twiddles, does a radix-R DFT in
 // registers and scatters the results to their positions for the next pass.  The first
@@ -89,11 +89,16 @@ __device__ __forceinline__ void dftR<8, -1>(double2 (&u)[8]) { dft8<-1>(u); }
 template <>
 __device__ __forceinline__ void dftR<8, 1>(double2 (&u)[8]) { dft8<1>(u); }
 
+// Threads per workgroup for an LDS FFT of 2^LOGP points: 8 points per thread up to 4096
+// points, 16 per thread for 8192 (512 threads, so that each wave may use 256 VGPRs).
+__host__ __device__ constexpr int fft_slots_for(int logp) { return logp >= 13 ? 16 : 8; }
+__host__ __device__ constexpr int fft_block_for(int logp) { return (1 << logp) / fft_slots_for(logp); }
+
 // One Stockham pass of radix R with Ns = product of the radices of earlier passes.
-template <int R, int DIR, int BLOCK, bool FIRST, bool LAST>
-__device__ __forceinline__ void stockham_pass(double2 (&v)[8], double2* lds,
+template <int R, int DIR, int BLOCK, int SLOTS, bool FIRST, bool LAST>
+__device__ __forceinline__ void stockham_pass(double2 (&v)[SLOTS], double2* lds,
                                               const double2* __restrict__ tw, int Ns) {
-    constexpr int C = 8 / R;  // butterflies per thread
+    constexpr int C = SLOTS / R;  // butterflies per thread
     const int tid = threadIdx.x;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -103,11 +108,28 @@ __device__ __forceinline__ void stockham_pass(double2 (&v)[8], double2* lds,
         for (int r = 0; r < R; ++r) u[r] = v[c + r * C];
         const int k = t & (Ns - 1);
         if (!FIRST) {
+            // w^r, r = 1..R-1, w = exp(-2 pi i k / (Ns R)): powers 1, 2, 4 from the table,
+            // the others as products of two of them (a few ulp, far below the tolerance)
             const int step = (TWN / (Ns * R)) * k;
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                double2 w = tw[step * r];
-                u[r] = DIR < 0 ? cmul(u[r], w) : cmulc(u[r], w);
+            const double2 w1 = tw[step];
+            if constexpr (R == 2) {
+                u[1] = DIR < 0 ? cmul(u[1], w1) : cmulc(u[1], w1);
+            } else {
+                const double2 w2 = tw[2 * step];
+                u[1] = DIR < 0 ? cmul(u[1], w1) : cmulc(u[1], w1);
+                u[2] = DIR < 0 ? cmul(u[2], w2) : cmulc(u[2], w2);
+                const double2 w3 = cmul(w1, w2);
+                u[3] = DIR < 0 ? cmul(u[3], w3) : cmulc(u[3], w3);
+                if constexpr (R == 8) {
+                    const double2 w4 = tw[4 * step];
+                    u[4] = DIR < 0 ? cmul(u[4], w4) : cmulc(u[4], w4);
+                    const double2 w5 = cmul(w1, w4);
+                    u[5] = DIR < 0 ? cmul(u[5], w5) : cmulc(u[5], w5);
+                    const double2 w6 = cmul(w2, w4);
+                    u[6] = DIR < 0 ? cmul(u[6], w6) : cmulc(u[6], w6);
+                    const double2 w7 = cmul(w3, w4);
+                    u[7] = DIR < 0 ? cmul(u[7], w7) : cmulc(u[7], w7);
+                }
             }
         }
         dftR<R, DIR>(u);
@@ -119,37 +141,39 @@ __device__ __forceinline__ void stockham_pass(double2 (&v)[8], double2* lds,
 #pragma unroll
             for (int r = 0; r < R; ++r) lds[base + r * Ns] = u[r];
         }
+        // one butterfly at a time: keeps the live registers to one butterfly's worth
+        if (C > 1 && SLOTS > 8) __builtin_amdgcn_sched_barrier(0);
     }
     if (!LAST) {
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < 8; ++s) v[s] = lds[tid + s * BLOCK];
+        for (int s = 0; s < SLOTS; ++s) v[s] = lds[tid + s * BLOCK];
         __syncthreads();
     }
 }
 
 // Full FFT of length P = 2^LOGP on the slots v (natural order in, natural order out).
 template <int LOGP, int DIR>
-__device__ __forceinline__ void fft_slots(double2 (&v)[8], double2* lds, const double2* __restrict__ tw) {
-    constexpr int P = 1 << LOGP;
-    constexpr int BLOCK = P / 8;
+__device__ __forceinline__ void fft_slots(double2 (&v)[fft_slots_for(LOGP)], double2* lds,
+                                          const double2* __restrict__ tw) {
+    constexpr int SL = fft_slots_for(LOGP);
+    constexpr int BL = fft_block_for(LOGP);
     constexpr int NR8 = LOGP / 3;
     constexpr int REM = LOGP % 3;
     static_assert(LOGP >= 9 && LOGP <= 13, "FFT length out of range");
-    // radix-8 passes
-    stockham_pass<8, DIR, BLOCK, true, false>(v, lds, tw, 1);
-    stockham_pass<8, DIR, BLOCK, false, false>(v, lds, tw, 8);
+    stockham_pass<8, DIR, BL, SL, true, false>(v, lds, tw, 1);
+    stockham_pass<8, DIR, BL, SL, false, false>(v, lds, tw, 8);
     if constexpr (NR8 == 3 && REM == 0) {
-        stockham_pass<8, DIR, BLOCK, false, true>(v, lds, tw, 64);
+        stockham_pass<8, DIR, BL, SL, false, true>(v, lds, tw, 64);
     } else {
-        stockham_pass<8, DIR, BLOCK, false, false>(v, lds, tw, 64);
+        stockham_pass<8, DIR, BL, SL, false, false>(v, lds, tw, 64);
         if constexpr (NR8 == 4 && REM == 0) {
-            stockham_pass<8, DIR, BLOCK, false, true>(v, lds, tw, 512);
+            stockham_pass<8, DIR, BL, SL, false, true>(v, lds, tw, 512);
         } else if constexpr (NR8 == 3) {
-            stockham_pass<(1 << REM), DIR, BLOCK, false, true>(v, lds, tw, 512);
+            stockham_pass<(1 << REM), DIR, BL, SL, false, true>(v, lds, tw, 512);
         } else {  // NR8 == 4, REM == 1 (P = 8192)
-            stockham_pass<8, DIR, BLOCK, false, false>(v, lds, tw, 512);
-            stockham_pass<2, DIR, BLOCK, false, true>(v, lds, tw, 4096);
+            stockham_pass<8, DIR, BL, SL, false, false>(v, lds, tw, 512);
+            stockham_pass<2, DIR, BL, SL, false, true>(v, lds, tw, 4096);
         }
     }
 }

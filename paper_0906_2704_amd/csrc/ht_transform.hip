@@ -14,7 +14,7 @@
 //            exponential core) plus q_1 x_1 / q_1 x_n.
 #include <hip/hip_runtime.h>
 
-#include "fft_lds.h"
+#include "chirp_core.h"
 #include "ht_internal.h"
 
 namespace ht {
@@ -37,48 +37,12 @@ __device__ __forceinline__ int64_t vbase(const View& v, int64_t b) {
     return (b / v.per_img) * v.img_stride + (b % v.per_img) * v.sig_stride;
 }
 
-__device__ __forceinline__ double2 select_out(double2 y, int mode) {
-    if (mode == MODE_RE) return make_double2(y.x, 0.0);
-    if (mode == MODE_IM) return make_double2(y.y, 0.0);
-    return y;
-}
-
-// Chirp-z core on the thread's slots: on entry `a` holds pre_j * x_j for the slot
-// indices j < N (0 elsewhere) of split s = 0; `reload` recomputes it for split s = 1.
-// On exit acc holds the convolution (before post-multiplication).
-template <int LOGP, typename Reload>
-__device__ __forceinline__ void chirp_conv(double2 (&acc)[8], const Chirp& ch, int S,
-                                           double2* lds, const double2* __restrict__ tw,
-                                           Reload reload) {
-    constexpr int P = 1 << LOGP;
-    constexpr int BLOCK = P / 8;
-    const int tid = threadIdx.x;
-    for (int s = 0; s < S; ++s) {
-        double2 v[8];
-        reload(v);
-        if (s == 1) {  // M = 2P = TWN: fold exp(-2 pi i j / M) into the input
-#pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = cmul(v[k], tw[tid + k * BLOCK]);
-        }
-        fft_slots<LOGP, -1>(v, lds, tw);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = cmul(v[k], ch.B[S * (tid + k * BLOCK) + s]);
-        fft_slots<LOGP, 1>(v, lds, tw);
-        if (s == 0) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) acc[k] = v[k];
-        } else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) acc[k] = cadd(acc[k], cmulc(v[k], tw[tid + k * BLOCK]));
-        }
-    }
-}
-
-template <int LOGP>
-__global__ __launch_bounds__((1 << LOGP) / 8) void k_inverse(Axis ax, View in, View out,
+template <int LOGP, int S>
+__global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View in, View out,
                                                              const double2* __restrict__ tw) {
     constexpr int P = 1 << LOGP;
-    constexpr int BLOCK = P / 8;
+    constexpr int SL = fft_slots_for(LOGP);
+    constexpr int BLOCK = fft_block_for(LOGP);
     __shared__ double2 lds[P];
     __shared__ double2 corr[2];
     const int tid = threadIdx.x;
@@ -100,30 +64,19 @@ __global__ __launch_bounds__((1 << LOGP) / 8) void k_inverse(Axis ax, View in, V
         x1 = cscale(y0, inv);
         xn = cscale(yL, inv);
     }
-    const Chirp& ch = ax.ana;
-    auto reload = [&](double2 (&v)[8]) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int j = tid + k * BLOCK;
-            if (j < N) {
-                double2 r = vload(in, ib, j + 1);
-                const double qa = ax.q[j + 1], qb = ax.q[N - j];
-                r.x = r.x - qa * x1.x - qb * xn.x;
-                r.y = r.y - qa * x1.y - qb * xn.y;
-                v[k] = cmul(r, ch.pre[j]);
-            } else {
-                v[k] = make_double2(0.0, 0.0);
-            }
-        }
+    // interior correction r_j = y_{j+1} - q^_j x_1 - (J q^)_j x_n, then the core analysis
+    auto in_fn = [&](int j) {
+        double2 r = vload(in, ib, j + 1);
+        const double qa = ax.q[j + 1], qb = ax.q[N - j];
+        r.x = r.x - qa * x1.x - qb * xn.x;
+        r.y = r.y - qa * x1.y - qb * xn.y;
+        return r;
     };
-    double2 acc[8];
-    chirp_conv<LOGP>(acc, ch, ax.S, lds, tw, reload);
-    const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ch.mode;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int j = tid + k * BLOCK;
-        if (j < N) acc[k] = select_out(cmul(acc[k], ch.post[j]), mode);
-    }
+    auto park = [&](int j, double2 y) { vstore(out, ob, j + 1, y); };
+    auto unpark = [&](int j) { return vload(out, ob, j + 1); };
+    const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ax.ana.mode;
+    double2 acc[SL];
+    chirp_core<LOGP, S>(acc, ax.ana, mode, N, lds, tw, in_fn, park, unpark);
     if (ax.rank > 0) {  // DST family: x_mid -= U (E^T K)^{-1} E^T x_mid
         if (tid < ax.rank) corr[tid] = acc[0];
         __syncthreads();
@@ -132,7 +85,7 @@ __global__ __launch_bounds__((1 << LOGP) / 8) void k_inverse(Axis ax, View in, V
         const double2 a0 = make_double2(ax.Gm[0] * s0.x + ax.Gm[1] * s1.x, ax.Gm[0] * s0.y + ax.Gm[1] * s1.y);
         const double2 a1 = make_double2(ax.Gm[2] * s0.x + ax.Gm[3] * s1.x, ax.Gm[2] * s0.y + ax.Gm[3] * s1.y);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < SL; ++k) {
             const int j = tid + k * BLOCK;
             if (j < N) {
                 const double u0 = ax.U[j];
@@ -147,7 +100,7 @@ __global__ __launch_bounds__((1 << LOGP) / 8) void k_inverse(Axis ax, View in, V
         }
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;
         if (j < N) vstore(out, ob, j + 1, acc[k]);
     }
@@ -157,11 +110,12 @@ __global__ __launch_bounds__((1 << LOGP) / 8) void k_inverse(Axis ax, View in, V
     }
 }
 
-template <int LOGP>
-__global__ __launch_bounds__((1 << LOGP) / 8) void k_forward(Axis ax, View in, View out,
+template <int LOGP, int S>
+__global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View in, View out,
                                                              const double2* __restrict__ tw) {
     constexpr int P = 1 << LOGP;
-    constexpr int BLOCK = P / 8;
+    constexpr int SL = fft_slots_for(LOGP);
+    constexpr int BLOCK = fft_block_for(LOGP);
     __shared__ double2 lds[P];
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
@@ -171,27 +125,19 @@ __global__ __launch_bounds__((1 << LOGP) / 8) void k_forward(Axis ax, View in, V
     const double2 x1 = vload(in, ib, 0), xn = vload(in, ib, n - 1);
     const double2 beta0 = ax.rank > 0 ? vload(in, ib, 1) : make_double2(0.0, 0.0);
     const double2 beta1 = ax.rank > 1 ? vload(in, ib, 2) : make_double2(0.0, 0.0);
-    const Chirp& ch = ax.syn;
-    auto reload = [&](double2 (&v)[8]) {
+    // the replaced (bubble) columns are added explicitly, not through the sine core
+    auto in_fn = [&](int j) { return j >= ax.rank ? vload(in, ib, j + 1) : make_double2(0.0, 0.0); };
+    auto park = [&](int j, double2 y) { vstore(out, ob, j + 1, y); };
+    auto unpark = [&](int j) { return vload(out, ob, j + 1); };
+    const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ax.syn.mode;
+    double2 u[SL];
+    chirp_core<LOGP, S>(u, ax.syn, mode, N, lds, tw, in_fn, park, unpark);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int j = tid + k * BLOCK;
-            if (j < N && j >= ax.rank)
-                v[k] = cmul(vload(in, ib, j + 1), ch.pre[j]);
-            else
-                v[k] = make_double2(0.0, 0.0);
-        }
-    };
-    double2 acc[8];
-    chirp_conv<LOGP>(acc, ch, ax.S, lds, tw, reload);
-    const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ch.mode;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;
         if (j < N) {
-            const double2 u = select_out(cmul(acc[k], ch.post[j]), mode);
             const double qa = ax.q[j + 1], qb = ax.q[N - j];
-            double2 y = make_double2(u.x + qa * x1.x + qb * xn.x, u.y + qa * x1.y + qb * xn.y);
+            double2 y = make_double2(u[k].x + qa * x1.x + qb * xn.x, u[k].y + qa * x1.y + qb * xn.y);
             if (ax.rank > 0) {
                 const double b0 = ax.bub[j];
                 y.x += b0 * beta0.x;
@@ -207,8 +153,8 @@ __global__ __launch_bounds__((1 << LOGP) / 8) void k_forward(Axis ax, View in, V
             if (ax.kind == HT_KIND_C || ax.kind == HT_KIND_F) {
                 const bool first_src = ax.kind == HT_KIND_C ? (j == 0) : (j == N - 1);
                 const bool last_src = ax.kind == HT_KIND_C ? (j == N - 1) : (j == 0);
-                if (first_src) vstore(out, ob, 0, make_double2(ax.q1 * x1.x + u.x, ax.q1 * x1.y + u.y));
-                if (last_src) vstore(out, ob, n - 1, make_double2(ax.q1 * xn.x + u.x, ax.q1 * xn.y + u.y));
+                if (first_src) vstore(out, ob, 0, make_double2(ax.q1 * x1.x + u[k].x, ax.q1 * x1.y + u[k].y));
+                if (last_src) vstore(out, ob, n - 1, make_double2(ax.q1 * xn.x + u[k].x, ax.q1 * xn.y + u[k].y));
             }
         }
     }
@@ -221,11 +167,22 @@ __global__ __launch_bounds__((1 << LOGP) / 8) void k_forward(Axis ax, View in, V
 template <int LOGP>
 static hipError_t launch_one(const Axis& ax, const double2* tw, bool inverse, const View& in,
                              const View& out, int64_t count, hipStream_t stream) {
-    const dim3 grid(static_cast<unsigned>(count)), block((1 << LOGP) / 8);
-    if (inverse)
-        hipLaunchKernelGGL(k_inverse<LOGP>, grid, block, 0, stream, ax, in, out, tw);
-    else
-        hipLaunchKernelGGL(k_forward<LOGP>, grid, block, 0, stream, ax, in, out, tw);
+    const dim3 grid(static_cast<unsigned>(count)), block(fft_block_for(LOGP));
+    if constexpr (LOGP == MAX_LOGP) {
+        if (ax.S == 2) {
+            if (inverse)
+                hipLaunchKernelGGL((k_inverse<LOGP, 2>), grid, block, 0, stream, ax, in, out, tw);
+            else
+                hipLaunchKernelGGL((k_forward<LOGP, 2>), grid, block, 0, stream, ax, in, out, tw);
+            return hipGetLastError();
+        }
+    }
+    {
+        if (inverse)
+            hipLaunchKernelGGL((k_inverse<LOGP, 1>), grid, block, 0, stream, ax, in, out, tw);
+        else
+            hipLaunchKernelGGL((k_forward<LOGP, 1>), grid, block, 0, stream, ax, in, out, tw);
+    }
     return hipGetLastError();
 }
 
@@ -266,14 +223,15 @@ extern "C" ht_status ht_transform_inv(const ht_plan* plan, const double* signal,
     const Axis& a0 = plan->ax[0];
     const Axis& a1 = plan->ax[1];
     const int64_t img = static_cast<int64_t>(a0.n) * a1.n;
-    // axis 1: every row, signal -> coeff
+    // axis 1: every row, signal -> workspace
     View r_in{const_cast<double*>(signal), 0, a1.n, 1, batch * a0.n, 0};
-    View r_out{coeff, 0, a1.n, 1, batch * a0.n, cp};
+    View r_out{plan->work, 0, a1.n, 1, batch * a0.n, cp};
     ht_status st = launch_core(a1, plan->tw, true, r_in, r_out, batch * a0.n, stream);
     if (st != HT_OK) return st;
-    // axis 0: every column, in place in coeff (a workgroup reads its whole column first)
-    View c_io{coeff, img, 1, a1.n, a1.n, cp};
-    return launch_core(a0, plan->tw, true, c_io, c_io, batch * a1.n, stream);
+    // axis 0: every column, workspace -> coeff
+    View c_in{plan->work, img, 1, a1.n, a1.n, cp};
+    View c_out{coeff, img, 1, a1.n, a1.n, cp};
+    return launch_core(a0, plan->tw, true, c_in, c_out, batch * a1.n, stream);
 }
 
 extern "C" ht_status ht_transform_fwd(const ht_plan* plan, const void* coeff, double* signal,

@@ -121,12 +121,14 @@ class Plan:
         return sum(self.n) if self.ndim == 2 else self.n[0]
 
 
-def ht_eigs(plan, psf, psf_len, psf_center, norm, batch=1):
+def ht_eigs(plan, psf, psf_len, psf_center, norm, batch=1, d=None, s=None):
     """Eigenvalues d and s (see include/ht.h).  psf: float64 device tensor."""
     L = lib()
     m = plan.spectrum_len()
-    d = torch.empty((batch, m), dtype=plan.coeff_dtype, device=psf.device)
-    s = torch.empty((batch, m), dtype=torch.float64, device=psf.device)
+    if d is None:
+        d = torch.empty((batch, m), dtype=plan.coeff_dtype, device=psf.device)
+    if s is None:
+        s = torch.empty((batch, m), dtype=torch.float64, device=psf.device)
     lens = (ctypes.c_int64 * plan.ndim)(*[int(v) for v in psf_len])
     cens = (ctypes.c_int64 * plan.ndim)(*[int(v) for v in psf_center])
     _check(L.ht_eigs(plan.handle, _ptr(psf, torch.float64, "psf"), lens, cens, NORMS.get(norm, norm),
@@ -168,7 +170,7 @@ def ht_tikhonov_filter(plan, coeff, d, s, mu, out=None):
     return out
 
 
-def ht_gcv_scan(plan, coeff, d, s, mu_grid, want_G=True):
+def ht_gcv_scan(plan, coeff, d, s, mu_grid, want_G=True, G=None, kb=None, mb=None):
     """Returns (G or None, k_best int32 [batch], mu_best float64 [batch])."""
     L = lib()
     batch = coeff.numel() // _item(plan)
@@ -176,9 +178,12 @@ def ht_gcv_scan(plan, coeff, d, s, mu_grid, want_G=True):
     K = mu_grid.shape[-1]
     per_item = 1 if mu_grid.dim() == 2 else 0
     dev = coeff.device
-    G = torch.empty((batch, K), dtype=torch.float64, device=dev) if want_G else None
-    kb = torch.empty(batch, dtype=torch.int32, device=dev)
-    mb = torch.empty(batch, dtype=torch.float64, device=dev)
+    if G is None and want_G:
+        G = torch.empty((batch, K), dtype=torch.float64, device=dev)
+    if kb is None:
+        kb = torch.empty(batch, dtype=torch.int32, device=dev)
+    if mb is None:
+        mb = torch.empty(batch, dtype=torch.float64, device=dev)
     _check(L.ht_gcv_scan(plan.handle, _ptr(coeff, plan.coeff_dtype, "coeff"), _ptr(d, plan.coeff_dtype, "d"),
                          _ptr(s, torch.float64, "s"), eig_batch, _ptr(mu_grid, torch.float64, "mu_grid"),
                          int(K), per_item, _ptr(G, torch.float64, "G"), _ptr(kb, torch.int32, "k_best"),
