@@ -56,7 +56,9 @@ typedef enum {
  *  HT_FAMILY_DST:   degree 1..3 -> the antireflective transform whose lowest degree-1
  *                   sine columns are replaced by polynomial "bubbles" (symmetric PSF);
  *                   degree 1 is identical to the antireflective transform.            */
-typedef enum { HT_FAMILY_PAPER = 0, HT_FAMILY_DST = 1 } ht_family;
+/*  HT_FAMILY_PAPER_DST3: degrees 1 and 2 as HT_FAMILY_PAPER, degree 3 as HT_FAMILY_DST
+ *                   (the paper defines no degree-3 transform of its own).            */
+typedef enum { HT_FAMILY_PAPER = 0, HT_FAMILY_DST = 1, HT_FAMILY_PAPER_DST3 = 2 } ht_family;
 
 /* Smoothing operator of eq. mintik: L = I, or the second difference with the same
  * boundary model (eq. L, L_C, L_F; in 2D the Laplacian L0 (x) I + I (x) L1).          */
@@ -133,6 +135,48 @@ ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const void* d, con
                       int64_t eig_batch, const double* mu_grid, int32_t K, int grid_per_item,
                       double* G, int32_t* k_best, double* mu_best, int64_t batch,
                       hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------
+ * Ragged batches: many 1D signals of uneven length n_b, each with its own PSF mask,
+ * boundary degree and mu grid, restored end to end (eigenvalues, inverse transform, GCV
+ * choice of mu over the signal's grid, filter, forward transform; Sections 2-4) by
+ * persistent fused kernels, one per FFT size class, that take signals from a
+ * longest-first queue.  Symmetric PSFs only (real transforms: AR, C, DST2, DST3).
+ * Every call is asynchronous, allocates nothing and may be captured in a HIP graph.
+ * --------------------------------------------------------------------------------- */
+typedef struct ht_batch ht_batch;
+
+/* Describe a batch (host arrays of length count): signal lengths n[b] in [5, 8192],
+ * degree[b] / psf_symmetric[b] resolved per `family` as for ht_plan_create, and the
+ * shape of each PSF mask (psf_len[b], psf_center[b]; 2m+1 <= n-2).  Builds the tables of
+ * every distinct (n, kind) once.  Signals are concatenated in item order (offsets are
+ * the prefix sums of n), masks likewise (prefix sums of psf_len).                    */
+ht_status ht_batch_create(int64_t count, const int64_t* n, const int* degree,
+                          const int* psf_symmetric, int family, const int64_t* psf_len,
+                          const int64_t* psf_center, ht_batch** out);
+ht_status ht_batch_destroy(ht_batch* batch);
+/* sum of n[b] (length of the signal and restored arrays), or -1 */
+int64_t ht_batch_total_length(const ht_batch* batch);
+/* sum of psf_len[b] (length of the PSF array), or -1 */
+int64_t ht_batch_psf_total(const ht_batch* batch);
+
+/* ht_batch_restore -- for every signal b: d, s on its grid, ghat = T^{-1} g,
+ * G_b(mu_{b,k}) for k < K (eq. mugcv), k_b = first argmin, f = T Phi D^{-1} ghat at
+ * mu_{b,k_b} (eq. freg).
+ *   signal [total_length], psf [psf_total], mu_grid [count][K] (one grid per signal,
+ *   mu > 0), restored [total_length] (must not overlap signal), G [count][K] or NULL,
+ *   k_best int32 [count] (-1 if some G is not finite; the restoration is then NaN),
+ *   mu_best [count].  1 <= K <= 256.  The sums of G are float64 in a fixed order.   */
+ht_status ht_batch_restore(const ht_batch* batch, const double* signal, const double* psf,
+                           int norm, const double* mu_grid, int32_t K, double* restored,
+                           double* G, int32_t* k_best, double* mu_best, hipStream_t stream);
+
+/* Schedule knob (used by the autotuner): number of persistent workgroups of size class
+ * `size_class` (0..5: FFT lengths 512, 1024, 2048, 4096, 8192, 2 x 8192).  workgroups <= 0
+ * only queries.  *current (may be NULL) receives the value in effect.               */
+ht_status ht_batch_schedule(ht_batch* batch, int size_class, int workgroups, int* current);
+/* number of signals in a size class, or -1 */
+int ht_batch_class_count(const ht_batch* batch, int size_class);
 
 const char* ht_status_str(ht_status status);
 const char* ht_last_error(void);

@@ -21,7 +21,8 @@ __device__ __forceinline__ double2 select_out(double2 y, int mode) {
     return y;
 }
 
-// in(j) returns x_j (j < N); result goes to out[k] for the slot j = tid + k * BLOCK < N.
+// in(k, j) returns x_j for the slot k holding j = tid + k * BLOCK < N; the result goes to
+// out[k].
 // The workgroup has fft_block_for(LOGP) threads.
 template <int LOGP, int S, class In, class Park, class Unpark>
 __device__ __forceinline__ void chirp_core(double2 (&out)[fft_slots_for(LOGP)], const Chirp& ch, int mode, int N,
@@ -36,7 +37,7 @@ __device__ __forceinline__ void chirp_core(double2 (&out)[fft_slots_for(LOGP)], 
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
             const int j = tid + k * BLOCK;
-            v[k] = j < N ? cmul(in(j), ch.pre[j]) : make_double2(0.0, 0.0);
+            v[k] = j < N ? cmul(in(k, j), ch.pre[j]) : make_double2(0.0, 0.0);
             if (s == 1) v[k] = cmul(v[k], tw[j]);  // exp(-2 pi i j / M)
         }
         __builtin_amdgcn_sched_barrier(0);

@@ -1,0 +1,518 @@
+// Ragged batches: thousands of 1D signals of uneven length, each with its own PSF, boundary
+// degree and mu grid, restored by one persistent fused kernel per FFT size class.
+//
+// For every signal a workgroup runs the whole method without leaving the chip between
+// steps: inverse transform (Theorem th:inv) -> eigenvalues of the blur and of the
+// smoothing operator on the signal's grid (eqs. jcf, Ac) -> GCV over the signal's grid
+// (eq. mugcv) -> Tikhonov filter at the chosen mu (eq. freg) -> forward transform.  The
+// coefficients, eigenvalues and filter factors live in registers; LDS holds the FFT, then
+// the exactly rounded cosine table of the signal's grid, then the (t_i, w_i) pairs the
+// GCV sums read.  Workgroups take signals from a per-class queue (an atomic counter),
+// longest first.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <map>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "chirp_core.h"
+#include "ht_internal.h"
+#include "plan_build.h"
+
+namespace ht {
+
+constexpr int NCLASS = 6;          // (LOGP, S): (9,1) (10,1) (11,1) (12,1) (13,1) (13,2)
+constexpr int BATCH_MAX_K = 256;
+
+struct RSig {
+    int64_t off;        // offset of the signal in the concatenated signal / output arrays
+    int64_t psf_off;    // offset of its mask in the concatenated PSF array
+    int32_t psf_len, psf_center;
+    int32_t axis;       // index of its transform tables
+    int32_t item;       // caller's index (row of the mu grid, outputs)
+};
+
+struct RaggedArgs {
+    const Axis* axes;
+    const RSig* sigs;
+    int* counters;
+    const double* g;
+    const double* psf;
+    const double* mus;
+    int K;
+    int norm;
+    double* f;
+    double* G;
+    int32_t* kbest;
+    double* mubest;
+};
+
+static int class_of(const Axis& a) { return a.S == 2 ? 5 : a.logP - MIN_LOGP; }
+
+__global__ void k_reset_counters(int* c) {
+    if (threadIdx.x < NCLASS) c[threadIdx.x] = 0;
+}
+
+template <int LOGP, int S>
+__global__ __launch_bounds__(fft_block_for(LOGP)) void k_restore(RaggedArgs a, int cls, int start, int count,
+                                                                 const double2* __restrict__ tw) {
+    constexpr int P = 1 << LOGP;
+    constexpr int SL = fft_slots_for(LOGP);
+    constexpr int BLOCK = fft_block_for(LOGP);
+    __shared__ double2 lds[P];
+    __shared__ double2 red[BLOCK];
+    __shared__ double Gs[BATCH_MAX_K];
+    __shared__ double2 bc[3];
+    __shared__ int s_item, s_kbest;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&a.counters[cls], 1);
+        __syncthreads();
+        const int qi = s_item;
+        __syncthreads();
+        if (qi >= count) break;
+        const RSig sg = a.sigs[start + qi];
+        const Axis& ax = a.axes[sg.axis];
+        const int n = ax.n, N = ax.N, rank = ax.rank, kind = ax.kind, den = ax.den;
+        const double* g = a.g + sg.off;
+        double* f = a.f + sg.off;
+        const double* h = a.psf + sg.psf_off;
+        const double q1 = ax.q1;
+
+        // ---- inverse transform: boundary coefficients, interior correction, core analysis
+        double x1, xn;
+        {
+            const double y0 = g[0], y1 = g[1], yN = g[n - 2], yL = g[n - 1];
+            if (kind == HT_KIND_C) {
+                const double r1 = y0 - y1, r2 = yL - yN;
+                x1 = ax.minv[0] * r1 + ax.minv[1] * r2;
+                xn = ax.minv[2] * r1 + ax.minv[3] * r2;
+            } else {
+                x1 = y0 / q1;
+                xn = yL / q1;
+            }
+        }
+        double c[SL];
+        {
+            auto in_inv = [&](int, int j) {
+                return make_double2(g[j + 1] - ax.q[j + 1] * x1 - ax.q[N - j] * xn, 0.0);
+            };
+            auto park = [&](int j, double2 y) { f[j + 1] = y.x; };
+            auto unpark = [&](int j) { return make_double2(f[j + 1], 0.0); };
+            double2 out[SL];
+            chirp_core<LOGP, S>(out, ax.ana, ax.ana.mode, N, lds, tw, in_inv, park, unpark);
+#pragma unroll
+            for (int k = 0; k < SL; ++k) c[k] = out[k].x;
+        }
+        if (rank > 0) {  // DST family correction x_mid -= U (E^T K)^{-1} E^T x_mid
+            if (tid < rank) bc[tid].x = c[0];
+            __syncthreads();
+            const double s0 = bc[0].x, s1 = rank > 1 ? bc[1].x : 0.0;
+            const double a0 = ax.Gm[0] * s0 + ax.Gm[1] * s1;
+            const double a1 = ax.Gm[2] * s0 + ax.Gm[3] * s1;
+#pragma unroll
+            for (int k = 0; k < SL; ++k) {
+                const int j = tid + k * BLOCK;
+                if (j < N) {
+                    c[k] -= ax.U[j] * a0;
+                    if (rank > 1) c[k] -= ax.U[N + j] * a1;
+                }
+            }
+        }
+
+        // ---- eigenvalues on the signal's grid: cos(pi r / den), r <= den, staged in LDS
+        double* ctab = reinterpret_cast<double*>(lds);
+        __syncthreads();
+        for (int r = tid; r <= den; r += BLOCK) ctab[r] = ax.tcos[r];
+        __syncthreads();
+        double z0 = 0.0;
+        for (int t = 0; t < sg.psf_len; ++t) z0 += h[t];
+        const bool ident = a.norm == HT_NORM_IDENTITY;
+        const double s_poly = ident ? 1.0 : 0.0;
+        const int per = 2 * den;
+        const int pc = sg.psf_center, pl = sg.psf_len;
+        const bool centred = 2 * pc + 1 == pl;
+        double dj[SL], sj[SL];
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int j = tid + k * BLOCK;
+            dj[k] = z0;
+            sj[k] = s_poly;
+            if (j < N && j >= rank) {
+                const int num = kind == HT_KIND_C ? j : j + 1;  // frequency pi * num / den
+                double acc;
+                if (centred) {
+                    // Re z = h_0 + sum_{t>0} (h_t + h_{-t}) cos(t theta)
+                    acc = h[pc];
+                    int r = 0;
+                    for (int t = 1; t <= pc; ++t) {
+                        r += num;
+                        if (r >= per) r -= per;
+                        const double cv = ctab[r <= den ? r : per - r];
+                        acc = fma(h[pc + t] + h[pc - t], cv, acc);
+                    }
+                } else {
+                    acc = 0.0;
+                    int r = static_cast<int>((static_cast<int64_t>(per) * pl - static_cast<int64_t>(pc) * num) % per);
+                    for (int t = 0; t < pl; ++t) {
+                        const double cv = ctab[r <= den ? r : per - r];
+                        acc = fma(h[t], cv, acc);
+                        r += num;
+                        if (r >= per) r -= per;
+                    }
+                }
+                dj[k] = acc;
+                const int rn = num % per;
+                sj[k] = ident ? 1.0 : 2.0 - 2.0 * ctab[rn <= den ? rn : per - rn];
+            }
+        }
+        __syncthreads();
+
+        // ---- GCV: stage t_i = |d_i|^2 / |s_i|^2, w_i = |ghat_i|^2 (s_i = 0: no contribution)
+        double2* stage = lds;
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int j = tid + k * BLOCK;
+            if (j < N) {
+                const double s2 = sj[k] * sj[k];
+                stage[j] = s2 != 0.0 ? make_double2(dj[k] * dj[k] / s2, c[k] * c[k]) : make_double2(1e150, 0.0);
+            }
+        }
+        if (tid == 0) {
+            const double s2 = s_poly * s_poly;
+            stage[N] = s2 != 0.0 ? make_double2(z0 * z0 / s2, x1 * x1) : make_double2(1e150, 0.0);
+            stage[N + 1] = s2 != 0.0 ? make_double2(z0 * z0 / s2, xn * xn) : make_double2(1e150, 0.0);
+        }
+        __syncthreads();
+        const int K = a.K;
+        const double* mus = a.mus + static_cast<int64_t>(sg.item) * K;
+        const int Kb = K < BLOCK ? K : BLOCK;
+        const int nparts = BLOCK / Kb;
+        const int part = tid / Kb, kl = tid - part * Kb;
+        for (int k0 = 0; k0 < K; k0 += Kb) {
+            const int kk = k0 + kl;
+            double Nt = 0.0, Dt = 0.0;
+            if (part < nparts && kk < K) {
+                const double mu = mus[kk];
+                double N0 = 0.0, N1 = 0.0, D0 = 0.0, D1 = 0.0;
+                int i = part;
+                for (; i + nparts < n; i += 2 * nparts) {
+                    const double2 p0 = stage[i], p1 = stage[i + nparts];
+                    const double u0 = p0.x + mu, u1 = p1.x + mu;
+                    // one reciprocal for two terms: 1/u0 = u1 / (u0 u1), 1/u1 = u0 / (u0 u1)
+                    double rp = __builtin_amdgcn_rcp(u0 * u1);
+                    const double pr = u0 * u1;
+                    double e = fma(-pr, rp, 1.0);
+                    rp = fma(rp, e, rp);
+                    e = fma(-pr, rp, 1.0);
+                    rp = fma(rp, e, rp);
+                    const double r0 = u1 * rp, r1 = u0 * rp;
+                    D0 += r0;
+                    D1 += r1;
+                    N0 = fma(p0.y, r0 * r0, N0);
+                    N1 = fma(p1.y, r1 * r1, N1);
+                }
+                if (i < n) {
+                    const double2 p0 = stage[i];
+                    const double u0 = p0.x + mu;
+                    double r = __builtin_amdgcn_rcp(u0);
+                    double e = fma(-u0, r, 1.0);
+                    r = fma(r, e, r);
+                    e = fma(-u0, r, 1.0);
+                    r = fma(r, e, r);
+                    D0 += r;
+                    N0 = fma(p0.y, r * r, N0);
+                }
+                Nt = N0 + N1;
+                Dt = D0 + D1;
+            }
+            red[tid] = make_double2(Nt, Dt);
+            __syncthreads();
+            if (part == 0 && kk < K) {
+                double2 acc = red[kl];
+                for (int p = 1; p < nparts; ++p) {
+                    const double2 v = red[p * Kb + kl];
+                    acc.x += v.x;
+                    acc.y += v.y;
+                }
+                const double Gk = acc.x / (acc.y * acc.y);
+                Gs[kk] = Gk;
+                if (a.G) a.G[static_cast<int64_t>(sg.item) * K + kk] = Gk;
+            }
+            __syncthreads();
+        }
+        if (tid < 64) {  // first minimum; -1 if some G is not finite
+            double best = 0.0;
+            int bk = -1, bad = 0;
+            for (int k = tid; k < K; k += 64) {
+                const double gv = Gs[k];
+                if (!isfinite(gv)) bad = 1;
+                if (bk < 0 || gv < best) {
+                    best = gv;
+                    bk = k;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off, 64);
+                const int ok = __shfl_xor(bk, off, 64);
+                bad |= __shfl_xor(bad, off, 64);
+                if (ok >= 0 && (bk < 0 || ob < best || (ob == best && ok < bk))) {
+                    best = ob;
+                    bk = ok;
+                }
+            }
+            if (tid == 0) {
+                s_kbest = bad ? -1 : bk;
+                a.kbest[sg.item] = s_kbest;
+                a.mubest[sg.item] = bad ? __builtin_nan("") : mus[bk];
+            }
+        }
+        __syncthreads();
+        const int kb = s_kbest;
+        const double mu_s = kb >= 0 ? mus[kb] : __builtin_nan("");
+
+        // ---- Tikhonov filter at mu*: fhat = d ghat / (d^2 + mu s^2)
+#pragma unroll
+        for (int k = 0; k < SL; ++k) c[k] = dj[k] * c[k] / fma(mu_s, sj[k] * sj[k], dj[k] * dj[k]);
+        const double fpoly = z0 / fma(mu_s, s_poly * s_poly, z0 * z0);
+        const double fx1 = fpoly * x1, fxn = fpoly * xn;
+        if (tid < rank) bc[tid].x = c[0];
+        __syncthreads();
+        const double beta0 = rank > 0 ? bc[0].x : 0.0;
+        const double beta1 = rank > 1 ? bc[1].x : 0.0;
+
+        // ---- forward transform of the filtered coefficients
+        {
+            auto in_fwd = [&](int k, int j) { return make_double2(j >= rank ? c[k] : 0.0, 0.0); };
+            auto park = [&](int j, double2 y) { f[j + 1] = y.x; };
+            auto unpark = [&](int j) { return make_double2(f[j + 1], 0.0); };
+            double2 u[SL];
+            chirp_core<LOGP, S>(u, ax.syn, ax.syn.mode, N, lds, tw, in_fwd, park, unpark);
+#pragma unroll
+            for (int k = 0; k < SL; ++k) {
+                const int j = tid + k * BLOCK;
+                if (j < N) {
+                    double y = u[k].x + ax.q[j + 1] * fx1 + ax.q[N - j] * fxn;
+                    if (rank > 0) y += ax.bub[j] * beta0;
+                    if (rank > 1) y += ax.bub[N + j] * beta1;
+                    f[j + 1] = y;
+                    if (kind == HT_KIND_C) {
+                        if (j == 0) f[0] = q1 * fx1 + u[k].x;
+                        if (j == N - 1) f[n - 1] = q1 * fxn + u[k].x;
+                    }
+                }
+            }
+            if (tid == 0 && kind != HT_KIND_C) {
+                f[0] = q1 * fx1;
+                f[n - 1] = q1 * fxn;
+            }
+        }
+    }
+}
+
+}  // namespace ht
+
+using namespace ht;
+
+struct ht_batch {
+    int64_t count = 0;
+    int device = 0;
+    const double2* tw = nullptr;
+    void* arena = nullptr;          // axis tables
+    Axis* d_axes = nullptr;
+    RSig* d_sigs = nullptr;
+    int* d_counters = nullptr;
+    int64_t total_n = 0, total_psf = 0;
+    int class_start[NCLASS] = {0};
+    int class_count[NCLASS] = {0};
+    int grid[NCLASS] = {0};         // persistent workgroups per class (schedule)
+};
+
+namespace {
+
+template <int LOGP, int S>
+int max_active(int device) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_restore<LOGP, S>, fft_block_for(LOGP), 0) != hipSuccess)
+        nb = 1;
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
+    return std::max(1, nb) * cus;
+}
+
+int default_grid(int cls, int device) {
+    switch (cls) {
+        case 0: return max_active<9, 1>(device);
+        case 1: return max_active<10, 1>(device);
+        case 2: return max_active<11, 1>(device);
+        case 3: return max_active<12, 1>(device);
+        case 4: return max_active<13, 1>(device);
+        default: return max_active<13, 2>(device);
+    }
+}
+
+}  // namespace
+
+extern "C" ht_status ht_batch_create(int64_t count, const int64_t* n, const int* degree, const int* psf_symmetric,
+                                     int family, const int64_t* psf_len, const int64_t* psf_center, ht_batch** out) {
+    if (!out) return fail(HT_ERR_INVALID_ARG, "ht_batch_create: null output");
+    *out = nullptr;
+    if (count < 1 || count > (1LL << 24)) return fail(HT_ERR_INVALID_ARG, "ht_batch_create: count must be in [1, 2^24]");
+    if (!n || !degree || !psf_symmetric || !psf_len || !psf_center)
+        return fail(HT_ERR_INVALID_ARG, "ht_batch_create: null argument");
+    std::vector<int> kind(count);
+    for (int64_t b = 0; b < count; ++b) {
+        if (n[b] < 5 || n[b] > MAX_N) return fail(HT_ERR_INVALID_ARG, "ht_batch_create: n must be in [5, 8192]");
+        ht_status st;
+        kind[b] = resolve_kind(degree[b], psf_symmetric[b], family, &st);
+        if (st != HT_OK) return st;
+        if (kind[b] == HT_KIND_F)
+            return fail(HT_ERR_UNSUPPORTED, "ht_batch_create: ragged batches take symmetric PSFs (real transforms)");
+        const int64_t len = psf_len[b], c = psf_center[b];
+        if (len < 1 || c < 0 || c >= len) return fail(HT_ERR_INVALID_ARG, "ht_batch_create: bad PSF length or center");
+        const int64_t m = std::max(c, len - 1 - c);
+        if (2 * m + 1 > n[b] - 2) return fail(HT_ERR_PSF_TOO_WIDE, "ht_batch_create: PSF half-width m needs 2m+1 <= n-2");
+    }
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return fail(HT_ERR_HIP, "ht_batch_create: no HIP device");
+    ht_status st;
+    const double2* tw = device_twiddles(device, &st);
+    if (!tw) return st;
+
+    // distinct (n, kind) pairs share one set of tables
+    std::map<std::pair<int, int>, int> ids;
+    std::vector<std::pair<int, int>> keys;
+    std::vector<int> axis_of(count);
+    for (int64_t b = 0; b < count; ++b) {
+        const auto key = std::make_pair(static_cast<int>(n[b]), kind[b]);
+        auto it = ids.find(key);
+        if (it == ids.end()) {
+            it = ids.emplace(key, static_cast<int>(keys.size())).first;
+            keys.push_back(key);
+        }
+        axis_of[b] = it->second;
+    }
+    const int64_t nax = static_cast<int64_t>(keys.size());
+    std::vector<HostAxis> hs(nax);
+    std::vector<ht_status> status(nax, HT_OK);
+    {
+        std::atomic<int64_t> next(0);
+        const int nthr = std::max(1, std::min<int>(static_cast<int>(std::thread::hardware_concurrency()), 32));
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthr; ++t)
+            pool.emplace_back([&]() {
+                for (int64_t a = next++; a < nax; a = next++) status[a] = build_axis(keys[a].first, keys[a].second, hs[a]);
+            });
+        for (auto& th : pool) th.join();
+    }
+    for (int64_t a = 0; a < nax; ++a)
+        if (status[a] != HT_OK) return fail(status[a], "ht_batch_create: building the tables of a signal length failed");
+    ht_batch* bt = new (std::nothrow) ht_batch();
+    if (!bt) return fail(HT_ERR_OOM, "ht_batch_create: host allocation failed");
+    bt->count = count;
+    bt->device = device;
+    bt->tw = tw;
+    std::vector<Axis> axes(nax);
+    st = upload_axes(hs.data(), nax, &bt->arena, axes.data());
+    if (st != HT_OK) {
+        delete bt;
+        return st;
+    }
+    // signal descriptors grouped by size class, longest first within a class
+    std::vector<int64_t> off(count), poff(count);
+    int64_t acc = 0, pacc = 0;
+    for (int64_t b = 0; b < count; ++b) {
+        off[b] = acc;
+        poff[b] = pacc;
+        acc += n[b];
+        pacc += psf_len[b];
+    }
+    bt->total_n = acc;
+    bt->total_psf = pacc;
+    std::vector<RSig> sigs(count);
+    for (int64_t b = 0; b < count; ++b)
+        sigs[b] = RSig{off[b], poff[b], static_cast<int32_t>(psf_len[b]), static_cast<int32_t>(psf_center[b]),
+                       axis_of[b], static_cast<int32_t>(b)};
+    std::stable_sort(sigs.begin(), sigs.end(), [&](const RSig& x, const RSig& y) {
+        const int cx = class_of(axes[x.axis]), cy = class_of(axes[y.axis]);
+        if (cx != cy) return cx < cy;
+        return axes[x.axis].n > axes[y.axis].n;
+    });
+    for (int64_t i = 0; i < count; ++i) bt->class_count[class_of(axes[sigs[i].axis])]++;
+    for (int c = 1; c < NCLASS; ++c) bt->class_start[c] = bt->class_start[c - 1] + bt->class_count[c - 1];
+    for (int c = 0; c < NCLASS; ++c) bt->grid[c] = std::min(bt->class_count[c], default_grid(c, device));
+    bool ok = hipMalloc(&bt->d_axes, sizeof(Axis) * nax) == hipSuccess &&
+              hipMalloc(&bt->d_sigs, sizeof(RSig) * count) == hipSuccess &&
+              hipMalloc(&bt->d_counters, sizeof(int) * NCLASS) == hipSuccess;
+    ok = ok && hipMemcpy(bt->d_axes, axes.data(), sizeof(Axis) * nax, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(bt->d_sigs, sigs.data(), sizeof(RSig) * count, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        ht_batch_destroy(bt);
+        return fail(HT_ERR_OOM, "ht_batch_create: device allocation failed");
+    }
+    *out = bt;
+    return HT_OK;
+}
+
+extern "C" ht_status ht_batch_destroy(ht_batch* bt) {
+    if (!bt) return HT_OK;
+    if (bt->arena) hipFree(bt->arena);
+    if (bt->d_axes) hipFree(bt->d_axes);
+    if (bt->d_sigs) hipFree(bt->d_sigs);
+    if (bt->d_counters) hipFree(bt->d_counters);
+    delete bt;
+    return HT_OK;
+}
+
+extern "C" int64_t ht_batch_total_length(const ht_batch* bt) { return bt ? bt->total_n : -1; }
+extern "C" int64_t ht_batch_psf_total(const ht_batch* bt) { return bt ? bt->total_psf : -1; }
+
+extern "C" ht_status ht_batch_schedule(ht_batch* bt, int size_class, int workgroups, int* current) {
+    if (!bt || size_class < 0 || size_class >= NCLASS) return fail(HT_ERR_INVALID_ARG, "ht_batch_schedule: bad argument");
+    if (workgroups > 0) bt->grid[size_class] = std::max(1, std::min(workgroups, std::max(1, bt->class_count[size_class])));
+    if (current) *current = bt->grid[size_class];
+    return HT_OK;
+}
+
+extern "C" int ht_batch_class_count(const ht_batch* bt, int size_class) {
+    if (!bt || size_class < 0 || size_class >= NCLASS) return -1;
+    return bt->class_count[size_class];
+}
+
+extern "C" ht_status ht_batch_restore(const ht_batch* bt, const double* signal, const double* psf, int norm,
+                                      const double* mu_grid, int32_t K, double* restored, double* G,
+                                      int32_t* k_best, double* mu_best, hipStream_t stream) {
+    if (!bt) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore: null batch");
+    if (!signal || !psf || !mu_grid || !restored || !k_best || !mu_best)
+        return fail(HT_ERR_INVALID_ARG, "ht_batch_restore: null argument");
+    if (norm != HT_NORM_IDENTITY && norm != HT_NORM_SECOND_DIFF) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore: bad norm");
+    if (K < 1 || K > BATCH_MAX_K) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore: K must be in [1, 256]");
+    if (signal == restored) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore: signal and restored must not overlap");
+    RaggedArgs a{bt->d_axes, bt->d_sigs, bt->d_counters, signal, psf, mu_grid, K, norm, restored, G, k_best, mu_best};
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, stream, bt->d_counters);
+    ht_status st = check_hip(hipGetLastError(), "ht_batch_restore reset");
+    if (st != HT_OK) return st;
+    // largest class first: its signals dominate the run time
+    for (int c = NCLASS - 1; c >= 0; --c) {
+        const int cnt = bt->class_count[c];
+        if (cnt == 0) continue;
+        const dim3 grid(static_cast<unsigned>(bt->grid[c]));
+        const int start = bt->class_start[c];
+        switch (c) {
+            case 0: hipLaunchKernelGGL((k_restore<9, 1>), grid, dim3(fft_block_for(9)), 0, stream, a, c, start, cnt, bt->tw); break;
+            case 1: hipLaunchKernelGGL((k_restore<10, 1>), grid, dim3(fft_block_for(10)), 0, stream, a, c, start, cnt, bt->tw); break;
+            case 2: hipLaunchKernelGGL((k_restore<11, 1>), grid, dim3(fft_block_for(11)), 0, stream, a, c, start, cnt, bt->tw); break;
+            case 3: hipLaunchKernelGGL((k_restore<12, 1>), grid, dim3(fft_block_for(12)), 0, stream, a, c, start, cnt, bt->tw); break;
+            case 4: hipLaunchKernelGGL((k_restore<13, 1>), grid, dim3(fft_block_for(13)), 0, stream, a, c, start, cnt, bt->tw); break;
+            default: hipLaunchKernelGGL((k_restore<13, 2>), grid, dim3(fft_block_for(13)), 0, stream, a, c, start, cnt, bt->tw); break;
+        }
+        st = check_hip(hipGetLastError(), "ht_batch_restore launch");
+        if (st != HT_OK) return st;
+    }
+    return HT_OK;
+}

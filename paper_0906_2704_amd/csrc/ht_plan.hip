@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "ht_internal.h"
+#include "plan_build.h"
 
 namespace ht {
 
@@ -39,7 +40,6 @@ ht_status check_hip(hipError_t e, const char* what) {
     return fail(HT_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-using cd = std::complex<double>;
 using ld = long double;
 static const ld PI_L = 3.141592653589793238462643383279502884L;
 
@@ -108,11 +108,6 @@ static void host_fft(std::vector<cd>& x, int sign) {
         }
     }
 }
-
-struct HostChirp {
-    std::vector<cd> pre, post, B;
-    int mode = MODE_RE;
-};
 
 // Chirp-z form of the core transforms (0-based j, k < N):
 //   sum_j x_j w^{jk} = c_k sum_j (c_j x_j) conj(c_{k-j}),  c_m = w^{m^2/2}.
@@ -188,16 +183,10 @@ static std::vector<double> host_core(const HostChirp& hc, const std::vector<doub
 
 // ----------------------------------------------------------------------- axis tables
 
-struct HostAxis {
-    Axis ax{};
-    std::vector<double> q, bub, U, tcos, tsin;
-    HostChirp ana, syn;
-    int M = 0;
-};
-
-static int resolve_kind(int degree, int sym, int family, ht_status* st) {
+int resolve_kind(int degree, int sym, int family, ht_status* st) {
     *st = HT_OK;
-    if (family == HT_FAMILY_PAPER) {
+    if (family == HT_FAMILY_PAPER_DST3 && degree == 3) family = HT_FAMILY_DST;
+    if (family == HT_FAMILY_PAPER || family == HT_FAMILY_PAPER_DST3) {
         if (degree == 1) {
             if (!sym) *st = fail(HT_ERR_UNSUPPORTED, "degree 1 (antireflective) needs a symmetric PSF");
             return HT_KIND_AR;
@@ -220,7 +209,7 @@ static int resolve_kind(int degree, int sym, int family, ht_status* st) {
 
 static ld to_ld(int64_t num, int64_t den) { return static_cast<ld>(num) / static_cast<ld>(den); }
 
-static ht_status build_axis(int n, int kind, HostAxis& h) {
+ht_status build_axis(int n, int kind, HostAxis& h) {
     const int N = n - 2;
     Axis& a = h.ax;
     a.n = n;
@@ -326,16 +315,18 @@ static ht_status build_axis(int n, int kind, HostAxis& h) {
     return HT_OK;
 }
 
-// Upload the host tables of both axes into one device arena and fix up the pointers.
-static ht_status upload(ht_plan* p, HostAxis* hs, int nax) {
+// Upload the host tables of `nax` axes into one device arena and fill in the device
+// pointers of each Axis.
+ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* axes_out) {
     size_t bytes = 0;
     auto reserve = [&](size_t nbytes) {
         const size_t off = bytes;
         bytes += (nbytes + 255) & ~static_cast<size_t>(255);
         return off;
     };
-    struct Offs { size_t q, bub, U, tcos, tsin, apre, apost, aB, spre, spost, sB; } o[2];
-    for (int a = 0; a < nax; ++a) {
+    struct Offs { size_t q, bub, U, tcos, tsin, apre, apost, aB, spre, spost, sB; };
+    std::vector<Offs> o(nax);
+    for (int64_t a = 0; a < nax; ++a) {
         const HostAxis& h = hs[a];
         const size_t N = h.ax.N;
         o[a].q = reserve(sizeof(double) * h.q.size());
@@ -350,16 +341,20 @@ static ht_status upload(ht_plan* p, HostAxis* hs, int nax) {
         o[a].spost = reserve(sizeof(double2) * N);
         o[a].sB = reserve(sizeof(double2) * h.M);
     }
-    std::vector<char> host(bytes, 0);
+    std::vector<char> host;
+    try {
+        host.assign(bytes, 0);
+    } catch (...) {
+        return fail(HT_ERR_OOM, "host staging allocation failed");
+    }
     auto put = [&](size_t off, const void* src, size_t nb) {
         if (nb) std::memcpy(host.data() + off, src, nb);
     };
     auto putc = [&](size_t off, const std::vector<cd>& v) {
-        std::vector<double2> t(v.size());
-        for (size_t i = 0; i < v.size(); ++i) t[i] = make_double2(v[i].real(), v[i].imag());
-        put(off, t.data(), sizeof(double2) * t.size());
+        double2* dst = reinterpret_cast<double2*>(host.data() + off);
+        for (size_t i = 0; i < v.size(); ++i) dst[i] = make_double2(v[i].real(), v[i].imag());
     };
-    for (int a = 0; a < nax; ++a) {
+    for (int64_t a = 0; a < nax; ++a) {
         const HostAxis& h = hs[a];
         put(o[a].q, h.q.data(), sizeof(double) * h.q.size());
         put(o[a].bub, h.bub.data(), sizeof(double) * h.bub.size());
@@ -374,13 +369,13 @@ static ht_status upload(ht_plan* p, HostAxis* hs, int nax) {
         putc(o[a].sB, h.syn.B);
     }
     char* dev = nullptr;
-    if (hipMalloc(&dev, bytes) != hipSuccess) return fail(HT_ERR_OOM, "plan table allocation failed");
+    if (hipMalloc(&dev, bytes) != hipSuccess) return fail(HT_ERR_OOM, "table allocation failed");
     if (hipMemcpy(dev, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
         hipFree(dev);
-        return fail(HT_ERR_HIP, "plan table upload failed");
+        return fail(HT_ERR_HIP, "table upload failed");
     }
-    p->arena = dev;
-    for (int a = 0; a < nax; ++a) {
+    *arena_out = dev;
+    for (int64_t a = 0; a < nax; ++a) {
         Axis ax = hs[a].ax;
         ax.q = reinterpret_cast<const double*>(dev + o[a].q);
         ax.bub = reinterpret_cast<const double*>(dev + o[a].bub);
@@ -391,7 +386,7 @@ static ht_status upload(ht_plan* p, HostAxis* hs, int nax) {
                        reinterpret_cast<const double2*>(dev + o[a].aB), hs[a].ana.mode};
         ax.syn = Chirp{reinterpret_cast<const double2*>(dev + o[a].spre), reinterpret_cast<const double2*>(dev + o[a].spost),
                        reinterpret_cast<const double2*>(dev + o[a].sB), hs[a].syn.mode};
-        p->ax[a] = ax;
+        axes_out[a] = ax;
     }
     return HT_OK;
 }
@@ -428,7 +423,7 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
     p->tw = tw;
     p->cplx = kind == HT_KIND_F ? 1 : 0;
     p->max_batch = ndim == 2 ? max_batch : 1;
-    st = upload(p, hs, ndim);
+    st = upload_axes(hs, ndim, &p->arena, p->ax);
     if (st != HT_OK) {
         delete p;
         return st;

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View i
         xn = cscale(yL, inv);
     }
     // interior correction r_j = y_{j+1} - q^_j x_1 - (J q^)_j x_n, then the core analysis
-    auto in_fn = [&](int j) {
+    auto in_fn = [&](int, int j) {
         double2 r = vload(in, ib, j + 1);
         const double qa = ax.q[j + 1], qb = ax.q[N - j];
         r.x = r.x - qa * x1.x - qb * xn.x;
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View i
     const double2 beta0 = ax.rank > 0 ? vload(in, ib, 1) : make_double2(0.0, 0.0);
     const double2 beta1 = ax.rank > 1 ? vload(in, ib, 2) : make_double2(0.0, 0.0);
     // the replaced (bubble) columns are added explicitly, not through the sine core
-    auto in_fn = [&](int j) { return j >= ax.rank ? vload(in, ib, j + 1) : make_double2(0.0, 0.0); };
+    auto in_fn = [&](int, int j) { return j >= ax.rank ? vload(in, ib, j + 1) : make_double2(0.0, 0.0); };
     auto park = [&](int j, double2 y) { vstore(out, ob, j + 1, y); };
     auto unpark = [&](int j) { return vload(out, ob, j + 1); };
     const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ax.syn.mode;

@@ -18,7 +18,7 @@ HT_FAMILY_PAPER, HT_FAMILY_DST = 0, 1
 HT_NORM_IDENTITY, HT_NORM_SECOND_DIFF = 0, 1
 KIND_NAMES = {1: "AR", 2: "C", 3: "F", 4: "DST2", 5: "DST3"}
 NORMS = {"I": HT_NORM_IDENTITY, "D2": HT_NORM_SECOND_DIFF}
-FAMILIES = {"paper": HT_FAMILY_PAPER, "dst": HT_FAMILY_DST}
+FAMILIES = {"paper": HT_FAMILY_PAPER, "dst": HT_FAMILY_DST, "paper+dst3": 2}
 
 _lib = None
 
@@ -196,3 +196,98 @@ def _item(plan):
     for v in plan.n:
         out *= v
     return out
+
+
+def _batch_sigs(L):
+    P, I64, I32, VP = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+    L.ht_batch_create.argtypes = [I64, VP, VP, VP, ctypes.c_int, VP, VP, ctypes.POINTER(P)]
+    L.ht_batch_create.restype = ctypes.c_int
+    L.ht_batch_destroy.argtypes = [P]
+    L.ht_batch_destroy.restype = ctypes.c_int
+    L.ht_batch_total_length.argtypes = [P]
+    L.ht_batch_total_length.restype = I64
+    L.ht_batch_psf_total.argtypes = [P]
+    L.ht_batch_psf_total.restype = I64
+    L.ht_batch_restore.argtypes = [P, VP, VP, ctypes.c_int, VP, I32, VP, VP, VP, VP, VP]
+    L.ht_batch_restore.restype = ctypes.c_int
+    L.ht_batch_schedule.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.ht_batch_schedule.restype = ctypes.c_int
+    L.ht_batch_class_count.argtypes = [P, ctypes.c_int]
+    L.ht_batch_class_count.restype = ctypes.c_int
+
+
+NCLASS = 6
+
+
+class Batch:
+    """A ragged batch (ht_batch_create).  All arguments are host sequences of length count."""
+
+    def __init__(self, n, degree, psf_len, psf_center, psf_symmetric=None, family="paper+dst3"):
+        import numpy as np
+        L = lib()
+        if not hasattr(L, "_batch_ready"):
+            _batch_sigs(L)
+            L._batch_ready = True
+        count = len(n)
+        self.count = count
+        self.n = np.asarray(n, dtype=np.int64)
+        self._keep = [np.ascontiguousarray(n, dtype=np.int64), np.ascontiguousarray(degree, dtype=np.int32),
+                      np.ascontiguousarray(np.ones(count) if psf_symmetric is None else psf_symmetric,
+                                           dtype=np.int32),
+                      np.ascontiguousarray(psf_len, dtype=np.int64), np.ascontiguousarray(psf_center, dtype=np.int64)]
+        h = ctypes.c_void_p()
+        k = self._keep
+        _check(L.ht_batch_create(count, k[0].ctypes.data, k[1].ctypes.data, k[2].ctypes.data,
+                                 FAMILIES.get(family, family), k[3].ctypes.data, k[4].ctypes.data, ctypes.byref(h)),
+               "ht_batch_create")
+        self._h = h
+        self.total_length = int(L.ht_batch_total_length(h))
+        self.psf_total = int(L.ht_batch_psf_total(h))
+        self.offsets = np.concatenate([[0], np.cumsum(self.n)]).astype(np.int64)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().ht_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def schedule(self, size_class, workgroups=0):
+        cur = ctypes.c_int()
+        _check(lib().ht_batch_schedule(self._h, int(size_class), int(workgroups), ctypes.byref(cur)),
+               "ht_batch_schedule")
+        return cur.value
+
+    def class_count(self, size_class):
+        return int(lib().ht_batch_class_count(self._h, int(size_class)))
+
+
+def ht_batch_restore(batch, signal, psf, norm, mu_grid, restored=None, G=None, kb=None, mb=None, want_G=True):
+    """Returns (restored, G or None, k_best, mu_best)."""
+    L = lib()
+    dev = signal.device
+    K = mu_grid.shape[-1]
+    if restored is None:
+        restored = torch.empty(batch.total_length, dtype=torch.float64, device=dev)
+    if G is None and want_G:
+        G = torch.empty((batch.count, K), dtype=torch.float64, device=dev)
+    if kb is None:
+        kb = torch.empty(batch.count, dtype=torch.int32, device=dev)
+    if mb is None:
+        mb = torch.empty(batch.count, dtype=torch.float64, device=dev)
+    if signal.numel() != batch.total_length or psf.numel() != batch.psf_total or mu_grid.numel() != batch.count * K:
+        raise HTError("ht_batch_restore: array sizes do not match the batch")
+    _check(L.ht_batch_restore(batch.handle, _ptr(signal, torch.float64, "signal"), _ptr(psf, torch.float64, "psf"),
+                              NORMS.get(norm, norm), _ptr(mu_grid, torch.float64, "mu_grid"), int(K),
+                              _ptr(restored, torch.float64, "restored"), _ptr(G, torch.float64, "G"),
+                              _ptr(kb, torch.int32, "k_best"), _ptr(mb, torch.float64, "mu_best"), _stream()),
+           "ht_batch_restore")
+    return restored, G, kb, mb
