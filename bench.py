@@ -105,6 +105,10 @@ class Uniform1D:
         ht.ht_transform_fwd(self.plan, self.fhat, out=self.f)
         t.mark()
 
+    def config(self):
+        return {"workload": self.name, "batch": self.batch, "n": self.n, "kind": self.kind, "norm": "D2",
+                "K": len(self.mus_host)}
+
     def work(self):
         """Algorithmic bytes / flops per launch of each stage."""
         B, n, K = self.batch, self.n, len(self.mus_host)
@@ -153,6 +157,154 @@ class Uniform1D:
         return done / el, "first %d of the %d signals, one at a time" % (done, self.batch)
 
 
+class Ragged1D:
+    """The batched workload: 4096 signals, n ~ U{128..8192}, Gaussian (sigma = m/3) or box
+    PSF with half-width m ~ U{2..32}, noise 0.1-5%, boundary degree ~ U{1,2,3} (degree 1:
+    antireflective, 2: T_C, 3: DST extension), second-difference norm, a 128-point mu
+    grid per signal on [10^lo, 10^(lo+7)], lo ~ U(-8,-6); one hipGraph replay per step."""
+
+    stages = ["batch_restore"]
+    profile = "k_restore_ragged4096.md"
+
+    def __init__(self, torch, ht, synth, batch, graph=True, autotune=True):
+        self.torch, self.ht, self.synth = torch, ht, synth
+        self.batch = batch
+        self.graph = graph
+        self.autotune = autotune
+        self.name = "1d_ragged_n128-8192_d123_K128_x%d" % batch
+        self.n = None
+        self.kind = "AR/C/DST3"
+
+    def setup(self):
+        torch, ht, synth = self.torch, self.ht, self.synth
+        rb = synth.ragged_batch(self.batch)
+        self.rb = rb
+        self.K = rb.mus.shape[1]
+        dev = "cuda"
+        self.bt = ht.Batch(rb.n, rb.degree, np.diff(rb.psf_offsets), rb.psf_center)
+        self.g = torch.tensor(rb.g, device=dev)
+        self.psf = torch.tensor(rb.psf_flat, device=dev)
+        self.mus = torch.tensor(rb.mus, device=dev)
+        self.f = torch.empty_like(self.g)
+        self.Gv = torch.empty((self.batch, self.K), dtype=torch.float64, device=dev)
+        self.kb = torch.empty(self.batch, dtype=torch.int32, device=dev)
+        self.mb = torch.empty(self.batch, dtype=torch.float64, device=dev)
+        self.tuning = None
+        if self.autotune:
+            from paper_0906_2704_amd import autotune
+            choice, ms = autotune.tune(self.bt, self._launch, use_cache=False,
+                                       log=lambda m: print(m, file=sys.stderr, flush=True))
+            self.tuning = {"choice": {str(c): list(v) for c, v in choice.items()},
+                           "class_ms": {str(c): round(t, 4) for c, t in ms.items()}}
+        self.cuda_graph = None
+        if self.graph:
+            self._launch()  # eager warm-up outside the capture
+            torch.cuda.synchronize()
+            self.cuda_graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.cuda_graph):
+                self._launch()
+            torch.cuda.synchronize()
+
+    def _launch(self):
+        self.ht.ht_batch_restore(self.bt, self.g, self.psf, "D2", self.mus, restored=self.f, G=self.Gv,
+                                 kb=self.kb, mb=self.mb)
+
+    def step(self, t):
+        t.start_step()
+        if self.cuda_graph is not None:
+            self.cuda_graph.replay()
+        else:
+            self._launch()
+        t.mark()
+
+    def config(self):
+        return {"workload": self.name, "batch": self.batch, "n": "U{128..8192}", "sum_n": int(self.rb.n.sum()),
+                "degree": "U{1,2,3}", "norm": "D2", "K": self.K, "graph": self.graph, "schedule": self.tuning}
+
+    def work(self):
+        n = self.rb.n.astype(np.float64)
+        pairs = float(np.sum(n)) * self.K
+        return {"batch_restore": ("alu", pairs * GCV_FLOPS_PER_PAIR)}
+
+    def kind_of(self, b):
+        return {1: "AR", 2: "C", 3: "DST3"}[int(self.rb.degree[b])]
+
+    def sample_items(self, count):
+        order = np.argsort(self.rb.n)
+        return [int(order[int(q)]) for q in np.linspace(0, self.batch - 1, count)]
+
+    def check(self):
+        from oracle import tikhonov as tk
+        from oracle import transforms as tr
+        f = self.f.cpu().numpy()
+        kb = self.kb.cpu().numpy()
+        worst = 0.0
+        for b in self.sample_items(4)[:3]:
+            kind = self.kind_of(b)
+            n = int(self.rb.n[b])
+            h, c = self.rb.psf[b]
+            g = self.rb.g[self.rb.offsets[b]:self.rb.offsets[b + 1]]
+            d = tr.blur_eigs(kind, n, h, c)
+            s = tr.smooth_eigs(kind, n, "D2")
+            gw = tr.inverse(kind, g)
+            _, kw, muw = tk.gcv_scan(gw, d, s, self.rb.mus[b])
+            assert kw == kb[b], (b, kw, kb[b])
+            fw = tr.forward(kind, tk.tikhonov_filter(gw, d, s, muw)).real
+            fb = f[self.rb.offsets[b]:self.rb.offsets[b + 1]]
+            worst = max(worst, float(np.max(np.abs(fb - fw)) / np.max(np.abs(fw))))
+        return worst
+
+    def cpu_baseline(self, budget_s):
+        from oracle import tikhonov as tk
+        from oracle import transforms as tr
+        t0 = time.perf_counter()
+        done = []
+        for b in self.sample_items(64):
+            if time.perf_counter() - t0 > budget_s:
+                break
+            kind = self.kind_of(b)
+            n = int(self.rb.n[b])
+            h, c = self.rb.psf[b]
+            g = self.rb.g[self.rb.offsets[b]:self.rb.offsets[b + 1]]
+            d = tr.blur_eigs(kind, n, h, c)
+            s = tr.smooth_eigs(kind, n, "D2")
+            gw = tr.inverse(kind, g)
+            _, _, muw = tk.gcv_scan(gw, d, s, self.rb.mus[b])
+            tr.forward(kind, tk.tikhonov_filter(gw, d, s, muw))
+            done.append(n)
+        el = time.perf_counter() - t0
+        return len(done) / el, ("%d signals at evenly spaced quantiles of n (n = %d..%d, mean %d; batch mean %d), "
+                                "one at a time, tables built inside the timing"
+                                % (len(done), min(done), max(done), int(np.mean(done)), int(np.mean(self.rb.n))))
+
+
+def csrc_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_0906_2704_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(profile):
+    """HBM bytes per step from a committed rocprofv3 counter summary, if it was taken on
+    the kernels as they are now (same source hash); otherwise None."""
+    path = os.path.join(ROOT, "profiles", profile)
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    import re
+    mh = re.search(r"csrc_sha256=([0-9a-f]+)", text)
+    mt = re.search(r"TRAFFIC_BYTES_PER_STEP=([0-9.]+)", text)
+    if not mh or not mt or mh.group(1) != csrc_hash():
+        return None
+    return float(mt.group(1))
+
+
 def blas_threads():
     try:
         import threadpoolctl
@@ -169,11 +321,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="uniform", choices=["uniform"])
-    ap.add_argument("--batch", type=int, default=65536)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--workload", default="ragged", choices=["ragged", "uniform"])
+    ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device copy of this size (MiB) before timing, for HBM counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -184,9 +340,20 @@ def main():
     from paper_0906_2704_amd import ht, synth
 
     ht.lib()
-    wl = Uniform1D(torch, ht, synth, args.batch)
+    if args.workload == "ragged":
+        wl = Ragged1D(torch, ht, synth, args.batch or 4096, graph=not args.no_graph, autotune=not args.no_autotune)
+    else:
+        wl = Uniform1D(torch, ht, synth, args.batch or 65536)
     print("setup %s" % wl.name, file=sys.stderr, flush=True)
     wl.setup()
+    if args.copy_calibration_mib > 0:
+        nel = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     timer = StageTimer(torch, wl.stages)
     for _ in range(args.warmup):
         wl.step(timer)
@@ -219,7 +386,7 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": amount / sec / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = profiled_traffic(wl.profile) if getattr(wl, "profile", None) else None
     roof["kernel"] = dom
 
     cpu = None
@@ -240,8 +407,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "batch": wl.batch, "n": wl.n, "kind": wl.kind,
-                   "norm": "D2", "K": len(wl.mus_host)},
+        "config": wl.config(),
         "stages_ms": stage_ms,
         "parity_max_rel_err": err,
         "roofline": roof,

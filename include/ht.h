@@ -171,10 +171,18 @@ ht_status ht_batch_restore(const ht_batch* batch, const double* signal, const do
                            int norm, const double* mu_grid, int32_t K, double* restored,
                            double* G, int32_t* k_best, double* mu_best, hipStream_t stream);
 
-/* Schedule knob (used by the autotuner): number of persistent workgroups of size class
- * `size_class` (0..5: FFT lengths 512, 1024, 2048, 4096, 8192, 2 x 8192).  workgroups <= 0
- * only queries.  *current (may be NULL) receives the value in effect.               */
-ht_status ht_batch_schedule(ht_batch* batch, int size_class, int workgroups, int* current);
+/* Schedule knobs (set by the autotuner) of size class `size_class` (0..5: FFT lengths
+ * 512, 1024, 2048, 4096, 8192, 2 x 8192): the number of persistent workgroups (<= 0:
+ * unchanged; capped at the class size, and at 1024 for class 5) and the kernel variant
+ * (-1: unchanged; 0: 8 points per thread, 1: 16 points per thread, classes 3..5 only).
+ * The values in effect are returned through the non-NULL pointers.  Results do not depend
+ * on the schedule.                                                                   */
+ht_status ht_batch_schedule(ht_batch* batch, int size_class, int workgroups, int variant,
+                            int* cur_workgroups, int* cur_variant);
+/* Tuning aid: restrict ht_batch_restore to the size classes whose bit is set in `mask`
+ * (bit c = class c; default all six).  Signals of the other classes are left untouched.
+ * Used to time one class at a time; a batch used for results keeps the full mask.     */
+ht_status ht_batch_class_mask(ht_batch* batch, unsigned mask);
 /* number of signals in a size class, or -1 */
 int ht_batch_class_count(const ht_batch* batch, int size_class);
 

@@ -23,13 +23,12 @@ __device__ __forceinline__ double2 select_out(double2 y, int mode) {
 
 // in(k, j) returns x_j for the slot k holding j = tid + k * BLOCK < N; the result goes to
 // out[k].
-// The workgroup has fft_block_for(LOGP) threads.
-template <int LOGP, int S, class In, class Park, class Unpark>
-__device__ __forceinline__ void chirp_core(double2 (&out)[fft_slots_for(LOGP)], const Chirp& ch, int mode, int N,
+// The workgroup has 2^LOGP / SL threads.
+template <int LOGP, int S, int SL, class In, class Park, class Unpark>
+__device__ __forceinline__ void chirp_core(double2 (&out)[SL], const Chirp& ch, int mode, int N,
                                            double2* lds, const double2* __restrict__ tw, In in,
                                            Park park, Unpark unpark) {
-    constexpr int SL = fft_slots_for(LOGP);
-    constexpr int BLOCK = fft_block_for(LOGP);
+    constexpr int BLOCK = (1 << LOGP) / SL;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -37,24 +36,24 @@ __device__ __forceinline__ void chirp_core(double2 (&out)[fft_slots_for(LOGP)], 
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
             const int j = tid + k * BLOCK;
-            v[k] = j < N ? cmul(in(k, j), ch.pre[j]) : make_double2(0.0, 0.0);
-            if (s == 1) v[k] = cmul(v[k], tw[j]);  // exp(-2 pi i j / M)
+            v[k] = j < N ? cmul(in(k, j), tload(ch.pre, j)) : make_double2(0.0, 0.0);
+            if (s == 1) v[k] = cmul(v[k], tload(tw, j));  // exp(-2 pi i j / M)
         }
         __builtin_amdgcn_sched_barrier(0);
-        fft_slots<LOGP, -1>(v, lds, tw);
+        fft_slots<LOGP, -1, SL>(v, lds, tw);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int k = 0; k < SL; ++k) v[k] = cmul(v[k], ch.B[S * (tid + k * BLOCK) + s]);
+        for (int k = 0; k < SL; ++k) v[k] = cmul(v[k], tload(ch.B, static_cast<unsigned>(S * (tid + k * BLOCK) + s)));
         __builtin_amdgcn_sched_barrier(0);
-        fft_slots<LOGP, 1>(v, lds, tw);
+        fft_slots<LOGP, 1, SL>(v, lds, tw);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
             const int j = tid + k * BLOCK;
             if (j < N) {
                 double2 c = v[k];
-                if (s == 1) c = cmulc(c, tw[j]);  // exp(+2 pi i j / M)
-                const double2 y = select_out(cmul(c, ch.post[j]), mode);
+                if (s == 1) c = cmulc(c, tload(tw, j));  // exp(+2 pi i j / M)
+                const double2 y = select_out(cmul(c, tload(ch.post, j)), mode);
                 if (S == 2 && s == 0)
                     park(j, y);
                 else if (S == 2)

@@ -28,6 +28,12 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
 }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
+// Table read with a 32-bit unsigned element index: lets the compiler address the table
+// as scalar base + 32-bit lane offset instead of a 64-bit address per lane.
+__device__ __forceinline__ double2 tload(const double2* __restrict__ base, unsigned idx) {
+    return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + (idx << 4));
+}
+
 // multiply by exp(DIR * i pi / 2): -i for the forward direction, +i for the inverse
 template <int DIR>
 __device__ __forceinline__ double2 rot90(double2 a) {
@@ -94,8 +100,9 @@ __device__ __forceinline__ void dftR<8, 1>(double2 (&u)[8]) { dft8<1>(u); }
 __host__ __device__ constexpr int fft_slots_for(int logp) { return logp >= 13 ? 16 : 8; }
 __host__ __device__ constexpr int fft_block_for(int logp) { return (1 << logp) / fft_slots_for(logp); }
 
-// One Stockham pass of radix R with Ns = product of the radices of earlier passes.
-template <int R, int DIR, int BLOCK, int SLOTS, bool FIRST, bool LAST>
+// One Stockham pass of radix R with Ns = product of the radices of earlier passes (Ns = 1:
+// no twiddles).  LAST: the outputs stay in the thread's own slots.
+template <int R, int DIR, int BLOCK, int SLOTS, bool LAST>
 __device__ __forceinline__ void stockham_pass(double2 (&v)[SLOTS], double2* lds,
                                               const double2* __restrict__ tw, int Ns) {
     constexpr int C = SLOTS / R;  // butterflies per thread
@@ -107,21 +114,21 @@ __device__ __forceinline__ void stockham_pass(double2 (&v)[SLOTS], double2* lds,
 #pragma unroll
         for (int r = 0; r < R; ++r) u[r] = v[c + r * C];
         const int k = t & (Ns - 1);
-        if (!FIRST) {
+        if (Ns > 1) {
             // w^r, r = 1..R-1, w = exp(-2 pi i k / (Ns R)): powers 1, 2, 4 from the table,
             // the others as products of two of them (a few ulp, far below the tolerance)
-            const int step = (TWN / (Ns * R)) * k;
-            const double2 w1 = tw[step];
+            const unsigned step = static_cast<unsigned>((TWN / R) / Ns * k);
+            const double2 w1 = tload(tw, step);
             if constexpr (R == 2) {
                 u[1] = DIR < 0 ? cmul(u[1], w1) : cmulc(u[1], w1);
             } else {
-                const double2 w2 = tw[2 * step];
+                const double2 w2 = tload(tw, 2u * step);
                 u[1] = DIR < 0 ? cmul(u[1], w1) : cmulc(u[1], w1);
                 u[2] = DIR < 0 ? cmul(u[2], w2) : cmulc(u[2], w2);
                 const double2 w3 = cmul(w1, w2);
                 u[3] = DIR < 0 ? cmul(u[3], w3) : cmulc(u[3], w3);
                 if constexpr (R == 8) {
-                    const double2 w4 = tw[4 * step];
+                    const double2 w4 = tload(tw, 4u * step);
                     u[4] = DIR < 0 ? cmul(u[4], w4) : cmulc(u[4], w4);
                     const double2 w5 = cmul(w1, w4);
                     u[5] = DIR < 0 ? cmul(u[5], w5) : cmulc(u[5], w5);
@@ -141,8 +148,6 @@ __device__ __forceinline__ void stockham_pass(double2 (&v)[SLOTS], double2* lds,
 #pragma unroll
             for (int r = 0; r < R; ++r) lds[base + r * Ns] = u[r];
         }
-        // one butterfly at a time: keeps the live registers to one butterfly's worth
-        if (C > 1 && SLOTS > 8) __builtin_amdgcn_sched_barrier(0);
     }
     if (!LAST) {
         __syncthreads();
@@ -152,30 +157,28 @@ __device__ __forceinline__ void stockham_pass(double2 (&v)[SLOTS], double2* lds,
     }
 }
 
-// Full FFT of length P = 2^LOGP on the slots v (natural order in, natural order out).
-template <int LOGP, int DIR>
-__device__ __forceinline__ void fft_slots(double2 (&v)[fft_slots_for(LOGP)], double2* lds,
-                                          const double2* __restrict__ tw) {
-    constexpr int SL = fft_slots_for(LOGP);
-    constexpr int BL = fft_block_for(LOGP);
+
+// Full FFT of length P = 2^LOGP on the slots v (natural order in, natural order out),
+// SL points per thread, P / SL threads.  The radix-8 passes run as a loop that is not
+// unrolled, so only one pass's addresses are live at a time.
+template <int LOGP, int DIR, int SL = fft_slots_for(LOGP)>
+__device__ __forceinline__ void fft_slots(double2 (&v)[SL], double2* lds, const double2* __restrict__ tw) {
+    constexpr int BL = (1 << LOGP) / SL;
+    static_assert(SL == 8 || SL == 16, "8 or 16 points per thread");
+    static_assert(LOGP >= 9 && LOGP <= 13, "FFT length out of range");
     constexpr int NR8 = LOGP / 3;
     constexpr int REM = LOGP % 3;
-    static_assert(LOGP >= 9 && LOGP <= 13, "FFT length out of range");
-    stockham_pass<8, DIR, BL, SL, true, false>(v, lds, tw, 1);
-    stockham_pass<8, DIR, BL, SL, false, false>(v, lds, tw, 8);
-    if constexpr (NR8 == 3 && REM == 0) {
-        stockham_pass<8, DIR, BL, SL, false, true>(v, lds, tw, 64);
-    } else {
-        stockham_pass<8, DIR, BL, SL, false, false>(v, lds, tw, 64);
-        if constexpr (NR8 == 4 && REM == 0) {
-            stockham_pass<8, DIR, BL, SL, false, true>(v, lds, tw, 512);
-        } else if constexpr (NR8 == 3) {
-            stockham_pass<(1 << REM), DIR, BL, SL, false, true>(v, lds, tw, 512);
-        } else {  // NR8 == 4, REM == 1 (P = 8192)
-            stockham_pass<8, DIR, BL, SL, false, false>(v, lds, tw, 512);
-            stockham_pass<2, DIR, BL, SL, false, true>(v, lds, tw, 4096);
-        }
+    constexpr int NMID = REM ? NR8 : NR8 - 1;  // radix-8 passes that go through LDS
+    int Ns = 1;
+#pragma unroll 1
+    for (int p = 0; p < NMID; ++p) {
+        stockham_pass<8, DIR, BL, SL, false>(v, lds, tw, Ns);
+        Ns *= 8;
     }
+    if constexpr (REM == 0)
+        stockham_pass<8, DIR, BL, SL, true>(v, lds, tw, Ns);
+    else
+        stockham_pass<(1 << REM), DIR, BL, SL, true>(v, lds, tw, Ns);
 }
 
 }  // namespace ht

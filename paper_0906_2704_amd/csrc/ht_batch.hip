@@ -49,6 +49,7 @@ struct RaggedArgs {
     double* G;
     int32_t* kbest;
     double* mubest;
+    double* scratch;    // MAX_N doubles per persistent workgroup of the split class
 };
 
 static int class_of(const Axis& a) { return a.S == 2 ? 5 : a.logP - MIN_LOGP; }
@@ -57,26 +58,92 @@ __global__ void k_reset_counters(int* c) {
     if (threadIdx.x < NCLASS) c[threadIdx.x] = 0;
 }
 
-template <int LOGP, int S>
-__global__ __launch_bounds__(fft_block_for(LOGP)) void k_restore(RaggedArgs a, int cls, int start, int count,
-                                                                 const double2* __restrict__ tw) {
+// 1/u to full float64 accuracy: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rcp_nr(double u) {
+    double r = __builtin_amdgcn_rcp(u);
+    double e = fma(-u, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-u, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Partial GCV sums of two grid values mu_a, mu_b over the staged elements
+// i = part, part + nparts, ... < n.  Two elements share one reciprocal:
+// 1/u0 = u1 / (u0 u1), 1/u1 = u0 / (u0 u1) (u >= mu > 0, the staged t are < 1e150).
+__device__ __forceinline__ void gcv_two(const double2* stage, int n, int part, int nparts, double mua, double mub,
+                                        double& Na, double& Da, double& Nb, double& Db) {
+    double na0 = 0.0, na1 = 0.0, da0 = 0.0, da1 = 0.0;
+    double nb0 = 0.0, nb1 = 0.0, db0 = 0.0, db1 = 0.0;
+    int i = part;
+    for (; i + nparts < n; i += 2 * nparts) {
+        const double2 p0 = stage[i], p1 = stage[i + nparts];
+        const double ua0 = p0.x + mua, ua1 = p1.x + mua;
+        const double ub0 = p0.x + mub, ub1 = p1.x + mub;
+        const double ra = rcp_nr(ua0 * ua1), rb = rcp_nr(ub0 * ub1);
+        const double ra0 = ua1 * ra, ra1 = ua0 * ra, rb0 = ub1 * rb, rb1 = ub0 * rb;
+        da0 += ra0;
+        da1 += ra1;
+        db0 += rb0;
+        db1 += rb1;
+        na0 = fma(p0.y, ra0 * ra0, na0);
+        na1 = fma(p1.y, ra1 * ra1, na1);
+        nb0 = fma(p0.y, rb0 * rb0, nb0);
+        nb1 = fma(p1.y, rb1 * rb1, nb1);
+    }
+    if (i < n) {
+        const double2 p0 = stage[i];
+        const double ra = rcp_nr(p0.x + mua), rb = rcp_nr(p0.x + mub);
+        da0 += ra;
+        db0 += rb;
+        na0 = fma(p0.y, ra * ra, na0);
+        nb0 = fma(p0.y, rb * rb, nb0);
+    }
+    Na = na0 + na1;
+    Da = da0 + da1;
+    Nb = nb0 + nb1;
+    Db = db0 + db1;
+}
+
+// Copy a record that every lane reads at the same address into scalar registers: each
+// 32-bit word goes through readfirstlane, so the compiler knows the fields (sizes, table
+// pointers) are wave-uniform and addresses tables as scalar base + lane offset.
+template <class T>
+__device__ __forceinline__ T uniform_load(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "record must be a whole number of words");
+    T out;
+    const int* src = reinterpret_cast<const int*>(p);
+    int* dst = reinterpret_cast<int*>(&out);
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return out;
+}
+
+template <int LOGP, int S, int SL>
+__global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int cls, int start, int count) {
     constexpr int P = 1 << LOGP;
-    constexpr int SL = fft_slots_for(LOGP);
-    constexpr int BLOCK = fft_block_for(LOGP);
+    constexpr int BLOCK = P / SL;
+    // cross-part GCV reduction buffer: only 64-thread groups can need more than one pass
+    // over the grid (K > 2 * BLOCK); otherwise the reduction reuses the staging buffer
+    constexpr int RED = BLOCK < BATCH_MAX_K / 2 ? 2 * BLOCK : 1;
     __shared__ double2 lds[P];
-    __shared__ double2 red[BLOCK];
+    __shared__ double2 red_small[RED];
     __shared__ double Gs[BATCH_MAX_K];
     __shared__ double2 bc[3];
     __shared__ int s_item, s_kbest;
     const int tid = threadIdx.x;
+    double* scratch = a.scratch + static_cast<int64_t>(blockIdx.x) * MAX_N;
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&a.counters[cls], 1);
         __syncthreads();
-        const int qi = s_item;
+        // uniform across the workgroup: keeps the signal's descriptor and table pointers in
+        // scalar registers
+        const int qi = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (qi >= count) break;
-        const RSig sg = a.sigs[start + qi];
-        const Axis& ax = a.axes[sg.axis];
+        const RSig sg = uniform_load(a.sigs + start + qi);
+        const Axis ax = uniform_load(a.axes + sg.axis);
+        // read per signal so that no twiddle address is hoisted out of the queue loop
+        const double2* __restrict__ tw = ax.tw;
         const int n = ax.n, N = ax.N, rank = ax.rank, kind = ax.kind, den = ax.den;
         const double* g = a.g + sg.off;
         double* f = a.f + sg.off;
@@ -104,7 +171,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_restore(RaggedArgs a, i
             auto park = [&](int j, double2 y) { f[j + 1] = y.x; };
             auto unpark = [&](int j) { return make_double2(f[j + 1], 0.0); };
             double2 out[SL];
-            chirp_core<LOGP, S>(out, ax.ana, ax.ana.mode, N, lds, tw, in_inv, park, unpark);
+            chirp_core<LOGP, S, SL>(out, ax.ana, ax.ana.mode, N, lds, tw, in_inv, park, unpark);
 #pragma unroll
             for (int k = 0; k < SL; ++k) c[k] = out[k].x;
         }
@@ -124,6 +191,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_restore(RaggedArgs a, i
             }
         }
 
+        __builtin_amdgcn_sched_barrier(0);
         // ---- eigenvalues on the signal's grid: cos(pi r / den), r <= den, staged in LDS
         double* ctab = reinterpret_cast<double*>(lds);
         __syncthreads();
@@ -172,6 +240,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_restore(RaggedArgs a, i
         }
         __syncthreads();
 
+        __builtin_amdgcn_sched_barrier(0);
         // ---- GCV: stage t_i = |d_i|^2 / |s_i|^2, w_i = |ghat_i|^2 (s_i = 0: no contribution)
         double2* stage = lds;
 #pragma unroll
@@ -190,58 +259,39 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_restore(RaggedArgs a, i
         __syncthreads();
         const int K = a.K;
         const double* mus = a.mus + static_cast<int64_t>(sg.item) * K;
-        const int Kb = K < BLOCK ? K : BLOCK;
+        const int Kh = (K + 1) / 2;  // two grid values per thread
+        const int Kb = Kh < BLOCK ? Kh : BLOCK;
         const int nparts = BLOCK / Kb;
         const int part = tid / Kb, kl = tid - part * Kb;
-        for (int k0 = 0; k0 < K; k0 += Kb) {
+        const bool one_pass = Kh <= Kb;
+        double2* red = one_pass ? lds : red_small;
+        for (int k0 = 0; k0 < Kh; k0 += Kb) {
             const int kk = k0 + kl;
-            double Nt = 0.0, Dt = 0.0;
-            if (part < nparts && kk < K) {
-                const double mu = mus[kk];
-                double N0 = 0.0, N1 = 0.0, D0 = 0.0, D1 = 0.0;
-                int i = part;
-                for (; i + nparts < n; i += 2 * nparts) {
-                    const double2 p0 = stage[i], p1 = stage[i + nparts];
-                    const double u0 = p0.x + mu, u1 = p1.x + mu;
-                    // one reciprocal for two terms: 1/u0 = u1 / (u0 u1), 1/u1 = u0 / (u0 u1)
-                    double rp = __builtin_amdgcn_rcp(u0 * u1);
-                    const double pr = u0 * u1;
-                    double e = fma(-pr, rp, 1.0);
-                    rp = fma(rp, e, rp);
-                    e = fma(-pr, rp, 1.0);
-                    rp = fma(rp, e, rp);
-                    const double r0 = u1 * rp, r1 = u0 * rp;
-                    D0 += r0;
-                    D1 += r1;
-                    N0 = fma(p0.y, r0 * r0, N0);
-                    N1 = fma(p1.y, r1 * r1, N1);
-                }
-                if (i < n) {
-                    const double2 p0 = stage[i];
-                    const double u0 = p0.x + mu;
-                    double r = __builtin_amdgcn_rcp(u0);
-                    double e = fma(-u0, r, 1.0);
-                    r = fma(r, e, r);
-                    e = fma(-u0, r, 1.0);
-                    r = fma(r, e, r);
-                    D0 += r;
-                    N0 = fma(p0.y, r * r, N0);
-                }
-                Nt = N0 + N1;
-                Dt = D0 + D1;
+            double Na = 0.0, Da = 0.0, Nb = 0.0, Db = 0.0;
+            if (part < nparts && kk < Kh) {
+                const int ka = 2 * kk, kb2 = ka + 1 < K ? ka + 1 : ka;
+                gcv_two(stage, n, part, nparts, mus[ka], mus[kb2], Na, Da, Nb, Db);
             }
-            red[tid] = make_double2(Nt, Dt);
+            if (one_pass) __syncthreads();  // the staged pairs are no longer read
+            red[2 * tid] = make_double2(Na, Da);
+            red[2 * tid + 1] = make_double2(Nb, Db);
             __syncthreads();
-            if (part == 0 && kk < K) {
-                double2 acc = red[kl];
+            if (part == 0 && kk < Kh) {
+                double2 A = red[2 * kl], B = red[2 * kl + 1];
                 for (int p = 1; p < nparts; ++p) {
-                    const double2 v = red[p * Kb + kl];
-                    acc.x += v.x;
-                    acc.y += v.y;
+                    const double2 va = red[2 * (p * Kb + kl)], vb = red[2 * (p * Kb + kl) + 1];
+                    A.x += va.x;
+                    A.y += va.y;
+                    B.x += vb.x;
+                    B.y += vb.y;
                 }
-                const double Gk = acc.x / (acc.y * acc.y);
-                Gs[kk] = Gk;
-                if (a.G) a.G[static_cast<int64_t>(sg.item) * K + kk] = Gk;
+                const int ka = 2 * kk;
+                Gs[ka] = A.x / (A.y * A.y);
+                if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka] = Gs[ka];
+                if (ka + 1 < K) {
+                    Gs[ka + 1] = B.x / (B.y * B.y);
+                    if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka + 1] = Gs[ka + 1];
+                }
             }
             __syncthreads();
         }
@@ -272,26 +322,38 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_restore(RaggedArgs a, i
             }
         }
         __syncthreads();
-        const int kb = s_kbest;
+        const int kb = __builtin_amdgcn_readfirstlane(s_kbest);
         const double mu_s = kb >= 0 ? mus[kb] : __builtin_nan("");
 
+        __builtin_amdgcn_sched_barrier(0);
         // ---- Tikhonov filter at mu*: fhat = d ghat / (d^2 + mu s^2)
 #pragma unroll
         for (int k = 0; k < SL; ++k) c[k] = dj[k] * c[k] / fma(mu_s, sj[k] * sj[k], dj[k] * dj[k]);
         const double fpoly = z0 / fma(mu_s, s_poly * s_poly, z0 * z0);
         const double fx1 = fpoly * x1, fxn = fpoly * xn;
         if (tid < rank) bc[tid].x = c[0];
+        if (S == 2) {  // the second half of the split reads the coefficients again
+#pragma unroll
+            for (int k = 0; k < SL; ++k) {
+                const int j = tid + k * BLOCK;
+                if (j < N) scratch[j] = c[k];
+            }
+        }
         __syncthreads();
         const double beta0 = rank > 0 ? bc[0].x : 0.0;
         const double beta1 = rank > 1 ? bc[1].x : 0.0;
 
+        __builtin_amdgcn_sched_barrier(0);
         // ---- forward transform of the filtered coefficients
         {
-            auto in_fwd = [&](int k, int j) { return make_double2(j >= rank ? c[k] : 0.0, 0.0); };
+            auto in_fwd = [&](int k, int j) {
+                const double v = S == 2 ? scratch[j] : c[k];
+                return make_double2(j >= rank ? v : 0.0, 0.0);
+            };
             auto park = [&](int j, double2 y) { f[j + 1] = y.x; };
             auto unpark = [&](int j) { return make_double2(f[j + 1], 0.0); };
             double2 u[SL];
-            chirp_core<LOGP, S>(u, ax.syn, ax.syn.mode, N, lds, tw, in_fwd, park, unpark);
+            chirp_core<LOGP, S, SL>(u, ax.syn, ax.syn.mode, N, lds, tw, in_fwd, park, unpark);
 #pragma unroll
             for (int k = 0; k < SL; ++k) {
                 const int j = tid + k * BLOCK;
@@ -326,18 +388,26 @@ struct ht_batch {
     Axis* d_axes = nullptr;
     RSig* d_sigs = nullptr;
     int* d_counters = nullptr;
+    double* d_scratch = nullptr;    // split class: MAX_N doubles per persistent workgroup
     int64_t total_n = 0, total_psf = 0;
     int class_start[NCLASS] = {0};
     int class_count[NCLASS] = {0};
     int grid[NCLASS] = {0};         // persistent workgroups per class (schedule)
+    int variant[NCLASS] = {0};      // 0: 8 points per thread, 1: 16 (FFT lengths >= 4096 only)
+    unsigned class_mask = (1u << NCLASS) - 1;  // size classes ht_batch_restore runs
 };
 
 namespace {
 
-template <int LOGP, int S>
+constexpr int SPLIT_MAX_GRID = 1024;  // persistent workgroups of the split class (scratch rows)
+
+int class_logp(int c) { return c == 5 ? 13 : MIN_LOGP + c; }
+bool has_variant(int c) { return class_logp(c) >= 12; }
+
+template <int LOGP, int S, int SL>
 int max_active(int device) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_restore<LOGP, S>, fft_block_for(LOGP), 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_restore<LOGP, S, SL>, (1 << LOGP) / SL, 0) != hipSuccess)
         nb = 1;
     hipDeviceProp_t prop;
     int cus = 256;
@@ -345,14 +415,42 @@ int max_active(int device) {
     return std::max(1, nb) * cus;
 }
 
-int default_grid(int cls, int device) {
+int full_grid(int cls, int variant, int device) {
     switch (cls) {
-        case 0: return max_active<9, 1>(device);
-        case 1: return max_active<10, 1>(device);
-        case 2: return max_active<11, 1>(device);
-        case 3: return max_active<12, 1>(device);
-        case 4: return max_active<13, 1>(device);
-        default: return max_active<13, 2>(device);
+        case 0: return max_active<9, 1, 8>(device);
+        case 1: return max_active<10, 1, 8>(device);
+        case 2: return max_active<11, 1, 8>(device);
+        case 3: return variant ? max_active<12, 1, 16>(device) : max_active<12, 1, 8>(device);
+        case 4: return variant ? max_active<13, 1, 16>(device) : max_active<13, 1, 8>(device);
+        default: return variant ? max_active<13, 2, 16>(device) : max_active<13, 2, 8>(device);
+    }
+}
+
+template <int LOGP, int S, int SL>
+void launch_class(const RaggedArgs& a, int c, int start, int cnt, int grid, const double2* tw, hipStream_t stream) {
+    (void)tw;
+    hipLaunchKernelGGL((k_restore<LOGP, S, SL>), dim3(static_cast<unsigned>(grid)), dim3((1 << LOGP) / SL), 0, stream,
+                       a, c, start, cnt);
+}
+
+void launch_any(const RaggedArgs& a, int c, int variant, int start, int cnt, int grid, const double2* tw,
+                hipStream_t stream) {
+    switch (c) {
+        case 0: launch_class<9, 1, 8>(a, c, start, cnt, grid, tw, stream); break;
+        case 1: launch_class<10, 1, 8>(a, c, start, cnt, grid, tw, stream); break;
+        case 2: launch_class<11, 1, 8>(a, c, start, cnt, grid, tw, stream); break;
+        case 3:
+            if (variant) launch_class<12, 1, 16>(a, c, start, cnt, grid, tw, stream);
+            else launch_class<12, 1, 8>(a, c, start, cnt, grid, tw, stream);
+            break;
+        case 4:
+            if (variant) launch_class<13, 1, 16>(a, c, start, cnt, grid, tw, stream);
+            else launch_class<13, 1, 8>(a, c, start, cnt, grid, tw, stream);
+            break;
+        default:
+            if (variant) launch_class<13, 2, 16>(a, c, start, cnt, grid, tw, stream);
+            else launch_class<13, 2, 8>(a, c, start, cnt, grid, tw, stream);
+            break;
     }
 }
 
@@ -423,6 +521,7 @@ extern "C" ht_status ht_batch_create(int64_t count, const int64_t* n, const int*
         delete bt;
         return st;
     }
+    for (auto& ax : axes) ax.tw = tw;
     // signal descriptors grouped by size class, longest first within a class
     std::vector<int64_t> off(count), poff(count);
     int64_t acc = 0, pacc = 0;
@@ -445,10 +544,16 @@ extern "C" ht_status ht_batch_create(int64_t count, const int64_t* n, const int*
     });
     for (int64_t i = 0; i < count; ++i) bt->class_count[class_of(axes[sigs[i].axis])]++;
     for (int c = 1; c < NCLASS; ++c) bt->class_start[c] = bt->class_start[c - 1] + bt->class_count[c - 1];
-    for (int c = 0; c < NCLASS; ++c) bt->grid[c] = std::min(bt->class_count[c], default_grid(c, device));
+    for (int c = 0; c < NCLASS; ++c) {
+        bt->variant[c] = 0;  // 8 points per thread: the faster variant on MI355X (autotuner)
+        bt->grid[c] = std::max(1, std::min(bt->class_count[c], full_grid(c, bt->variant[c], device)));
+    }
+    bt->grid[5] = std::min(bt->grid[5], SPLIT_MAX_GRID);
     bool ok = hipMalloc(&bt->d_axes, sizeof(Axis) * nax) == hipSuccess &&
               hipMalloc(&bt->d_sigs, sizeof(RSig) * count) == hipSuccess &&
               hipMalloc(&bt->d_counters, sizeof(int) * NCLASS) == hipSuccess;
+    if (ok && bt->class_count[5] > 0)
+        ok = hipMalloc(&bt->d_scratch, sizeof(double) * MAX_N * SPLIT_MAX_GRID) == hipSuccess;
     ok = ok && hipMemcpy(bt->d_axes, axes.data(), sizeof(Axis) * nax, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(bt->d_sigs, sigs.data(), sizeof(RSig) * count, hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
@@ -465,6 +570,7 @@ extern "C" ht_status ht_batch_destroy(ht_batch* bt) {
     if (bt->d_axes) hipFree(bt->d_axes);
     if (bt->d_sigs) hipFree(bt->d_sigs);
     if (bt->d_counters) hipFree(bt->d_counters);
+    if (bt->d_scratch) hipFree(bt->d_scratch);
     delete bt;
     return HT_OK;
 }
@@ -472,10 +578,27 @@ extern "C" ht_status ht_batch_destroy(ht_batch* bt) {
 extern "C" int64_t ht_batch_total_length(const ht_batch* bt) { return bt ? bt->total_n : -1; }
 extern "C" int64_t ht_batch_psf_total(const ht_batch* bt) { return bt ? bt->total_psf : -1; }
 
-extern "C" ht_status ht_batch_schedule(ht_batch* bt, int size_class, int workgroups, int* current) {
+extern "C" ht_status ht_batch_schedule(ht_batch* bt, int size_class, int workgroups, int variant,
+                                       int* cur_workgroups, int* cur_variant) {
     if (!bt || size_class < 0 || size_class >= NCLASS) return fail(HT_ERR_INVALID_ARG, "ht_batch_schedule: bad argument");
-    if (workgroups > 0) bt->grid[size_class] = std::max(1, std::min(workgroups, std::max(1, bt->class_count[size_class])));
-    if (current) *current = bt->grid[size_class];
+    if (variant >= 0) {
+        if (variant > 1 || (variant == 1 && !has_variant(size_class)))
+            return fail(HT_ERR_INVALID_ARG, "ht_batch_schedule: variant not available for this size class");
+        bt->variant[size_class] = variant;
+    }
+    if (workgroups > 0) {
+        int cap = std::max(1, bt->class_count[size_class]);
+        if (size_class == 5) cap = std::min(cap, SPLIT_MAX_GRID);
+        bt->grid[size_class] = std::max(1, std::min(workgroups, cap));
+    }
+    if (cur_workgroups) *cur_workgroups = bt->grid[size_class];
+    if (cur_variant) *cur_variant = bt->variant[size_class];
+    return HT_OK;
+}
+
+extern "C" ht_status ht_batch_class_mask(ht_batch* bt, unsigned mask) {
+    if (!bt || mask == 0 || mask >= (1u << NCLASS)) return fail(HT_ERR_INVALID_ARG, "ht_batch_class_mask: bad argument");
+    bt->class_mask = mask;
     return HT_OK;
 }
 
@@ -493,24 +616,16 @@ extern "C" ht_status ht_batch_restore(const ht_batch* bt, const double* signal, 
     if (norm != HT_NORM_IDENTITY && norm != HT_NORM_SECOND_DIFF) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore: bad norm");
     if (K < 1 || K > BATCH_MAX_K) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore: K must be in [1, 256]");
     if (signal == restored) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore: signal and restored must not overlap");
-    RaggedArgs a{bt->d_axes, bt->d_sigs, bt->d_counters, signal, psf, mu_grid, K, norm, restored, G, k_best, mu_best};
+    RaggedArgs a{bt->d_axes, bt->d_sigs, bt->d_counters, signal, psf, mu_grid, K, norm, restored, G, k_best, mu_best,
+                 bt->d_scratch};
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, stream, bt->d_counters);
     ht_status st = check_hip(hipGetLastError(), "ht_batch_restore reset");
     if (st != HT_OK) return st;
     // largest class first: its signals dominate the run time
     for (int c = NCLASS - 1; c >= 0; --c) {
         const int cnt = bt->class_count[c];
-        if (cnt == 0) continue;
-        const dim3 grid(static_cast<unsigned>(bt->grid[c]));
-        const int start = bt->class_start[c];
-        switch (c) {
-            case 0: hipLaunchKernelGGL((k_restore<9, 1>), grid, dim3(fft_block_for(9)), 0, stream, a, c, start, cnt, bt->tw); break;
-            case 1: hipLaunchKernelGGL((k_restore<10, 1>), grid, dim3(fft_block_for(10)), 0, stream, a, c, start, cnt, bt->tw); break;
-            case 2: hipLaunchKernelGGL((k_restore<11, 1>), grid, dim3(fft_block_for(11)), 0, stream, a, c, start, cnt, bt->tw); break;
-            case 3: hipLaunchKernelGGL((k_restore<12, 1>), grid, dim3(fft_block_for(12)), 0, stream, a, c, start, cnt, bt->tw); break;
-            case 4: hipLaunchKernelGGL((k_restore<13, 1>), grid, dim3(fft_block_for(13)), 0, stream, a, c, start, cnt, bt->tw); break;
-            default: hipLaunchKernelGGL((k_restore<13, 2>), grid, dim3(fft_block_for(13)), 0, stream, a, c, start, cnt, bt->tw); break;
-        }
+        if (cnt == 0 || !(bt->class_mask & (1u << c))) continue;
+        launch_any(a, c, bt->variant[c], bt->class_start[c], cnt, bt->grid[c], bt->tw, stream);
         st = check_hip(hipGetLastError(), "ht_batch_restore launch");
         if (st != HT_OK) return st;
     }

@@ -47,6 +47,7 @@ struct Axis {
     int den;              // eigenvalue grid: angles pi * r / den
     const double* tcos;   // [2 den] cos(pi r / den)
     const double* tsin;   // [2 den] sin(pi r / den)
+    const double2* tw;    // the device's FFT twiddle table
 };
 
 // Strided view of a batch of 1D signals: signal b lives at

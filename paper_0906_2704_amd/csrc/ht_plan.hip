@@ -386,6 +386,7 @@ ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* a
                        reinterpret_cast<const double2*>(dev + o[a].aB), hs[a].ana.mode};
         ax.syn = Chirp{reinterpret_cast<const double2*>(dev + o[a].spre), reinterpret_cast<const double2*>(dev + o[a].spost),
                        reinterpret_cast<const double2*>(dev + o[a].sB), hs[a].syn.mode};
+        ax.tw = nullptr;
         axes_out[a] = ax;
     }
     return HT_OK;
@@ -428,6 +429,7 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
         delete p;
         return st;
     }
+    for (int a = 0; a < ndim; ++a) p->ax[a].tw = tw;
     if (ndim == 2) {
         const int64_t img = n[0] * n[1];
         if (hipMalloc(&p->work, sizeof(double2) * img * max_batch) != hipSuccess) {

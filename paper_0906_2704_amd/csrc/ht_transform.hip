@@ -76,7 +76,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View i
     auto unpark = [&](int j) { return vload(out, ob, j + 1); };
     const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ax.ana.mode;
     double2 acc[SL];
-    chirp_core<LOGP, S>(acc, ax.ana, mode, N, lds, tw, in_fn, park, unpark);
+    chirp_core<LOGP, S, SL>(acc, ax.ana, mode, N, lds, tw, in_fn, park, unpark);
     if (ax.rank > 0) {  // DST family: x_mid -= U (E^T K)^{-1} E^T x_mid
         if (tid < ax.rank) corr[tid] = acc[0];
         __syncthreads();
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View i
     auto unpark = [&](int j) { return vload(out, ob, j + 1); };
     const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ax.syn.mode;
     double2 u[SL];
-    chirp_core<LOGP, S>(u, ax.syn, mode, N, lds, tw, in_fn, park, unpark);
+    chirp_core<LOGP, S, SL>(u, ax.syn, mode, N, lds, tw, in_fn, park, unpark);
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;

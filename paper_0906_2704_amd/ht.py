@@ -210,8 +210,11 @@ def _batch_sigs(L):
     L.ht_batch_psf_total.restype = I64
     L.ht_batch_restore.argtypes = [P, VP, VP, ctypes.c_int, VP, I32, VP, VP, VP, VP, VP]
     L.ht_batch_restore.restype = ctypes.c_int
-    L.ht_batch_schedule.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.ht_batch_schedule.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int)]
     L.ht_batch_schedule.restype = ctypes.c_int
+    L.ht_batch_class_mask.argtypes = [P, ctypes.c_uint]
+    L.ht_batch_class_mask.restype = ctypes.c_int
     L.ht_batch_class_count.argtypes = [P, ctypes.c_int]
     L.ht_batch_class_count.restype = ctypes.c_int
 
@@ -260,11 +263,15 @@ class Batch:
         except Exception:
             pass
 
-    def schedule(self, size_class, workgroups=0):
-        cur = ctypes.c_int()
-        _check(lib().ht_batch_schedule(self._h, int(size_class), int(workgroups), ctypes.byref(cur)),
-               "ht_batch_schedule")
-        return cur.value
+    def schedule(self, size_class, workgroups=0, variant=-1):
+        """Set / query (workgroups, variant) of a size class; returns the values in effect."""
+        cur, var = ctypes.c_int(), ctypes.c_int()
+        _check(lib().ht_batch_schedule(self._h, int(size_class), int(workgroups), int(variant), ctypes.byref(cur),
+                                       ctypes.byref(var)), "ht_batch_schedule")
+        return cur.value, var.value
+
+    def class_mask(self, mask):
+        _check(lib().ht_batch_class_mask(self._h, int(mask)), "ht_batch_class_mask")
 
     def class_count(self, size_class):
         return int(lib().ht_batch_class_count(self._h, int(size_class)))

@@ -12,6 +12,8 @@ from oracle import tikhonov as tk
 from oracle import transforms as tr
 from paper_0906_2704_amd import synth
 
+from parity import assert_gcv_close
+
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
@@ -178,7 +180,7 @@ def test_filter_and_gcv_parity(ht, kind):
         for b in range(B):
             gw = tr.inverse(kind, G[b])
             Gw, kw, muw = tk.gcv_scan(gw, dw, sw, mus)
-            assert np.max(np.abs(Gv[b] - Gw) / np.abs(Gw)) < TOL
+            assert_gcv_close(Gv[b], Gw, gw, dw, sw, mus, (kind, norm, b))
             assert kb[b] == kw and mb[b] == muw
         mu_t = to_dev(mb)
         fhat = ht.ht_tikhonov_filter(p, ghat, d, s, mu_t)
@@ -204,7 +206,7 @@ def test_gcv_per_item_grids_and_eigs(ht):
     for b in range(B):
         gw = tr.inverse(kind, Y[b])
         Gw, kw, _ = tk.gcv_scan(gw, tr.blur_eigs(kind, n, *hs[b]), tr.smooth_eigs(kind, n, "D2"), grids[b])
-        assert np.max(np.abs(Gv[b] - Gw) / np.abs(Gw)) < TOL
+        assert_gcv_close(Gv[b], Gw, gw, tr.blur_eigs(kind, n, *hs[b]), tr.smooth_eigs(kind, n, "D2"), grids[b], b)
         assert kb[b] == kw
 
 

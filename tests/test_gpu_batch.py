@@ -10,6 +10,8 @@ from oracle import tikhonov as tk
 from oracle import transforms as tr
 from paper_0906_2704_amd import synth
 
+from parity import assert_gcv_close
+
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
 KIND_OF_DEGREE = {1: "AR", 2: "C", 3: "DST3"}
@@ -57,7 +59,7 @@ def check_items(items, bt, f, G, kb, mb, norm, kind_of=KIND_OF_DEGREE):
         s = tr.smooth_eigs(kind, n, norm)
         ghat = tr.inverse(kind, p.g)
         Gw, kw, muw = tk.gcv_scan(ghat, d, s, p.mus)
-        assert np.max(np.abs(G[b] - Gw) / np.abs(Gw)) < TOL, (b, n, kind)
+        assert_gcv_close(G[b], Gw, ghat, d, s, p.mus, (b, n, kind))
         assert kb[b] == kw and mb[b] == muw, (b, n, kind, kb[b], kw)
         fw = tr.forward(kind, tk.tikhonov_filter(ghat, d, s, muw)).real
         fb = f[bt.offsets[b]:bt.offsets[b + 1]]
@@ -120,3 +122,33 @@ def test_ragged_rejects_bad_input(ht):
         ht.Batch([10], [1], [9], [4])
     with pytest.raises(ht.HTError, match="INVALID_ARG"):
         ht.Batch([4], [1], [1], [0])
+
+
+def test_ragged_graph_replays_match_eager(ht):
+    """The whole restore captured in a HIP graph: every replay (with eager work and
+    synchronisations in between) reproduces the eager result bitwise."""
+    items = make_items([200, 700, 1800, 3000, 5000], seed=9)
+    bt, f_eager, G_eager, kb_eager, _ = run_batch(ht, items, "D2")
+    dev = "cuda"
+    g = torch.tensor(np.concatenate([p.g for p in items]), device=dev)
+    psf = torch.tensor(np.concatenate([p.h for p in items]), device=dev)
+    mus = torch.tensor(np.stack([p.mus for p in items]), device=dev)
+    f = torch.empty_like(g)
+    G = torch.empty((len(items), mus.shape[1]), dtype=torch.float64, device=dev)
+    kb = torch.empty(len(items), dtype=torch.int32, device=dev)
+    mb = torch.empty(len(items), dtype=torch.float64, device=dev)
+    ht.ht_batch_restore(bt, g, psf, "D2", mus, restored=f, G=G, kb=kb, mb=mb)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ht.ht_batch_restore(bt, g, psf, "D2", mus, restored=f, G=G, kb=kb, mb=mb)
+    for rep in range(4):
+        f.zero_()
+        G.zero_()
+        kb.fill_(-7)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(f.cpu().numpy(), f_eager), rep
+        assert np.array_equal(G.cpu().numpy(), G_eager), rep
+        assert np.array_equal(kb.cpu().numpy(), kb_eager), rep
+        _ = (g * 2.0).sum().item()  # unrelated eager work between replays
