@@ -22,13 +22,14 @@ __device__ __forceinline__ double2 select_out(double2 y, int mode) {
 }
 
 // in(k, j) returns x_j for the slot k holding j = tid + k * BLOCK < N; the result goes to
-// out[k].
-// The workgroup has 2^LOGP / SL threads.
-template <int LOGP, int S, int SL, class In, class Park, class Unpark>
-__device__ __forceinline__ void chirp_core(double2 (&out)[SL], const Chirp& ch, int mode, int N,
+// out[k].  OutT = double2 keeps the complex result (selected by `mode`), OutT = double the
+// real or imaginary part only.  The workgroup has 2^LOGP / SL threads.
+template <int LOGP, int S, int SL, class OutT, class In, class Park, class Unpark>
+__device__ __forceinline__ void chirp_core(OutT (&out)[SL], const Chirp& ch, int mode, int N,
                                            double2* lds, const double2* __restrict__ tw, In in,
                                            Park park, Unpark unpark) {
     constexpr int BLOCK = (1 << LOGP) / SL;
+    constexpr bool REAL = sizeof(OutT) == sizeof(double);
     const int tid = threadIdx.x;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -43,7 +44,7 @@ __device__ __forceinline__ void chirp_core(double2 (&out)[SL], const Chirp& ch, 
         fft_slots<LOGP, -1, SL>(v, lds, tw);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int k = 0; k < SL; ++k) v[k] = cmul(v[k], tload(ch.B, static_cast<unsigned>(S * (tid + k * BLOCK) + s)));
+        for (int k = 0; k < SL; ++k) v[k] = cmul(v[k], tload(ch.B, static_cast<unsigned>(s * (1 << LOGP) + tid + k * BLOCK)));
         __builtin_amdgcn_sched_barrier(0);
         fft_slots<LOGP, 1, SL>(v, lds, tw);
         __builtin_amdgcn_sched_barrier(0);
@@ -53,11 +54,16 @@ __device__ __forceinline__ void chirp_core(double2 (&out)[SL], const Chirp& ch, 
             if (j < N) {
                 double2 c = v[k];
                 if (s == 1) c = cmulc(c, tload(tw, j));  // exp(+2 pi i j / M)
-                const double2 y = select_out(cmul(c, tload(ch.post, j)), mode);
+                const double2 y2 = cmul(c, tload(ch.post, j));
+                OutT y;
+                if constexpr (REAL)
+                    y = mode == MODE_IM ? y2.y : y2.x;
+                else
+                    y = select_out(y2, mode);
                 if (S == 2 && s == 0)
                     park(j, y);
                 else if (S == 2)
-                    out[k] = cadd(y, unpark(j));
+                    out[k] = y + unpark(j);
                 else
                     out[k] = y;
             }

@@ -168,12 +168,9 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
             auto in_inv = [&](int, int j) {
                 return make_double2(g[j + 1] - ax.q[j + 1] * x1 - ax.q[N - j] * xn, 0.0);
             };
-            auto park = [&](int j, double2 y) { f[j + 1] = y.x; };
-            auto unpark = [&](int j) { return make_double2(f[j + 1], 0.0); };
-            double2 out[SL];
-            chirp_core<LOGP, S, SL>(out, ax.ana, ax.ana.mode, N, lds, tw, in_inv, park, unpark);
-#pragma unroll
-            for (int k = 0; k < SL; ++k) c[k] = out[k].x;
+            auto park = [&](int j, double y) { f[j + 1] = y; };
+            auto unpark = [&](int j) { return f[j + 1]; };
+            chirp_core<LOGP, S, SL>(c, ax.ana, ax.ana.mode, N, lds, tw, in_inv, park, unpark);
         }
         if (rank > 0) {  // DST family correction x_mid -= U (E^T K)^{-1} E^T x_mid
             if (tid < rank) bc[tid].x = c[0];
@@ -350,21 +347,21 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
                 const double v = S == 2 ? scratch[j] : c[k];
                 return make_double2(j >= rank ? v : 0.0, 0.0);
             };
-            auto park = [&](int j, double2 y) { f[j + 1] = y.x; };
-            auto unpark = [&](int j) { return make_double2(f[j + 1], 0.0); };
-            double2 u[SL];
+            auto park = [&](int j, double y) { f[j + 1] = y; };
+            auto unpark = [&](int j) { return f[j + 1]; };
+            double u[SL];
             chirp_core<LOGP, S, SL>(u, ax.syn, ax.syn.mode, N, lds, tw, in_fwd, park, unpark);
 #pragma unroll
             for (int k = 0; k < SL; ++k) {
                 const int j = tid + k * BLOCK;
                 if (j < N) {
-                    double y = u[k].x + ax.q[j + 1] * fx1 + ax.q[N - j] * fxn;
+                    double y = u[k] + ax.q[j + 1] * fx1 + ax.q[N - j] * fxn;
                     if (rank > 0) y += ax.bub[j] * beta0;
                     if (rank > 1) y += ax.bub[N + j] * beta1;
                     f[j + 1] = y;
                     if (kind == HT_KIND_C) {
-                        if (j == 0) f[0] = q1 * fx1 + u[k].x;
-                        if (j == N - 1) f[n - 1] = q1 * fxn + u[k].x;
+                        if (j == 0) f[0] = q1 * fx1 + u[k];
+                        if (j == N - 1) f[n - 1] = q1 * fxn + u[k];
                     }
                 }
             }

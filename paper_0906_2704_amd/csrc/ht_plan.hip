@@ -354,6 +354,16 @@ ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* a
         double2* dst = reinterpret_cast<double2*>(host.data() + off);
         for (size_t i = 0; i < v.size(); ++i) dst[i] = make_double2(v[i].real(), v[i].imag());
     };
+    // filter spectra stored split-major: half s holds B[S u + s], u < M / S, contiguously
+    auto putc_split = [&](size_t off, const std::vector<cd>& v, int S) {
+        double2* dst = reinterpret_cast<double2*>(host.data() + off);
+        const size_t P = v.size() / S;
+        for (int sidx = 0; sidx < S; ++sidx)
+            for (size_t u = 0; u < P; ++u) {
+                const cd w = v[S * u + sidx];
+                dst[sidx * P + u] = make_double2(w.real(), w.imag());
+            }
+    };
     for (int64_t a = 0; a < nax; ++a) {
         const HostAxis& h = hs[a];
         put(o[a].q, h.q.data(), sizeof(double) * h.q.size());
@@ -363,10 +373,10 @@ ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* a
         put(o[a].tsin, h.tsin.data(), sizeof(double) * h.tsin.size());
         putc(o[a].apre, h.ana.pre);
         putc(o[a].apost, h.ana.post);
-        putc(o[a].aB, h.ana.B);
+        putc_split(o[a].aB, h.ana.B, h.ax.S);
         putc(o[a].spre, h.syn.pre);
         putc(o[a].spost, h.syn.post);
-        putc(o[a].sB, h.syn.B);
+        putc_split(o[a].sB, h.syn.B, h.ax.S);
     }
     char* dev = nullptr;
     if (hipMalloc(&dev, bytes) != hipSuccess) return fail(HT_ERR_OOM, "table allocation failed");
