@@ -1,0 +1,129 @@
+"""GPU parity of the 2D tensor-product path (Section 6): T^(2) = T_{n0} (x) T_{n1} applied
+as 1D transforms along axis 1 then axis 0, separable-PSF eigenvalues d0_i d1_j, the 2D
+Laplacian s0_i + s1_j (or L = I), GCV over the whole image, filter and forward
+transform, against the CPU oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import tikhonov as tk
+from oracle import transforms as tr
+from oracle import twod
+from paper_0906_2704_amd import synth
+
+from parity import assert_gcv_close, rel_normwise
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def ht():
+    from paper_0906_2704_amd import ht as _ht
+    _ht.lib()
+    return _ht
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def problem(n0, n1, sym, seed, eta=0.005):
+    rng = np.random.default_rng(seed)
+    m0, m1 = min(6, (n0 - 3) // 2), min(5, (n1 - 3) // 2)
+    if sym:
+        h0, c0 = synth.gaussian_psf(m0, 1.7)
+        h1, c1 = synth.gaussian_psf(m1, 1.2)
+    else:
+        h0, c0 = synth.gaussian_psf(m0, 1.7, shift=1.0)
+        h1, c1 = synth.gaussian_psf(m1, 1.2, shift=0.6)
+    F = synth.piecewise_poly_image(rng, (n0 + 2 * m0, n1 + 2 * m1))
+    G = synth.add_noise(rng, synth.observe_2d(F, h0, c0, h1, c1, (n0, n1)), eta)
+    return G, (h0, c0), (h1, c1)
+
+
+def run_2d(ht, n0, n1, sym, norm, seed, K=32):
+    G, (h0, c0), (h1, c1) = problem(n0, n1, sym, seed)
+    kind = "C" if sym else "F"
+    plan = ht.Plan((n0, n1), 2, psf_symmetric=sym, max_batch=2)
+    assert plan.kinds == [kind, kind]
+    psf = to_dev(np.concatenate([h0, h1]))
+    d, s = ht.ht_eigs(plan, psf, [len(h0), len(h1)], [c0, c1], norm)
+    g = to_dev(G[None])
+    ghat = ht.ht_transform_inv(plan, g)
+    mus = synth.mu_grid(-6.0, 0.0, K)
+    Gv, kb, mb = ht.ht_gcv_scan(plan, ghat, d, s, to_dev(mus))
+    f = ht.ht_transform_fwd(plan, ht.ht_tikhonov_filter(plan, ghat, d, s, mb))
+    torch.cuda.synchronize()
+    return dict(G=G, h=(h0, c0, h1, c1), kind=kind, d=d.cpu().numpy()[0], s=s.cpu().numpy()[0],
+                ghat=ghat.cpu().numpy()[0], Gv=Gv.cpu().numpy()[0], kb=int(kb.cpu()[0]),
+                mb=float(mb.cpu()[0]), f=f.cpu().numpy()[0], mus=mus, plan=plan)
+
+
+def check(r, norm):
+    G = r["G"]
+    n0, n1 = G.shape
+    h0, c0, h1, c1 = r["h"]
+    kind = r["kind"]
+    d0 = tr.blur_eigs(kind, n0, h0, c0)
+    d1 = tr.blur_eigs(kind, n1, h1, c1)
+    assert rel_normwise(r["d"][:n0], d0) < TOL and rel_normwise(r["d"][n0:], d1) < TOL
+    s2 = twod.smooth2d(kind, kind, n0, n1, norm)
+    s_gpu = r["s"][:n0, None] + r["s"][None, n0:]
+    assert np.max(np.abs(s_gpu - s2)) < 4 * TOL
+    ghat = twod.inverse2d(kind, kind, G)
+    assert rel_normwise(r["ghat"], ghat) < TOL
+    dd = np.multiply.outer(d0, d1)
+    Gw, kw, muw = tk.gcv_scan(ghat.ravel(), dd.ravel(), s2.ravel(), r["mus"])
+    assert_gcv_close(r["Gv"], Gw, ghat.ravel(), dd.ravel(), s2.ravel(), r["mus"], "2d")
+    assert r["kb"] == kw and r["mb"] == muw
+    fw = twod.forward2d(kind, kind, tk.tikhonov_filter(ghat, dd, s2, muw))
+    assert rel_normwise(r["f"], fw.real) < TOL
+
+
+@pytest.mark.parametrize("sym", [False, True])
+@pytest.mark.parametrize("norm", ["D2", "I"])
+@pytest.mark.parametrize("shape", [(12, 17), (64, 48), (130, 261)])
+def test_2d_parity(ht, sym, norm, shape):
+    print("case", shape, sym, norm, flush=True)
+    r = run_2d(ht, shape[0], shape[1], sym, norm, seed=shape[0] * 7 + shape[1])
+    check(r, norm)
+
+
+def test_2d_nonsymmetric_512(ht):
+    """The 512 x 512 image with the separable nonsymmetric PSF (T_F (x) T_F, Laplacian)."""
+    p = synth.config1(0)
+    plan = ht.Plan((512, 512), 2, psf_symmetric=False)
+    psf = to_dev(np.concatenate([p.h0, p.h1]))
+    d, s = ht.ht_eigs(plan, psf, [len(p.h0), len(p.h1)], [p.c0, p.c1], "D2")
+    ghat = ht.ht_transform_inv(plan, to_dev(p.g[None]))
+    Gv, kb, mb = ht.ht_gcv_scan(plan, ghat, d, s, to_dev(p.mus))
+    f = ht.ht_transform_fwd(plan, ht.ht_tikhonov_filter(plan, ghat, d, s, mb)).cpu().numpy()[0]
+    kind = "F"
+    d0 = tr.blur_eigs(kind, 512, p.h0, p.c0)
+    d1 = tr.blur_eigs(kind, 512, p.h1, p.c1)
+    gh = twod.inverse2d(kind, kind, p.g)
+    assert rel_normwise(ghat.cpu().numpy()[0], gh) < TOL
+    dd = np.multiply.outer(d0, d1)
+    s2 = twod.smooth2d(kind, kind, 512, 512, "D2")
+    Gw, kw, muw = tk.gcv_scan(gh.ravel(), dd.ravel(), s2.ravel(), p.mus)
+    assert_gcv_close(Gv.cpu().numpy()[0], Gw, gh.ravel(), dd.ravel(), s2.ravel(), p.mus, "512")
+    assert int(kb.cpu()[0]) == kw
+    fw = twod.forward2d(kind, kind, tk.tikhonov_filter(gh, dd, s2, muw)).real
+    assert rel_normwise(f, fw) < TOL
+    rre = np.linalg.norm(f - p.f_true) / np.linalg.norm(p.f_true)
+    assert rre < 0.5
+
+
+def test_2d_batch_of_two_and_limits(ht):
+    G1, (h0, c0), (h1, c1) = problem(40, 33, True, 1)
+    G2, _, _ = problem(40, 33, True, 2)
+    plan = ht.Plan((40, 33), 2, psf_symmetric=True, max_batch=2)
+    g = to_dev(np.stack([G1, G2]))
+    ghat = ht.ht_transform_inv(plan, g).cpu().numpy()
+    assert rel_normwise(ghat[0], twod.inverse2d("C", "C", G1)) < TOL
+    assert rel_normwise(ghat[1], twod.inverse2d("C", "C", G2)) < TOL
+    with pytest.raises(ht.HTError, match="max_batch"):
+        ht.ht_transform_inv(plan, to_dev(np.stack([G1, G2, G1])))
