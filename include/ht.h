@@ -186,6 +186,68 @@ ht_status ht_batch_class_mask(ht_batch* batch, unsigned mask);
 /* number of signals in a size class, or -1 */
 int ht_batch_class_count(const ht_batch* batch, int size_class);
 
+/* ---------------------------------------------------------------------------------
+ * Learned mu: a small network predicts log10(mu) from statistics of the transform
+ * coefficients and the blur spectrum; the GCV functional certifies the prediction and
+ * the full scan is the fallback.  Not in the paper: an accelerator of its GCV step.
+ * --------------------------------------------------------------------------------- */
+
+/* ht_batch_features -- for every signal: ghat = T^{-1} g (written to coeff [total_length],
+ * ordered as the coefficient vectors of ht_transform_inv) and 72 features
+ * (features [count][72], float32): the means of log10(|ghat_j|^2 + 1e-20) over 64 equal
+ * bands of the normalised core frequency j/(n-2) (band b holds j with
+ * floor(64 j / (n-2)) = b; the two polynomial entries are excluded), then the means of
+ * log10(|d_j|^2 + 1e-20) over 8 such bands of the blur eigenvalues (the floor keeps the
+ * logarithms well conditioned where the spectrum vanishes).  Needs n >= 66.          */
+ht_status ht_batch_features(const ht_batch* batch, const double* signal, const double* psf,
+                            double* coeff, float* features, hipStream_t stream);
+
+/* ht_batch_restore_learned -- coeff_restored holds the coefficients from
+ * ht_batch_features on entry and the restorations on exit.  For every signal the grid
+ * index k^ nearest to pred_log10_mu[b] is certified: G is evaluated on [k^-h, k^+h]
+ * (h = cert_half in [1, K-1], clipped to the grid); with k_m its first minimum there,
+ * the certificate holds if G(k^) <= 1.05 G(k_m) and k_m is not an interior edge of the
+ * bracket, and then
+ * mu = mu_{k_m}; otherwise the full grid is scanned (fallback[b] = 1) and mu is the
+ * scan's choice.  G [count][K] (nullable) receives the evaluated values only.          */
+ht_status ht_batch_restore_learned(const ht_batch* batch, double* coeff_restored,
+                                   const double* psf, int norm, const double* mu_grid,
+                                   int32_t K, const float* pred_log10_mu, int32_t cert_half,
+                                   double* G, int32_t* k_best, double* mu_best,
+                                   int32_t* fallback, hipStream_t stream);
+
+/* Network kernels (row-major matrices; bfloat16 stored as uint16_t bit patterns):
+ * ht_gemm_bf16: C = act(A B + bias), A(i,k) = A[i sa_i + k sa_k], B(k,j) = B[k sb_k + j sb_j]
+ *   (bfloat16), float32 accumulation on the matrix cores; act 0 = none, 1 = GELU
+ *   0.5 x (1 + erf(x / sqrt 2)); Z (pre-activation), C (activation; rounded to bfloat16
+ *   when Cb is also given, so that C and Cb hold the same values) and Cb may each be NULL;
+ *   all outputs use leading dimension ldc.
+ * ht_to_bf16: dst = bf16((src - mean[col]) / std[col]) (mean, std both NULL: plain).
+ * ht_from_bf16: dst = float32 value of the bfloat16 src.
+ * ht_gelu_backward: dz = dh * GELU'(z), dzb (nullable) its bfloat16 copy.
+ * ht_colsum: out[j] = sum_i X[i][j] (* weight[i] if weight != NULL), fixed order.
+ * ht_mse_grad: dy = 2 (y - t) / rows, sq = (y - t)^2.
+ * ht_outer: dh[i][j] = dy[i] * w[j].
+ * ht_adam: Adam on float32 parameters (bias-corrected, step >= 1); pb (nullable) gets
+ *   the bfloat16 copy of the updated parameters.                                      */
+ht_status ht_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t sa_i, int64_t sa_k,
+                       const uint16_t* B, int64_t sb_k, int64_t sb_j, const float* bias, int act,
+                       float* Z, float* C, int64_t ldc, uint16_t* Cb, hipStream_t stream);
+ht_status ht_to_bf16(const float* src, uint16_t* dst, int64_t rows, int cols, const float* mean,
+                     const float* stdv, hipStream_t stream);
+ht_status ht_from_bf16(const uint16_t* src, float* dst, int64_t count, hipStream_t stream);
+ht_status ht_gelu_backward(const float* z, const float* dh, float* dz, uint16_t* dzb,
+                           int64_t count, hipStream_t stream);
+ht_status ht_colsum(const float* X, int64_t rows, int cols, const float* weight, float* out,
+                    hipStream_t stream);
+ht_status ht_mse_grad(const float* y, const float* t, float* dy, float* sq, int64_t rows,
+                      hipStream_t stream);
+ht_status ht_outer(const float* dy, const float* w, float* dh, int64_t rows, int cols,
+                   hipStream_t stream);
+ht_status ht_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr,
+                  float beta1, float beta2, float eps, int64_t step, uint16_t* pb,
+                  hipStream_t stream);
+
 const char* ht_status_str(ht_status status);
 const char* ht_last_error(void);
 

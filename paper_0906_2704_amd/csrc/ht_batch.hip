@@ -50,7 +50,21 @@ struct RaggedArgs {
     int32_t* kbest;
     double* mubest;
     double* scratch;    // MAX_N doubles per persistent workgroup of the split class
+    const float* pred;  // learned mode: predicted log10(mu) per item
+    int32_t* fallback;  // learned mode: 1 where the certificate failed and the full scan ran
+    float* feat;        // feature mode: [count][NFEAT]
+    int cert_half;      // learned mode: certificate bracket half-width in grid steps
 };
+
+// What one pass of the fused kernel does with each signal.
+enum BatchMode {
+    MODE_SCAN = 0,      // inverse, eigenvalues, full GCV scan, filter, forward
+    MODE_FEATURES = 1,  // inverse, eigenvalues, band statistics; the coefficients go to f
+    MODE_LEARNED = 2    // coefficients from f, eigenvalues, GCV certificate around the
+                        // predicted mu (full scan if it fails), filter, forward
+};
+constexpr int NFEAT_G = 64, NFEAT_D = 8, NFEAT = NFEAT_G + NFEAT_D;
+constexpr double CERT_SLACK = 1.05;   // G(predicted) may exceed the bracket minimum by 5%
 
 static int class_of(const Axis& a) { return a.S == 2 ? 5 : a.logP - MIN_LOGP; }
 
@@ -118,7 +132,7 @@ __device__ __forceinline__ T uniform_load(const T* p) {
     return out;
 }
 
-template <int LOGP, int S, int SL>
+template <int LOGP, int S, int SL, int MODE>
 __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int cls, int start, int count) {
     constexpr int P = 1 << LOGP;
     constexpr int BLOCK = P / SL;
@@ -129,7 +143,7 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
     __shared__ double2 red_small[RED];
     __shared__ double Gs[BATCH_MAX_K];
     __shared__ double2 bc[3];
-    __shared__ int s_item, s_kbest;
+    __shared__ int s_item, s_kbest, s_fall;
     const int tid = threadIdx.x;
     double* scratch = a.scratch + static_cast<int64_t>(blockIdx.x) * MAX_N;
     for (;;) {
@@ -152,6 +166,16 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
 
         // ---- inverse transform: boundary coefficients, interior correction, core analysis
         double x1, xn;
+        double c[SL];
+        if constexpr (MODE == MODE_LEARNED) {  // coefficients left in f by the feature pass
+            x1 = f[0];
+            xn = f[n - 1];
+#pragma unroll
+            for (int k = 0; k < SL; ++k) {
+                const int j = tid + k * BLOCK;
+                c[k] = j < N ? f[j + 1] : 0.0;
+            }
+        } else {
         {
             const double y0 = g[0], y1 = g[1], yN = g[n - 2], yL = g[n - 1];
             if (kind == HT_KIND_C) {
@@ -163,7 +187,6 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
                 xn = yL / q1;
             }
         }
-        double c[SL];
         {
             auto in_inv = [&](int, int j) {
                 return make_double2(g[j + 1] - ax.q[j + 1] * x1 - ax.q[N - j] * xn, 0.0);
@@ -186,6 +209,19 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
                     if (rank > 1) c[k] -= ax.U[N + j] * a1;
                 }
             }
+        }
+        if constexpr (MODE == MODE_FEATURES) {  // the coefficient vector for the learned pass
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < SL; ++k) {
+                const int j = tid + k * BLOCK;
+                if (j < N) f[j + 1] = c[k];
+            }
+            if (tid == 0) {
+                f[0] = x1;
+                f[n - 1] = xn;
+            }
+        }
         }
 
         __builtin_amdgcn_sched_barrier(0);
@@ -237,89 +273,165 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
         }
         __syncthreads();
 
+        if constexpr (MODE == MODE_FEATURES) {
+            // band means of log10(|ghat_j|^2 + 1e-20) (64 bands) and log10(|d_j|^2 + 1e-20) (8 bands) over the
+            // normalised core frequency j / N; band b holds j with floor(B j / N) = b
+            double2* lg = lds;
+#pragma unroll
+            for (int k = 0; k < SL; ++k) {
+                const int j = tid + k * BLOCK;
+                if (j < N) lg[j] = make_double2(log10(c[k] * c[k] + 1e-20), log10(dj[k] * dj[k] + 1e-20));
+            }
+            __syncthreads();
+            if (tid < NFEAT) {
+                const int nb = tid < NFEAT_G ? NFEAT_G : NFEAT_D;
+                const int b = tid < NFEAT_G ? tid : tid - NFEAT_G;
+                const int j0 = static_cast<int>((static_cast<int64_t>(b) * N + nb - 1) / nb);
+                const int j1 = static_cast<int>((static_cast<int64_t>(b + 1) * N + nb - 1) / nb);
+                double acc = 0.0;
+                for (int j = j0; j < j1; ++j) acc += tid < NFEAT_G ? lg[j].x : lg[j].y;
+                a.feat[static_cast<int64_t>(sg.item) * NFEAT + tid] = static_cast<float>(acc / (j1 - j0));
+            }
+            __syncthreads();
+            continue;
+        }
+
         __builtin_amdgcn_sched_barrier(0);
         // ---- GCV: stage t_i = |d_i|^2 / |s_i|^2, w_i = |ghat_i|^2 (s_i = 0: no contribution)
         double2* stage = lds;
+        auto stage_fill = [&]() {
 #pragma unroll
-        for (int k = 0; k < SL; ++k) {
-            const int j = tid + k * BLOCK;
-            if (j < N) {
-                const double s2 = sj[k] * sj[k];
-                stage[j] = s2 != 0.0 ? make_double2(dj[k] * dj[k] / s2, c[k] * c[k]) : make_double2(1e150, 0.0);
-            }
-        }
-        if (tid == 0) {
-            const double s2 = s_poly * s_poly;
-            stage[N] = s2 != 0.0 ? make_double2(z0 * z0 / s2, x1 * x1) : make_double2(1e150, 0.0);
-            stage[N + 1] = s2 != 0.0 ? make_double2(z0 * z0 / s2, xn * xn) : make_double2(1e150, 0.0);
-        }
-        __syncthreads();
-        const int K = a.K;
-        const double* mus = a.mus + static_cast<int64_t>(sg.item) * K;
-        const int Kh = (K + 1) / 2;  // two grid values per thread
-        const int Kb = Kh < BLOCK ? Kh : BLOCK;
-        const int nparts = BLOCK / Kb;
-        const int part = tid / Kb, kl = tid - part * Kb;
-        const bool one_pass = Kh <= Kb;
-        double2* red = one_pass ? lds : red_small;
-        for (int k0 = 0; k0 < Kh; k0 += Kb) {
-            const int kk = k0 + kl;
-            double Na = 0.0, Da = 0.0, Nb = 0.0, Db = 0.0;
-            if (part < nparts && kk < Kh) {
-                const int ka = 2 * kk, kb2 = ka + 1 < K ? ka + 1 : ka;
-                gcv_two(stage, n, part, nparts, mus[ka], mus[kb2], Na, Da, Nb, Db);
-            }
-            if (one_pass) __syncthreads();  // the staged pairs are no longer read
-            red[2 * tid] = make_double2(Na, Da);
-            red[2 * tid + 1] = make_double2(Nb, Db);
-            __syncthreads();
-            if (part == 0 && kk < Kh) {
-                double2 A = red[2 * kl], B = red[2 * kl + 1];
-                for (int p = 1; p < nparts; ++p) {
-                    const double2 va = red[2 * (p * Kb + kl)], vb = red[2 * (p * Kb + kl) + 1];
-                    A.x += va.x;
-                    A.y += va.y;
-                    B.x += vb.x;
-                    B.y += vb.y;
-                }
-                const int ka = 2 * kk;
-                Gs[ka] = A.x / (A.y * A.y);
-                if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka] = Gs[ka];
-                if (ka + 1 < K) {
-                    Gs[ka + 1] = B.x / (B.y * B.y);
-                    if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka + 1] = Gs[ka + 1];
-                }
-            }
-            __syncthreads();
-        }
-        if (tid < 64) {  // first minimum; -1 if some G is not finite
-            double best = 0.0;
-            int bk = -1, bad = 0;
-            for (int k = tid; k < K; k += 64) {
-                const double gv = Gs[k];
-                if (!isfinite(gv)) bad = 1;
-                if (bk < 0 || gv < best) {
-                    best = gv;
-                    bk = k;
-                }
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off, 64);
-                const int ok = __shfl_xor(bk, off, 64);
-                bad |= __shfl_xor(bad, off, 64);
-                if (ok >= 0 && (bk < 0 || ob < best || (ob == best && ok < bk))) {
-                    best = ob;
-                    bk = ok;
+            for (int k = 0; k < SL; ++k) {
+                const int j = tid + k * BLOCK;
+                if (j < N) {
+                    const double s2 = sj[k] * sj[k];
+                    stage[j] = s2 != 0.0 ? make_double2(dj[k] * dj[k] / s2, c[k] * c[k]) : make_double2(1e150, 0.0);
                 }
             }
             if (tid == 0) {
-                s_kbest = bad ? -1 : bk;
-                a.kbest[sg.item] = s_kbest;
-                a.mubest[sg.item] = bad ? __builtin_nan("") : mus[bk];
+                const double s2 = s_poly * s_poly;
+                stage[N] = s2 != 0.0 ? make_double2(z0 * z0 / s2, x1 * x1) : make_double2(1e150, 0.0);
+                stage[N + 1] = s2 != 0.0 ? make_double2(z0 * z0 / s2, xn * xn) : make_double2(1e150, 0.0);
             }
+            __syncthreads();
+        };
+        const int K = a.K;
+        const double* mus = a.mus + static_cast<int64_t>(sg.item) * K;
+        double2* red = lds;  // cross-part sums (after the staged pairs are no longer read)
+        // G_k for k in [klo, khi] into Gs (and a.G); two grid values per thread
+        auto eval_range = [&](int klo, int khi) {
+            const int cnt = khi - klo + 1;
+            const int Kh = (cnt + 1) / 2;
+            const int Kb = Kh < BLOCK ? Kh : BLOCK;
+            const int nparts = BLOCK / Kb;
+            const int part = tid / Kb, kl = tid - part * Kb;
+            const bool one_pass = Kh <= Kb;
+            double2* rbuf = one_pass ? red : red_small;
+            for (int k0 = 0; k0 < Kh; k0 += Kb) {
+                const int kk = k0 + kl;
+                double Na = 0.0, Da = 0.0, Nb = 0.0, Db = 0.0;
+                if (part < nparts && kk < Kh) {
+                    const int ka = klo + 2 * kk, kb2 = ka + 1 <= khi ? ka + 1 : ka;
+                    gcv_two(stage, n, part, nparts, mus[ka], mus[kb2], Na, Da, Nb, Db);
+                }
+                if (one_pass) __syncthreads();
+                rbuf[2 * tid] = make_double2(Na, Da);
+                rbuf[2 * tid + 1] = make_double2(Nb, Db);
+                __syncthreads();
+                if (part == 0 && kk < Kh) {
+                    double2 A = rbuf[2 * kl], B = rbuf[2 * kl + 1];
+                    for (int p = 1; p < nparts; ++p) {
+                        const double2 va = rbuf[2 * (p * Kb + kl)], vb = rbuf[2 * (p * Kb + kl) + 1];
+                        A.x += va.x;
+                        A.y += va.y;
+                        B.x += vb.x;
+                        B.y += vb.y;
+                    }
+                    const int ka = klo + 2 * kk;
+                    Gs[ka] = A.x / (A.y * A.y);
+                    if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka] = Gs[ka];
+                    if (ka + 1 <= khi) {
+                        Gs[ka + 1] = B.x / (B.y * B.y);
+                        if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka + 1] = Gs[ka + 1];
+                    }
+                }
+                __syncthreads();
+            }
+        };
+        // first minimum over [klo, khi]; -1 if some G is not finite
+        auto argmin_range = [&](int klo, int khi) {
+            if (tid < 64) {
+                double best = 0.0;
+                int bk = -1, bad = 0;
+                for (int k = klo + tid; k <= khi; k += 64) {
+                    const double gv = Gs[k];
+                    if (!isfinite(gv)) bad = 1;
+                    if (bk < 0 || gv < best) {
+                        best = gv;
+                        bk = k;
+                    }
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double ob = __shfl_xor(best, off, 64);
+                    const int ok = __shfl_xor(bk, off, 64);
+                    bad |= __shfl_xor(bad, off, 64);
+                    if (ok >= 0 && (bk < 0 || ob < best || (ob == best && ok < bk))) {
+                        best = ob;
+                        bk = ok;
+                    }
+                }
+                if (tid == 0) s_kbest = bad ? -1 : bk;
+            }
+            __syncthreads();
+            return __builtin_amdgcn_readfirstlane(s_kbest);
+        };
+        int kstar;
+        if constexpr (MODE == MODE_LEARNED) {
+            // nearest grid index to the prediction, then the certificate bracket
+            if (tid == 0) {
+                const double pr = static_cast<double>(a.pred[sg.item]);
+                int kh = 0;
+                double bd = fabs(log10(mus[0]) - pr);
+                for (int k = 1; k < K; ++k) {
+                    const double dd = fabs(log10(mus[k]) - pr);
+                    if (dd < bd) {
+                        bd = dd;
+                        kh = k;
+                    }
+                }
+                s_item = kh;  // reused as a broadcast slot (the queue index was already read)
+            }
+            __syncthreads();
+            const int khat = __builtin_amdgcn_readfirstlane(s_item);
+            __syncthreads();
+            const int half = a.cert_half;
+            const int lo = khat - half < 0 ? 0 : khat - half;
+            const int hi = khat + half > K - 1 ? K - 1 : khat + half;
+            stage_fill();
+            eval_range(lo, hi);
+            const int km = argmin_range(lo, hi);
+            const bool edge = (km == lo && lo > 0) || (km == hi && hi < K - 1);
+            const bool ok = km >= 0 && !edge && Gs[khat] <= CERT_SLACK * Gs[km];
+            if (ok) {
+                kstar = km;
+            } else {
+                __syncthreads();
+                stage_fill();  // the reduction above reused the staging buffer
+                eval_range(0, K - 1);
+                kstar = argmin_range(0, K - 1);
+            }
+            if (tid == 0) a.fallback[sg.item] = ok ? 0 : 1;
+        } else {
+            stage_fill();
+            eval_range(0, K - 1);
+            kstar = argmin_range(0, K - 1);
+        }
+        if (tid == 0) {
+            a.kbest[sg.item] = kstar;
+            a.mubest[sg.item] = kstar >= 0 ? mus[kstar] : __builtin_nan("");
         }
         __syncthreads();
-        const int kb = __builtin_amdgcn_readfirstlane(s_kbest);
+        const int kb = kstar;
         const double mu_s = kb >= 0 ? mus[kb] : __builtin_nan("");
 
         __builtin_amdgcn_sched_barrier(0);
@@ -392,6 +504,7 @@ struct ht_batch {
     int grid[NCLASS] = {0};         // persistent workgroups per class (schedule)
     int variant[NCLASS] = {0};      // 0: 8 points per thread, 1: 16 (FFT lengths >= 4096 only)
     unsigned class_mask = (1u << NCLASS) - 1;  // size classes ht_batch_restore runs
+    int64_t min_n = 0;
 };
 
 namespace {
@@ -404,7 +517,8 @@ bool has_variant(int c) { return class_logp(c) >= 12; }
 template <int LOGP, int S, int SL>
 int max_active(int device) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_restore<LOGP, S, SL>, (1 << LOGP) / SL, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_restore<LOGP, S, SL, MODE_SCAN>, (1 << LOGP) / SL, 0) !=
+        hipSuccess)
         nb = 1;
     hipDeviceProp_t prop;
     int cus = 256;
@@ -424,31 +538,49 @@ int full_grid(int cls, int variant, int device) {
 }
 
 template <int LOGP, int S, int SL>
-void launch_class(const RaggedArgs& a, int c, int start, int cnt, int grid, const double2* tw, hipStream_t stream) {
-    (void)tw;
-    hipLaunchKernelGGL((k_restore<LOGP, S, SL>), dim3(static_cast<unsigned>(grid)), dim3((1 << LOGP) / SL), 0, stream,
-                       a, c, start, cnt);
+void launch_class(const RaggedArgs& a, int mode, int c, int start, int cnt, int grid, hipStream_t stream) {
+    const dim3 g(static_cast<unsigned>(grid)), b((1 << LOGP) / SL);
+    if (mode == MODE_FEATURES)
+        hipLaunchKernelGGL((k_restore<LOGP, S, SL, MODE_FEATURES>), g, b, 0, stream, a, c, start, cnt);
+    else if (mode == MODE_LEARNED)
+        hipLaunchKernelGGL((k_restore<LOGP, S, SL, MODE_LEARNED>), g, b, 0, stream, a, c, start, cnt);
+    else
+        hipLaunchKernelGGL((k_restore<LOGP, S, SL, MODE_SCAN>), g, b, 0, stream, a, c, start, cnt);
 }
 
-void launch_any(const RaggedArgs& a, int c, int variant, int start, int cnt, int grid, const double2* tw,
-                hipStream_t stream) {
+void launch_any(const RaggedArgs& a, int mode, int c, int variant, int start, int cnt, int grid, hipStream_t stream) {
     switch (c) {
-        case 0: launch_class<9, 1, 8>(a, c, start, cnt, grid, tw, stream); break;
-        case 1: launch_class<10, 1, 8>(a, c, start, cnt, grid, tw, stream); break;
-        case 2: launch_class<11, 1, 8>(a, c, start, cnt, grid, tw, stream); break;
+        case 0: launch_class<9, 1, 8>(a, mode, c, start, cnt, grid, stream); break;
+        case 1: launch_class<10, 1, 8>(a, mode, c, start, cnt, grid, stream); break;
+        case 2: launch_class<11, 1, 8>(a, mode, c, start, cnt, grid, stream); break;
         case 3:
-            if (variant) launch_class<12, 1, 16>(a, c, start, cnt, grid, tw, stream);
-            else launch_class<12, 1, 8>(a, c, start, cnt, grid, tw, stream);
+            if (variant) launch_class<12, 1, 16>(a, mode, c, start, cnt, grid, stream);
+            else launch_class<12, 1, 8>(a, mode, c, start, cnt, grid, stream);
             break;
         case 4:
-            if (variant) launch_class<13, 1, 16>(a, c, start, cnt, grid, tw, stream);
-            else launch_class<13, 1, 8>(a, c, start, cnt, grid, tw, stream);
+            if (variant) launch_class<13, 1, 16>(a, mode, c, start, cnt, grid, stream);
+            else launch_class<13, 1, 8>(a, mode, c, start, cnt, grid, stream);
             break;
         default:
-            if (variant) launch_class<13, 2, 16>(a, c, start, cnt, grid, tw, stream);
-            else launch_class<13, 2, 8>(a, c, start, cnt, grid, tw, stream);
+            if (variant) launch_class<13, 2, 16>(a, mode, c, start, cnt, grid, stream);
+            else launch_class<13, 2, 8>(a, mode, c, start, cnt, grid, stream);
             break;
     }
+}
+
+ht_status run_classes(const ht_batch* bt, const RaggedArgs& a, int mode, hipStream_t stream) {
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, stream, bt->d_counters);
+    ht_status st = check_hip(hipGetLastError(), "batch counter reset");
+    if (st != HT_OK) return st;
+    // largest class first: its signals dominate the run time
+    for (int c = NCLASS - 1; c >= 0; --c) {
+        const int cnt = bt->class_count[c];
+        if (cnt == 0 || !(bt->class_mask & (1u << c))) continue;
+        launch_any(a, mode, c, bt->variant[c], bt->class_start[c], cnt, bt->grid[c], stream);
+        st = check_hip(hipGetLastError(), "batch launch");
+        if (st != HT_OK) return st;
+    }
+    return HT_OK;
 }
 
 }  // namespace
@@ -530,6 +662,7 @@ extern "C" ht_status ht_batch_create(int64_t count, const int64_t* n, const int*
     }
     bt->total_n = acc;
     bt->total_psf = pacc;
+    bt->min_n = *std::min_element(n, n + count);
     std::vector<RSig> sigs(count);
     for (int64_t b = 0; b < count; ++b)
         sigs[b] = RSig{off[b], poff[b], static_cast<int32_t>(psf_len[b]), static_cast<int32_t>(psf_center[b]),
@@ -563,11 +696,11 @@ extern "C" ht_status ht_batch_create(int64_t count, const int64_t* n, const int*
 
 extern "C" ht_status ht_batch_destroy(ht_batch* bt) {
     if (!bt) return HT_OK;
-    if (bt->arena) hipFree(bt->arena);
-    if (bt->d_axes) hipFree(bt->d_axes);
-    if (bt->d_sigs) hipFree(bt->d_sigs);
-    if (bt->d_counters) hipFree(bt->d_counters);
-    if (bt->d_scratch) hipFree(bt->d_scratch);
+    if (bt->arena) (void)hipFree(bt->arena);
+    if (bt->d_axes) (void)hipFree(bt->d_axes);
+    if (bt->d_sigs) (void)hipFree(bt->d_sigs);
+    if (bt->d_counters) (void)hipFree(bt->d_counters);
+    if (bt->d_scratch) (void)hipFree(bt->d_scratch);
     delete bt;
     return HT_OK;
 }
@@ -614,17 +747,34 @@ extern "C" ht_status ht_batch_restore(const ht_batch* bt, const double* signal, 
     if (K < 1 || K > BATCH_MAX_K) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore: K must be in [1, 256]");
     if (signal == restored) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore: signal and restored must not overlap");
     RaggedArgs a{bt->d_axes, bt->d_sigs, bt->d_counters, signal, psf, mu_grid, K, norm, restored, G, k_best, mu_best,
-                 bt->d_scratch};
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, stream, bt->d_counters);
-    ht_status st = check_hip(hipGetLastError(), "ht_batch_restore reset");
-    if (st != HT_OK) return st;
-    // largest class first: its signals dominate the run time
-    for (int c = NCLASS - 1; c >= 0; --c) {
-        const int cnt = bt->class_count[c];
-        if (cnt == 0 || !(bt->class_mask & (1u << c))) continue;
-        launch_any(a, c, bt->variant[c], bt->class_start[c], cnt, bt->grid[c], bt->tw, stream);
-        st = check_hip(hipGetLastError(), "ht_batch_restore launch");
-        if (st != HT_OK) return st;
-    }
-    return HT_OK;
+                 bt->d_scratch, nullptr, nullptr, nullptr};
+    return run_classes(bt, a, MODE_SCAN, stream);
+}
+
+extern "C" ht_status ht_batch_features(const ht_batch* bt, const double* signal, const double* psf, double* coeff,
+                                       float* features, hipStream_t stream) {
+    if (!bt) return fail(HT_ERR_INVALID_ARG, "ht_batch_features: null batch");
+    if (!signal || !psf || !coeff || !features) return fail(HT_ERR_INVALID_ARG, "ht_batch_features: null argument");
+    if (signal == coeff) return fail(HT_ERR_INVALID_ARG, "ht_batch_features: signal and coeff must not overlap");
+    if (bt->min_n < NFEAT_G + 2) return fail(HT_ERR_UNSUPPORTED, "ht_batch_features: needs n >= 66 (64 bands)");
+    RaggedArgs a{bt->d_axes, bt->d_sigs, bt->d_counters, signal, psf, nullptr, 1, HT_NORM_SECOND_DIFF, coeff, nullptr,
+                 nullptr, nullptr, bt->d_scratch, nullptr, nullptr, features, 0};
+    return run_classes(bt, a, MODE_FEATURES, stream);
+}
+
+extern "C" ht_status ht_batch_restore_learned(const ht_batch* bt, double* coeff_restored, const double* psf, int norm,
+                                              const double* mu_grid, int32_t K, const float* pred_log10_mu,
+                                              int32_t cert_half, double* G, int32_t* k_best, double* mu_best,
+                                              int32_t* fallback, hipStream_t stream) {
+    if (!bt) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_learned: null batch");
+    if (!coeff_restored || !psf || !mu_grid || !pred_log10_mu || !k_best || !mu_best || !fallback)
+        return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_learned: null argument");
+    if (norm != HT_NORM_IDENTITY && norm != HT_NORM_SECOND_DIFF)
+        return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_learned: bad norm");
+    if (K < 1 || K > BATCH_MAX_K) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_learned: K must be in [1, 256]");
+    if (cert_half < 1 || cert_half >= K)
+        return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_learned: cert_half must be in [1, K-1]");
+    RaggedArgs a{bt->d_axes, bt->d_sigs, bt->d_counters, nullptr, psf, mu_grid, K, norm, coeff_restored, G, k_best,
+                 mu_best, bt->d_scratch, pred_log10_mu, fallback, nullptr, cert_half};
+    return run_classes(bt, a, MODE_LEARNED, stream);
 }

@@ -1,0 +1,256 @@
+// Kernels of the learned-mu predictor: a small MLP trained and evaluated on the GPU.
+//
+//   GEMM      C = act(A B + bias) with A, B in bfloat16 and float32 accumulation on the
+//             matrix cores (v_mfma_f32_16x16x16bf16_1k): one wave per 16 x 16 output tile,
+//             A and B addressed through strides so that transposed operands need no copy
+//   GELU      exact, 0.5 x (1 + erf(x / sqrt 2)); derivative Phi(x) + x phi(x)
+//   reductions column sums (bias gradients) in a fixed order: deterministic
+//   Adam      float32 master weights and moments, bfloat16 copies for the GEMMs
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ht_internal.h"
+
+namespace ht {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return static_cast<uint16_t>(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float x) {
+    const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
+    const float pdf = 0.39894228040143268f * expf(-0.5f * x * x);
+    return cdf + x * pdf;
+}
+
+struct Gemm {
+    int M, N, K;
+    const uint16_t* A;
+    int64_t sa_i, sa_k;
+    const uint16_t* B;
+    int64_t sb_k, sb_j;
+    const float* bias;  // [N] or null
+    int act;            // 0: none, 1: GELU
+    float* Z;           // pre-activation out (may be null)
+    float* C;           // activated out (may be null)
+    int64_t ldc;
+    uint16_t* Cb;       // bfloat16 copy of the activated out (may be null)
+};
+
+// One wave computes C[ti*16 .. +16][tj*16 .. +16]; operands outside the matrices read 0.
+// Lane l supplies A rows l % 16, k = 4 (l / 16) + 0..3 and B columns l % 16, same k, and
+// receives D rows 4 (l / 16) + 0..3 of column l % 16.
+__global__ __launch_bounds__(256) void k_gemm(Gemm g) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int ntj = (g.N + 15) / 16;
+    const int ntiles = ((g.M + 15) / 16) * ntj;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= ntiles) return;
+    const int ti = tile / ntj, tj = tile - ti * ntj;
+    const int r = lane & 15, q = lane >> 4;
+    const int ai = ti * 16 + r, bj = tj * 16 + r;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < g.K; k0 += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = k0 + 4 * q + i;
+            const bool ka = ai < g.M && k < g.K, kb = bj < g.N && k < g.K;
+            a[i] = ka ? static_cast<short>(g.A[ai * g.sa_i + k * g.sa_k]) : static_cast<short>(0);
+            b[i] = kb ? static_cast<short>(g.B[k * g.sb_k + bj * g.sb_j]) : static_cast<short>(0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    const int cj = tj * 16 + r;
+    if (cj >= g.N) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int ci = ti * 16 + 4 * q + i;
+        if (ci >= g.M) continue;
+        float z = acc[i] + (g.bias ? g.bias[cj] : 0.0f);
+        if (g.Z) g.Z[ci * g.ldc + cj] = z;
+        const float y = g.act ? gelu(z) : z;
+        const uint16_t yb = f32_to_bf16(y);
+        if (g.C) g.C[ci * g.ldc + cj] = g.Cb ? bf16_to_f32(yb) : y;
+        if (g.Cb) g.Cb[ci * g.ldc + cj] = yb;
+    }
+}
+
+// dst = bf16((src - mean[col]) / std[col]) (mean/std may be null: plain conversion)
+__global__ void k_to_bf16(const float* src, uint16_t* dst, int64_t rows, int cols, const float* mean,
+                          const float* stdv) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= rows * cols) return;
+    const int c = static_cast<int>(i % cols);
+    float v = src[i];
+    if (mean) v = (v - mean[c]) / stdv[c];
+    dst[i] = f32_to_bf16(v);
+}
+
+__global__ void k_from_bf16(const uint16_t* src, float* dst, int64_t count) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = bf16_to_f32(src[i]);
+}
+
+// dz = dh * GELU'(z); also the bfloat16 copy used by the next GEMMs
+__global__ void k_gelu_bwd(const float* z, const float* dh, float* dz, uint16_t* dzb, int64_t count) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float v = dh[i] * gelu_grad(z[i]);
+    dz[i] = v;
+    if (dzb) dzb[i] = f32_to_bf16(v);
+}
+
+// out[j] = sum_i X[i][j] (rows summed in a fixed tree order): one block per column
+__global__ __launch_bounds__(256) void k_colsum(const float* X, int64_t rows, int cols, float* out) {
+    __shared__ float part[256];
+    const int j = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t i = threadIdx.x; i < rows; i += 256) s += X[i * cols + j];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = part[0];
+}
+
+// dy = 2 (y - t) / B (mean squared error), and the per-row squared errors
+__global__ void k_mse_grad(const float* y, const float* t, float* dy, float* sq, int64_t rows) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    const float e = y[i] - t[i];
+    dy[i] = 2.0f * e / static_cast<float>(rows);
+    sq[i] = e * e;
+}
+
+// dh[i][j] = dy[i] * w[j]  (gradient through the last, one-output layer)
+__global__ void k_outer(const float* dy, const float* w, float* dh, int64_t rows, int cols) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= rows * cols) return;
+    dh[i] = dy[i / cols] * w[i % cols];
+}
+
+// X[i][j] * y[i] summed over i: gradient of a one-output layer's weights
+__global__ __launch_bounds__(256) void k_weighted_colsum(const float* X, const float* y, int64_t rows, int cols,
+                                                         float* out) {
+    __shared__ float part[256];
+    const int j = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t i = threadIdx.x; i < rows; i += 256) s += X[i * cols + j] * y[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = part[0];
+}
+
+__global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2,
+                       float eps, float c1, float c2, uint16_t* pb) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float upd = lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    const float pi = p[i] - upd;
+    p[i] = pi;
+    if (pb) pb[i] = f32_to_bf16(pi);
+}
+
+static unsigned blocks_for(int64_t n, int t = 256) { return static_cast<unsigned>((n + t - 1) / t); }
+
+}  // namespace ht
+
+using namespace ht;
+
+extern "C" ht_status ht_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t sa_i, int64_t sa_k,
+                                  const uint16_t* B, int64_t sb_k, int64_t sb_j, const float* bias, int act,
+                                  float* Z, float* C, int64_t ldc, uint16_t* Cb, hipStream_t stream) {
+    if (M < 0 || N < 0 || K < 0 || (act != 0 && act != 1)) return fail(HT_ERR_INVALID_ARG, "ht_gemm_bf16: bad sizes");
+    if (M == 0 || N == 0) return HT_OK;
+    if (!A || !B || (!Z && !C && !Cb) || ldc < N) return fail(HT_ERR_INVALID_ARG, "ht_gemm_bf16: null argument or ldc < N");
+    const int64_t tiles = static_cast<int64_t>((M + 15) / 16) * ((N + 15) / 16);
+    if (tiles > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_gemm_bf16: too large");
+    Gemm g{M, N, K, A, sa_i, sa_k, B, sb_k, sb_j, bias, act, Z, C, ldc, Cb};
+    hipLaunchKernelGGL(k_gemm, dim3(static_cast<unsigned>((tiles + 3) / 4)), dim3(256), 0, stream, g);
+    return check_hip(hipGetLastError(), "ht_gemm_bf16 launch");
+}
+
+extern "C" ht_status ht_to_bf16(const float* src, uint16_t* dst, int64_t rows, int cols, const float* mean,
+                                const float* stdv, hipStream_t stream) {
+    if (rows < 0 || cols < 1 || (!mean) != (!stdv)) return fail(HT_ERR_INVALID_ARG, "ht_to_bf16: bad argument");
+    if (rows == 0) return HT_OK;
+    if (!src || !dst) return fail(HT_ERR_INVALID_ARG, "ht_to_bf16: null argument");
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(rows * cols)), dim3(256), 0, stream, src, dst, rows, cols, mean, stdv);
+    return check_hip(hipGetLastError(), "ht_to_bf16 launch");
+}
+
+extern "C" ht_status ht_from_bf16(const uint16_t* src, float* dst, int64_t count, hipStream_t stream) {
+    if (count < 0) return fail(HT_ERR_INVALID_ARG, "ht_from_bf16: bad count");
+    if (count == 0) return HT_OK;
+    if (!src || !dst) return fail(HT_ERR_INVALID_ARG, "ht_from_bf16: null argument");
+    hipLaunchKernelGGL(k_from_bf16, dim3(blocks_for(count)), dim3(256), 0, stream, src, dst, count);
+    return check_hip(hipGetLastError(), "ht_from_bf16 launch");
+}
+
+extern "C" ht_status ht_gelu_backward(const float* z, const float* dh, float* dz, uint16_t* dzb, int64_t count,
+                                      hipStream_t stream) {
+    if (count < 0) return fail(HT_ERR_INVALID_ARG, "ht_gelu_backward: bad count");
+    if (count == 0) return HT_OK;
+    if (!z || !dh || !dz) return fail(HT_ERR_INVALID_ARG, "ht_gelu_backward: null argument");
+    hipLaunchKernelGGL(k_gelu_bwd, dim3(blocks_for(count)), dim3(256), 0, stream, z, dh, dz, dzb, count);
+    return check_hip(hipGetLastError(), "ht_gelu_backward launch");
+}
+
+extern "C" ht_status ht_colsum(const float* X, int64_t rows, int cols, const float* weight, float* out,
+                               hipStream_t stream) {
+    if (rows < 0 || cols < 1 || cols > 65535 || !X || !out) return fail(HT_ERR_INVALID_ARG, "ht_colsum: bad argument");
+    if (weight)
+        hipLaunchKernelGGL(k_weighted_colsum, dim3(cols), dim3(256), 0, stream, X, weight, rows, cols, out);
+    else
+        hipLaunchKernelGGL(k_colsum, dim3(cols), dim3(256), 0, stream, X, rows, cols, out);
+    return check_hip(hipGetLastError(), "ht_colsum launch");
+}
+
+extern "C" ht_status ht_mse_grad(const float* y, const float* t, float* dy, float* sq, int64_t rows,
+                                 hipStream_t stream) {
+    if (rows < 1 || !y || !t || !dy || !sq) return fail(HT_ERR_INVALID_ARG, "ht_mse_grad: bad argument");
+    hipLaunchKernelGGL(k_mse_grad, dim3(blocks_for(rows)), dim3(256), 0, stream, y, t, dy, sq, rows);
+    return check_hip(hipGetLastError(), "ht_mse_grad launch");
+}
+
+extern "C" ht_status ht_outer(const float* dy, const float* w, float* dh, int64_t rows, int cols, hipStream_t stream) {
+    if (rows < 0 || cols < 1 || !dy || !w || !dh) return fail(HT_ERR_INVALID_ARG, "ht_outer: bad argument");
+    if (rows == 0) return HT_OK;
+    hipLaunchKernelGGL(k_outer, dim3(blocks_for(rows * cols)), dim3(256), 0, stream, dy, w, dh, rows, cols);
+    return check_hip(hipGetLastError(), "ht_outer launch");
+}
+
+extern "C" ht_status ht_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float beta1,
+                             float beta2, float eps, int64_t step, uint16_t* pb, hipStream_t stream) {
+    if (count < 0 || step < 1 || !p || !g || !m || !v) return fail(HT_ERR_INVALID_ARG, "ht_adam: bad argument");
+    if (count == 0) return HT_OK;
+    const float c1 = 1.0f - powf(beta1, static_cast<float>(step));
+    const float c2 = 1.0f - powf(beta2, static_cast<float>(step));
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(count)), dim3(256), 0, stream, p, g, m, v, count, lr, beta1, beta2, eps,
+                       c1, c2, pb);
+    return check_hip(hipGetLastError(), "ht_adam launch");
+}

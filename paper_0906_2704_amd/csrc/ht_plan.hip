@@ -73,7 +73,7 @@ const double2* device_twiddles(int device, ht_status* st) {
         return nullptr;
     }
     if (hipMemcpy(dptr, h.data(), sizeof(double2) * TWN, hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(dptr);
+        (void)hipFree(dptr);
         *st = fail(HT_ERR_HIP, "device twiddle table upload failed");
         return nullptr;
     }
@@ -381,7 +381,7 @@ ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* a
     char* dev = nullptr;
     if (hipMalloc(&dev, bytes) != hipSuccess) return fail(HT_ERR_OOM, "table allocation failed");
     if (hipMemcpy(dev, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(dev);
+        (void)hipFree(dev);
         return fail(HT_ERR_HIP, "table upload failed");
     }
     *arena_out = dev;
@@ -458,9 +458,9 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
 
 extern "C" ht_status ht_plan_destroy(ht_plan* p) {
     if (!p) return HT_OK;
-    if (p->arena) hipFree(p->arena);
-    if (p->work) hipFree(p->work);
-    if (p->gcv_part) hipFree(p->gcv_part);
+    if (p->arena) (void)hipFree(p->arena);
+    if (p->work) (void)hipFree(p->work);
+    if (p->gcv_part) (void)hipFree(p->gcv_part);
     delete p;
     return HT_OK;
 }

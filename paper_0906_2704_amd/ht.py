@@ -298,3 +298,121 @@ def ht_batch_restore(batch, signal, psf, norm, mu_grid, restored=None, G=None, k
                               _ptr(kb, torch.int32, "k_best"), _ptr(mb, torch.float64, "mu_best"), _stream()),
            "ht_batch_restore")
     return restored, G, kb, mb
+
+
+# ----------------------------------------------------------------------------- learned mu
+
+def _learned_sigs(L):
+    I64, I32, VP, F = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_float
+    Ci = ctypes.c_int
+    L.ht_batch_features.argtypes = [VP, VP, VP, VP, VP, VP]
+    L.ht_batch_restore_learned.argtypes = [VP, VP, VP, Ci, VP, I32, VP, I32, VP, VP, VP, VP, VP]
+    L.ht_gemm_bf16.argtypes = [Ci, Ci, Ci, VP, I64, I64, VP, I64, I64, VP, Ci, VP, VP, I64, VP, VP]
+    L.ht_to_bf16.argtypes = [VP, VP, I64, Ci, VP, VP, VP]
+    L.ht_from_bf16.argtypes = [VP, VP, I64, VP]
+    L.ht_gelu_backward.argtypes = [VP, VP, VP, VP, I64, VP]
+    L.ht_colsum.argtypes = [VP, I64, Ci, VP, VP, VP]
+    L.ht_mse_grad.argtypes = [VP, VP, VP, VP, I64, VP]
+    L.ht_outer.argtypes = [VP, VP, VP, I64, Ci, VP]
+    L.ht_adam.argtypes = [VP, VP, VP, VP, I64, F, F, F, F, I64, VP, VP]
+    for name in ("ht_batch_features", "ht_batch_restore_learned", "ht_gemm_bf16", "ht_to_bf16", "ht_from_bf16",
+                 "ht_gelu_backward", "ht_colsum", "ht_mse_grad", "ht_outer", "ht_adam"):
+        getattr(L, name).restype = ctypes.c_int
+
+
+def _llib():
+    L = lib()
+    if not hasattr(L, "_learned_ready"):
+        _learned_sigs(L)
+        L._learned_ready = True
+    return L
+
+
+def _p(t, name, dtype=None):
+    if t is None:
+        return None
+    if dtype is not None and t.dtype != dtype:
+        raise HTError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_cuda or not t.is_contiguous():
+        raise HTError("%s must be a contiguous device tensor" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+BF16 = torch.bfloat16
+
+
+def ht_batch_features(batch, signal, psf, coeff=None, features=None):
+    L = _llib()
+    dev = signal.device
+    if coeff is None:
+        coeff = torch.empty(batch.total_length, dtype=torch.float64, device=dev)
+    if features is None:
+        features = torch.empty((batch.count, 72), dtype=torch.float32, device=dev)
+    _check(L.ht_batch_features(batch.handle, _p(signal, "signal", torch.float64), _p(psf, "psf", torch.float64),
+                               _p(coeff, "coeff", torch.float64), _p(features, "features", torch.float32), _stream()),
+           "ht_batch_features")
+    return coeff, features
+
+
+def ht_batch_restore_learned(batch, coeff, psf, norm, mu_grid, pred, cert_half=8, G=None, kb=None, mb=None,
+                             fallback=None):
+    """coeff (from ht_batch_features) is overwritten with the restorations."""
+    L = _llib()
+    dev = coeff.device
+    K = mu_grid.shape[-1]
+    kb = torch.empty(batch.count, dtype=torch.int32, device=dev) if kb is None else kb
+    mb = torch.empty(batch.count, dtype=torch.float64, device=dev) if mb is None else mb
+    fallback = torch.empty(batch.count, dtype=torch.int32, device=dev) if fallback is None else fallback
+    _check(L.ht_batch_restore_learned(batch.handle, _p(coeff, "coeff", torch.float64), _p(psf, "psf", torch.float64),
+                                      NORMS.get(norm, norm), _p(mu_grid, "mu_grid", torch.float64), int(K),
+                                      _p(pred, "pred", torch.float32), int(cert_half), _p(G, "G", torch.float64),
+                                      _p(kb, "k_best", torch.int32), _p(mb, "mu_best", torch.float64),
+                                      _p(fallback, "fallback", torch.int32), _stream()), "ht_batch_restore_learned")
+    return coeff, kb, mb, fallback
+
+
+def ht_gemm_bf16(M, N, K, A, sa, B, sb, bias=None, act=0, Z=None, C=None, Cb=None, ldc=None):
+    """C = act(A B + bias); A(i,k) = A[i sa[0] + k sa[1]], B(k,j) = B[k sb[0] + j sb[1]]."""
+    L = _llib()
+    _check(L.ht_gemm_bf16(int(M), int(N), int(K), _p(A, "A", BF16), int(sa[0]), int(sa[1]), _p(B, "B", BF16),
+                          int(sb[0]), int(sb[1]), _p(bias, "bias", torch.float32), int(act),
+                          _p(Z, "Z", torch.float32), _p(C, "C", torch.float32), int(ldc if ldc is not None else N),
+                          _p(Cb, "Cb", BF16), _stream()), "ht_gemm_bf16")
+
+
+def ht_to_bf16(src, dst, rows, cols, mean=None, std=None):
+    _check(_llib().ht_to_bf16(_p(src, "src", torch.float32), _p(dst, "dst", BF16), int(rows), int(cols),
+                              _p(mean, "mean", torch.float32), _p(std, "std", torch.float32), _stream()),
+           "ht_to_bf16")
+
+
+def ht_from_bf16(src, dst):
+    _check(_llib().ht_from_bf16(_p(src, "src", BF16), _p(dst, "dst", torch.float32), src.numel(), _stream()),
+           "ht_from_bf16")
+
+
+def ht_gelu_backward(z, dh, dz, dzb=None):
+    _check(_llib().ht_gelu_backward(_p(z, "z", torch.float32), _p(dh, "dh", torch.float32),
+                                    _p(dz, "dz", torch.float32), _p(dzb, "dzb", BF16), z.numel(), _stream()),
+           "ht_gelu_backward")
+
+
+def ht_colsum(X, rows, cols, out, weight=None):
+    _check(_llib().ht_colsum(_p(X, "X", torch.float32), int(rows), int(cols), _p(weight, "weight", torch.float32),
+                             _p(out, "out", torch.float32), _stream()), "ht_colsum")
+
+
+def ht_mse_grad(y, t, dy, sq):
+    _check(_llib().ht_mse_grad(_p(y, "y", torch.float32), _p(t, "t", torch.float32), _p(dy, "dy", torch.float32),
+                               _p(sq, "sq", torch.float32), y.numel(), _stream()), "ht_mse_grad")
+
+
+def ht_outer(dy, w, dh, rows, cols):
+    _check(_llib().ht_outer(_p(dy, "dy", torch.float32), _p(w, "w", torch.float32), _p(dh, "dh", torch.float32),
+                            int(rows), int(cols), _stream()), "ht_outer")
+
+
+def ht_adam(p, g, m, v, lr, step, pb=None, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(_llib().ht_adam(_p(p, "p", torch.float32), _p(g, "g", torch.float32), _p(m, "m", torch.float32),
+                           _p(v, "v", torch.float32), p.numel(), float(lr), float(beta1), float(beta2), float(eps),
+                           int(step), _p(pb, "pb", BF16), _stream()), "ht_adam")

@@ -75,6 +75,9 @@ def observe_1d(f_ext, h, center, n):
     h = np.asarray(h, dtype=np.float64)
     ml, mr = int(center), h.size - 1 - int(center)
     assert f_ext.shape[-1] == n + ml + mr
+    if f_ext.ndim == 1:
+        # 'valid' convolution: output i sums h[idx] f_ext[i + mr - (idx - center)]
+        return np.convolve(f_ext, h, mode="valid")
     g = np.zeros(f_ext.shape[:-1] + (n,))
     for idx in range(h.size):
         j = idx - center
@@ -194,11 +197,12 @@ class RaggedBatch:
 
 
 def ragged_batch(count=4096, n_lo=128, n_hi=8192, K=128, degrees=(1, 2, 3), config=2,
-                 first_item=0, sort_desc=True, n_values=None):
+                 first_item=0, sort_desc=True, n_values=None, grid=None):
     """Batched workload: n ~ U{n_lo..n_hi}; Gaussian (sigma = m/3) or box PSF with equal
     probability, half-width m ~ U{2..32}; noise level log-uniform in [0.1%, 5%]; degree
     uniform over `degrees`; per-signal grid of K log-spaced mu on [10^lo, 10^(lo+7)],
-    lo ~ U(-8, -6).  Signals are 4 random cubic pieces.  Sorted by n, longest first."""
+    lo ~ U(-8, -6) (or the fixed grid 10^grid[0] .. 10^grid[1]).  Signals are 4 random cubic
+    pieces.  Sorted by n, longest first (unless sort_desc is False)."""
     items = []
     for b in range(count):
         rng = rng_for(config, first_item + b)
@@ -212,7 +216,7 @@ def ragged_batch(count=4096, n_lo=128, n_hi=8192, K=128, degrees=(1, 2, 3), conf
         eta = float(10.0 ** rng.uniform(-3.0, np.log10(0.05)))
         deg = int(degrees[int(rng.integers(0, len(degrees)))])
         lo = float(rng.uniform(-8.0, -6.0))
-        mus = mu_grid(lo, lo + 7.0, K)
+        mus = mu_grid(lo, lo + 7.0, K) if grid is None else mu_grid(grid[0], grid[1], K)
         f_ext = piecewise_poly(rng, n + 2 * m, 4, 3)
         g = add_noise(rng, observe_1d(f_ext, h, c, n), eta)
         items.append((n, g, f_ext[m:m + n], deg, (h, c), eta, mus))
@@ -236,3 +240,10 @@ def ragged_batch(count=4096, n_lo=128, n_hi=8192, K=128, degrees=(1, 2, 3), conf
         eta=np.array([t[5] for t in items]),
         mus=np.stack([t[6] for t in items]),
     )
+
+
+def learned_batch(count, first_item=0, K=128, grid=(-8.0, 1.0)):
+    """Learned-mu workload: signals as the batched workload with n ~ U{256..4096} and the
+    fixed grid of K log-spaced mu on [1e-8, 10]; item order kept."""
+    return ragged_batch(count, n_lo=256, n_hi=4096, K=K, config=4, first_item=first_item, sort_desc=False,
+                        grid=grid)

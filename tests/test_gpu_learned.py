@@ -1,0 +1,168 @@
+"""GPU checks of the learned-mu path: the bfloat16 matrix-core GEMM against exact products,
+the network's forward and backward kernels against the float64 oracle (same bfloat16
+rounding points), Adam, the feature kernel and the certified restore against the oracle,
+and what the trained network gains over the plain scan."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import learned as olearned
+from oracle import mlp as omlp
+from oracle import tikhonov as tk
+from oracle import transforms as tr
+from paper_0906_2704_amd import synth
+
+from parity import rel_normwise
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def ht():
+    from paper_0906_2704_amd import ht as _ht
+    _ht.lib()
+    return _ht
+
+
+def bf16_tensor(a):
+    return torch.tensor(np.asarray(a, dtype=np.float32), device=DEV).to(torch.bfloat16)
+
+
+@pytest.mark.parametrize("M,N,K", [(16, 16, 16), (37, 50, 70), (130, 3, 257)])
+def test_gemm_matches_exact_products(ht, M, N, K):
+    rng = np.random.default_rng(M * N + K)
+    # small integers times powers of two: exact in bfloat16, products exact in float32
+    A = rng.integers(-8, 9, (M, K)) * 0.25
+    B = rng.integers(-8, 9, (K, N)) * 0.125
+    bias = rng.standard_normal(N).astype(np.float32)
+    C = torch.empty((M, N), dtype=torch.float32, device=DEV)
+    ht.ht_gemm_bf16(M, N, K, bf16_tensor(A), (K, 1), bf16_tensor(B), (N, 1), bias=torch.tensor(bias, device=DEV),
+                    C=C)
+    want = A @ B + bias
+    assert np.max(np.abs(C.cpu().numpy() - want)) <= 1e-6 * max(1.0, np.max(np.abs(want)))
+    # transposed operands through strides, GELU epilogue and the bfloat16 copy
+    At = bf16_tensor(A.T.copy())
+    Bt = bf16_tensor(B.T.copy())
+    Z = torch.empty((M, N), dtype=torch.float32, device=DEV)
+    Cb = torch.empty((M, N), dtype=torch.bfloat16, device=DEV)
+    ht.ht_gemm_bf16(M, N, K, At, (1, M), Bt, (1, K), act=1, Z=Z, C=C, Cb=Cb)
+    assert np.max(np.abs(Z.cpu().numpy() - A @ B)) <= 1e-6 * max(1.0, np.max(np.abs(A @ B)))
+    g = omlp.gelu(A @ B)
+    assert np.max(np.abs(C.cpu().numpy() - omlp.bf16(g))) <= 1e-2 * max(1.0, np.max(np.abs(g)))
+    assert np.array_equal(Cb.float().cpu().numpy(), C.cpu().numpy())
+
+
+def test_network_forward_backward_match_oracle(ht):
+    from paper_0906_2704_amd import learned
+    rng = np.random.default_rng(1)
+    params = omlp.init_params(rng)
+    for i in (1, 3, 5, 7):
+        params[i] = (0.1 * rng.standard_normal(params[i].shape)).astype(np.float32)
+    B = 96
+    X = rng.standard_normal((B, 72)).astype(np.float32)
+    t = rng.standard_normal(B).astype(np.float32)
+    net = learned.Net(DEV)
+    net.set_params(params)
+    y = net.forward(torch.tensor(X, device=DEV)).cpu().numpy()
+    net.backward(torch.tensor(t, device=DEV))
+    grads = [g.cpu().numpy() for g in net.G]
+    yw, cache = omlp.forward(params, X, bf=True)
+    gw = omlp.backward(cache, yw, t.astype(np.float64), bf=True)
+    assert rel_normwise(y, yw) < 5e-3
+    for i, (g, w) in enumerate(zip(grads, gw)):
+        assert rel_normwise(np.asarray(g).reshape(-1), np.asarray(w).reshape(-1)) < 2e-2, i
+
+
+def test_adam_step(ht):
+    rng = np.random.default_rng(2)
+    p = rng.standard_normal(300).astype(np.float32)
+    g = rng.standard_normal(300).astype(np.float32)
+    m = rng.standard_normal(300).astype(np.float32) * 0.1
+    v = np.abs(rng.standard_normal(300)).astype(np.float32) * 0.1
+    P, Gt, Mt, Vt = (torch.tensor(a, device=DEV) for a in (p, g, m, v))
+    Pb = torch.empty(300, dtype=torch.bfloat16, device=DEV)
+    ht.ht_adam(P, Gt, Mt, Vt, 1e-3, 5, pb=Pb)
+    m2 = 0.9 * m + 0.1 * g
+    v2 = 0.999 * v + 0.001 * g * g
+    want = p - 1e-3 * (m2 / (1 - 0.9 ** 5)) / (np.sqrt(v2 / (1 - 0.999 ** 5)) + 1e-8)
+    assert np.max(np.abs(P.cpu().numpy() - want)) < 1e-6
+    assert np.array_equal(Pb.float().cpu().numpy(), omlp.bf16(P.cpu().numpy()))
+
+
+def _small_batch(ht, count, first_item=0):
+    rb = synth.learned_batch(count, first_item=first_item)
+    bt = ht.Batch(rb.n, rb.degree, np.diff(rb.psf_offsets), rb.psf_center)
+    g = torch.tensor(rb.g, device=DEV)
+    psf = torch.tensor(rb.psf_flat, device=DEV)
+    mus = torch.tensor(rb.mus, device=DEV)
+    return rb, bt, g, psf, mus
+
+
+def _oracle_item(rb, b, norm="D2"):
+    kind = {1: "AR", 2: "C", 3: "DST3"}[int(rb.degree[b])]
+    n = int(rb.n[b])
+    h, c = rb.psf[b]
+    g = rb.g[rb.offsets[b]:rb.offsets[b + 1]]
+    d = tr.blur_eigs(kind, n, h, c)
+    s = tr.smooth_eigs(kind, n, norm)
+    ghat = tr.inverse(kind, g)
+    return kind, d, s, ghat
+
+
+def test_features_and_certified_restore_match_oracle(ht):
+    from paper_0906_2704_amd import learned
+    rb, bt, g, psf, mus = _small_batch(ht, 12, first_item=100)
+    coeff, feats = ht.ht_batch_features(bt, g, psf)
+    coeff_h, feats_h = coeff.cpu().numpy(), feats.cpu().numpy()
+    # predictions: the scan's optimum shifted by a few grid steps (some inside, some
+    # outside the certificate)
+    _, Gs, kscan, _ = ht.ht_batch_restore(bt, g, psf, "D2", mus)
+    kscan = kscan.cpu().numpy()
+    lm = np.log10(rb.mus[0])
+    shifts = np.array([0, 1, -2, 3, 8, -9, 0, 2, -1, 20, 4, -4])
+    kh = np.clip(kscan + shifts, 0, learned.GRID_K - 1)
+    pred = torch.tensor(lm[kh].astype(np.float32), device=DEV)
+    out, kb, mb, fb = ht.ht_batch_restore_learned(bt, coeff, psf, "D2", mus, pred, cert_half=8)
+    out, kb, fb = out.cpu().numpy(), kb.cpu().numpy(), fb.cpu().numpy()
+    for b in range(rb.n.size):
+        kind, d, s, ghat = _oracle_item(rb, b)
+        assert rel_normwise(coeff_h[rb.offsets[b]:rb.offsets[b + 1]], ghat) < 1e-12
+        fw = olearned.features(ghat, d)
+        assert np.max(np.abs(feats_h[b] - fw)) < 1e-5 * max(1.0, np.max(np.abs(fw))), b
+        Gw, kw, _ = tk.gcv_scan(ghat, d, s, rb.mus[b])
+        khat = olearned.nearest_index(rb.mus[b], float(np.float32(lm[kh[b]])))
+        kc, fell = olearned.certify(Gw, khat, half=8)
+        assert kb[b] == kc and bool(fb[b]) == fell, (b, kb[b], kc, fb[b], fell)
+        fr = tr.forward(kind, tk.tikhonov_filter(ghat, d, s, rb.mus[b][kc])).real
+        assert rel_normwise(out[rb.offsets[b]:rb.offsets[b + 1]], fr) < 1e-12
+
+
+def test_trained_network_gains_over_scan(ht):
+    """Train on problems the method labels itself; on held-out problems the certified
+    learned path evaluates far fewer GCV points than the scan at restoration error within
+    5% of the scan's."""
+    from paper_0906_2704_amd import learned
+    torch.manual_seed(0)
+    rb, bt, g, psf, mus = _small_batch(ht, 6000, first_item=0)
+    labels, _, _ = learned.labels_by_scan(bt, g, psf, mus)
+    _, feats = ht.ht_batch_features(bt, g, psf)
+    net = learned.Net(DEV, seed=0)
+    learned.fit_standardisation(net, feats)
+    hist = learned.train(net, feats, labels, epochs=25, batch=500, lr=2e-3)
+    assert hist[-1] < 0.5 * hist[0]
+    rt, btt, gt, psft, must = _small_batch(ht, 800, first_item=50000)
+    f_scan, _, k_scan, _ = ht.ht_batch_restore(btt, gt, psft, "D2", must, want_G=False)
+    f_l, k_l, _, fb, _ = learned.restore_learned(net, btt, gt, psft, must)
+    f_scan, f_l = f_scan.cpu().numpy(), f_l.cpu().numpy()
+    fb = fb.cpu().numpy()
+    rre = lambda f, b: np.linalg.norm(f[rt.offsets[b]:rt.offsets[b + 1]] - rt.f_true[rt.offsets[b]:rt.offsets[b + 1]]) \
+        / np.linalg.norm(rt.f_true[rt.offsets[b]:rt.offsets[b + 1]])
+    r_scan = np.mean([rre(f_scan, b) for b in range(800)])
+    r_learn = np.mean([rre(f_l, b) for b in range(800)])
+    evals = np.mean(np.where(fb == 1, 17 + learned.GRID_K, 17))
+    print("fallback rate %.3f  mean RRE scan %.4f learned %.4f  GCV evaluations/signal %.1f vs %d"
+          % (fb.mean(), r_scan, r_learn, evals, learned.GRID_K))
+    assert r_learn <= 1.05 * r_scan
+    assert evals < 0.5 * learned.GRID_K
