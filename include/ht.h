@@ -73,8 +73,9 @@ typedef struct ht_plan ht_plan;
  *   degree         preserved polynomial degree (1..3, see ht_family)
  *   psf_symmetric  nonzero if h_{-j} = h_j (selects T_C over T_F for degree 2)
  *   family         ht_family
- *   max_batch      2D only: number of images one call may process (sizes the plan's
- *                  workspace); ignored for 1D
+ *   max_batch      number of images (2D) one call may process, sizing the plan's
+ *                  workspace; in 1D it bounds the signals per call only for the
+ *                  split-precision core (ht_plan_set_precision) and is otherwise ignored
  * Lengths must satisfy 5 <= n <= 8192.  The plan owns all device tables (boundary
  * vectors and 2x2 solves of Theorem th:inv in closed form, chirp and filter-spectrum
  * tables of the core transform, trigonometric tables of the exactly reduced angles).
@@ -87,6 +88,29 @@ ht_status ht_plan_destroy(ht_plan* plan);
 int ht_plan_kind(const ht_plan* plan, int axis);
 /* 1 if coefficients / eigenvalues are complex128 (kind F on any axis), else 0. */
 int ht_plan_is_complex(const ht_plan* plan);
+
+/* Arithmetic of the core transform inside ht_transform_inv / ht_transform_fwd.
+ *   HT_PRECISION_F64     float64 chirp-z FFT core (default).
+ *   HT_PRECISION_BF16X3  the core as a dense GEMM on the matrix cores: the core matrix
+ *                        (A_inv = inverse of the interior core block, A_fwd = the core
+ *                        columns of T on the whole grid) and the vectors are each split
+ *                        x = x_hi + x_lo into two bfloat16 parts, and the product is
+ *                        A_hi B_hi + A_hi B_lo + A_lo B_hi accumulated in float32.
+ *   HT_PRECISION_F16X3   the same with float16 parts and a power-of-two scale per row.
+ * The 2x2 boundary solve, the interior correction, the boundary columns of the forward
+ * transform and all inputs and outputs stay float64.  Relative error of one 1D pass is
+ * of order 2^-16 (bfloat16) or 2^-21 (float16) of the vector's norm instead of 2^-52. */
+typedef enum { HT_PRECISION_F64 = 0, HT_PRECISION_BF16X3 = 1, HT_PRECISION_F16X3 = 2 } ht_precision;
+
+/* ht_plan_set_precision -- choose the core arithmetic of `plan` (ht_precision).  The
+ * split-precision cores need real cores on every axis (T_C, antireflective, DST family;
+ * HT_ERR_UNSUPPORTED for T_F) and the plan's device current.  Builds the dense split
+ * core matrices (2 n^2 x 4 bytes per axis) and a workspace for max_batch signals or
+ * images; blocking (synchronises the device).  Not to be called while the plan is in use
+ * on a stream.  HT_PRECISION_F64 releases them.                                       */
+ht_status ht_plan_set_precision(ht_plan* plan, int precision);
+/* The plan's ht_precision, or -1 for a null plan. */
+int ht_plan_precision(const ht_plan* plan);
 
 /* ht_eigs -- eigenvalues d of the blurring matrix and s of the smoothing operator in the
  * plan's basis (eqs. jcf, Ac, Af; L_A, L_C, L_F of Section 4), computed from the PSF by
@@ -106,7 +130,8 @@ ht_status ht_eigs(const ht_plan* plan, const double* psf, const int64_t* psf_len
 /* ht_transform_inv -- coeff = T^{-1} signal (Theorem th:inv): the 2x2 boundary system in
  * float64, the interior correction, one core analysis transform (DST-I, DCT-II or DFT of
  * order n-2) and, for DST2/DST3, the rank-(degree-1) correction.  In 2D the 1D transform
- * runs along axis 1 then axis 0 (Section 6).  signal and coeff must not overlap.       */
+ * runs along axis 1 then axis 0 (Section 6).  signal and coeff must not overlap.  With
+ * a split-precision core (ht_plan_set_precision) batch must not exceed max_batch.      */
 ht_status ht_transform_inv(const ht_plan* plan, const double* signal, void* coeff,
                            int64_t batch, hipStream_t stream);
 

@@ -34,16 +34,18 @@ def tikhonov_filter(ghat, d, s, mu):
     return out.astype(np.complex128 if cplx else np.float64)
 
 
-def gcv_values(ghat, d, s, mus):
-    """G(mu_k) for every mu_k of the grid (eq. mugcv), long-double sums."""
-    gl = np.asarray(ghat).astype(np.clongdouble)
-    dl = np.asarray(d).astype(np.clongdouble)
-    s2 = np.asarray(s).astype(LD) ** 2
+def gcv_values(ghat, d, s, mus, wide=True):
+    """G(mu_k) for every mu_k of the grid (eq. mugcv), long-double sums (float64 sums with
+    wide=False, for million-entry images)."""
+    R, C = (LD, np.clongdouble) if wide else (np.float64, np.complex128)
+    gl = np.asarray(ghat).astype(C)
+    dl = np.asarray(d).astype(C)
+    s2 = np.asarray(s).astype(R) ** 2
     d2 = (dl * np.conj(dl)).real
     g2 = (gl * np.conj(gl)).real
     out = np.empty(len(mus), dtype=np.float64)
     for k, mu in enumerate(mus):
-        sigma = s2 / (d2 + LD(mu) * s2)
+        sigma = s2 / (d2 + R(mu) * s2)
         out[k] = np.float64(np.sum(sigma * sigma * g2) / np.sum(sigma) ** 2)
     return out
 

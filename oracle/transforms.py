@@ -310,6 +310,15 @@ def forward(kind, x):
     return _round(y, kind, x)
 
 
+def forward_f64(kind, x):
+    """y = T x with a float64 product (used as the reference at sizes where the long-double
+    product is too slow; its error, about 1e-15 relative, is far below what it checks)."""
+    T = transform_matrix(kind, np.asarray(x).shape[-1])
+    T64 = T.astype(np.complex128 if is_complex(kind) else np.float64)
+    y = np.asarray(x) @ T64.T
+    return y if (is_complex(kind) or np.iscomplexobj(x)) else y.real
+
+
 def _round(y, kind, x):
     if is_complex(kind) or np.iscomplexobj(x):
         return y.astype(np.complex128)
@@ -318,7 +327,8 @@ def _round(y, kind, x):
 
 def inverse(kind, y, refine_steps=3):
     """x = T^{-1} y (the "inverse transform") by dense LU of T with iterative refinement,
-    residuals y - T x evaluated in long double.  y: (n,) or (batch, n)."""
+    residuals y - T x evaluated in long double.  y: (n,) or (batch, n).  refine_steps=0 is
+    the plain float64 LU solve (about 1e-12 relative at n = 2048)."""
     y = np.asarray(y)
     squeeze = y.ndim == 1
     Y = np.atleast_2d(y)

@@ -16,14 +16,17 @@ from . import transforms as tr
 from . import tikhonov as tk
 
 
-def forward2d(kind0, kind1, X):
-    Y = tr.forward(kind1, X)            # rows (axis 1)
-    return tr.forward(kind0, Y.T).T     # columns (axis 0)
+def forward2d(kind0, kind1, X, wide=True):
+    """wide=False: float64 products (large images)."""
+    fwd = tr.forward if wide else tr.forward_f64
+    Y = fwd(kind1, X)                   # rows (axis 1)
+    return fwd(kind0, Y.T).T            # columns (axis 0)
 
 
-def inverse2d(kind0, kind1, Y):
-    X = tr.inverse(kind1, Y)
-    return tr.inverse(kind0, X.T).T
+def inverse2d(kind0, kind1, Y, refine_steps=3):
+    """refine_steps=0: plain float64 LU solves (large images)."""
+    X = tr.inverse(kind1, Y, refine_steps)
+    return tr.inverse(kind0, X.T, refine_steps).T
 
 
 def eigs2d_separable(kind0, kind1, n0, n1, h0, c0, h1, c1):

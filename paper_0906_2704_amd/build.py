@@ -6,7 +6,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["ht_plan.hip", "ht_transform.hip", "ht_spectral.hip", "ht_batch.hip", "ht_mlp.hip"]
+SOURCES = ["ht_plan.hip", "ht_transform.hip", "ht_spectral.hip", "ht_batch.hip", "ht_mlp.hip", "ht_gemm.hip"]
 LIB = os.path.join(HERE, "libht.so")
 
 HIPCC_FLAGS = [

@@ -60,6 +60,8 @@ struct View {
     int cplx;             // 1: interleaved complex128, 0: float64
 };
 
+struct GemmState;  // split-precision matrix-core cores of a plan (ht_gemm.hip)
+
 }  // namespace ht
 
 struct ht_plan {
@@ -73,6 +75,7 @@ struct ht_plan {
     double* gcv_part = nullptr;        // 2D GCV partial sums
     int64_t gcv_part_elems = 0;
     const double2* tw = nullptr;       // global twiddle table of this device
+    ht::GemmState* gemm = nullptr;     // set by ht_plan_set_precision (null: float64 core)
 };
 
 namespace ht {
@@ -81,6 +84,11 @@ namespace ht {
 ht_status fail(ht_status st, const std::string& msg);
 ht_status check_hip(hipError_t e, const char* what);
 const double2* device_twiddles(int device, ht_status* st);
+
+// split-precision cores (ht_gemm.hip): in and out contiguous, must not overlap
+ht_status gemm_transform(const ht_plan* p, bool inverse, const double* in, double* out, int64_t batch,
+                         hipStream_t stream);
+void gemm_release(GemmState* g);
 
 // launchers (ht_transform.hip)
 ht_status launch_core(const Axis& ax, const double2* tw, bool inverse, const View& in,

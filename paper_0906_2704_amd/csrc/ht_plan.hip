@@ -433,7 +433,7 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
     p->device = device;
     p->tw = tw;
     p->cplx = kind == HT_KIND_F ? 1 : 0;
-    p->max_batch = ndim == 2 ? max_batch : 1;
+    p->max_batch = max_batch < 1 ? 1 : max_batch;
     st = upload_axes(hs, ndim, &p->arena, p->ax);
     if (st != HT_OK) {
         delete p;
@@ -461,6 +461,7 @@ extern "C" ht_status ht_plan_destroy(ht_plan* p) {
     if (p->arena) (void)hipFree(p->arena);
     if (p->work) (void)hipFree(p->work);
     if (p->gcv_part) (void)hipFree(p->gcv_part);
+    gemm_release(p->gemm);
     delete p;
     return HT_OK;
 }

@@ -212,6 +212,10 @@ extern "C" ht_status ht_transform_inv(const ht_plan* plan, const double* signal,
     if (batch < 0) return fail(HT_ERR_INVALID_ARG, "ht_transform_inv: negative batch");
     if (batch == 0) return HT_OK;
     if (!signal || !coeff) return fail(HT_ERR_INVALID_ARG, "ht_transform_inv: null argument");
+    if (plan->gemm) {
+        if (signal == coeff) return fail(HT_ERR_INVALID_ARG, "ht_transform_inv: signal and coeff must not overlap");
+        return gemm_transform(plan, true, signal, static_cast<double*>(coeff), batch, stream);
+    }
     const int cp = plan->cplx;
     if (plan->ndim == 1) {
         const Axis& a = plan->ax[0];
@@ -240,6 +244,10 @@ extern "C" ht_status ht_transform_fwd(const ht_plan* plan, const void* coeff, do
     if (batch < 0) return fail(HT_ERR_INVALID_ARG, "ht_transform_fwd: negative batch");
     if (batch == 0) return HT_OK;
     if (!signal || !coeff) return fail(HT_ERR_INVALID_ARG, "ht_transform_fwd: null argument");
+    if (plan->gemm) {
+        if (signal == coeff) return fail(HT_ERR_INVALID_ARG, "ht_transform_fwd: signal and coeff must not overlap");
+        return gemm_transform(plan, false, static_cast<const double*>(coeff), signal, batch, stream);
+    }
     const int cp = plan->cplx;
     if (plan->ndim == 1) {
         const Axis& a = plan->ax[0];

@@ -19,6 +19,7 @@ HT_NORM_IDENTITY, HT_NORM_SECOND_DIFF = 0, 1
 KIND_NAMES = {1: "AR", 2: "C", 3: "F", 4: "DST2", 5: "DST3"}
 NORMS = {"I": HT_NORM_IDENTITY, "D2": HT_NORM_SECOND_DIFF}
 FAMILIES = {"paper": HT_FAMILY_PAPER, "dst": HT_FAMILY_DST, "paper+dst3": 2}
+PRECISIONS = {"f64": 0, "bf16x3": 1, "f16x3": 2}
 
 _lib = None
 
@@ -46,11 +47,13 @@ def lib():
     L.ht_transform_fwd.argtypes = [P, VP, VP, I64, VP]
     L.ht_tikhonov_filter.argtypes = [P, VP, VP, VP, I64, VP, VP, I64, VP]
     L.ht_gcv_scan.argtypes = [P, VP, VP, VP, I64, VP, I32, ctypes.c_int, VP, VP, VP, I64, VP]
+    L.ht_plan_set_precision.argtypes = [P, ctypes.c_int]
+    L.ht_plan_precision.argtypes = [P]
     L.ht_status_str.argtypes = [ctypes.c_int]
     L.ht_status_str.restype = ctypes.c_char_p
     L.ht_last_error.restype = ctypes.c_char_p
     for name in ("ht_plan_create", "ht_plan_destroy", "ht_eigs", "ht_transform_inv", "ht_transform_fwd",
-                 "ht_tikhonov_filter", "ht_gcv_scan"):
+                 "ht_tikhonov_filter", "ht_gcv_scan", "ht_plan_set_precision", "ht_plan_precision"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -113,6 +116,15 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_precision(self, precision):
+        """Core arithmetic: "f64" (default), "bf16x3" or "f16x3" (ht_plan_set_precision)."""
+        _check(lib().ht_plan_set_precision(self._h, PRECISIONS.get(precision, precision)), "ht_plan_set_precision")
+
+    @property
+    def precision(self):
+        code = lib().ht_plan_precision(self._h)
+        return {v: k for k, v in PRECISIONS.items()}[code]
 
     def item_shape(self):
         return tuple(self.n)

@@ -13,6 +13,7 @@ PSF masks are returned as (h, center): h[idx] is the tap h_{idx-center}.
 from dataclasses import dataclass
 
 import numpy as np
+from scipy.ndimage import convolve1d
 
 SEED_BASE = 0x0906_2704
 
@@ -87,10 +88,24 @@ def observe_1d(f_ext, h, center, n):
     return g
 
 
+def _observe_axis(F_ext, h, center, n, axis):
+    """observe_1d along one axis of a 2D array.  For odd mask lengths L = 2m+1 the valid
+    samples are entries m .. m+n-1 of the zero-padded 'same' convolution, whatever the
+    centre: g_i = sum_idx h[idx] f[i + L-1 - idx]."""
+    h = np.asarray(h, dtype=np.float64)
+    if h.size % 2 == 0:
+        if axis == 1:
+            return observe_1d(F_ext, h, center, n)
+        return observe_1d(F_ext.T, h, center, n).T
+    m = (h.size - 1) // 2
+    full = convolve1d(F_ext, h, axis=axis, mode="constant")
+    return full[:, m:m + n] if axis == 1 else full[m:m + n, :]
+
+
 def observe_2d(F_ext, h0, c0, h1, c1, shape):
     n0, n1 = shape
-    tmp = observe_1d(F_ext, h1, c1, n1)            # along axis 1
-    return observe_1d(tmp.T, h0, c0, n0).T          # along axis 0
+    tmp = _observe_axis(F_ext, h1, c1, n1, 1)       # along axis 1
+    return _observe_axis(tmp, h0, c0, n0, 0)        # along axis 0
 
 
 def add_noise(rng, g, eta):

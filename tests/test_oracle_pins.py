@@ -12,6 +12,7 @@ import pytest
 
 from oracle import bc, tikhonov as tk, transforms as tr, twod
 from paper_0906_2704_amd import synth
+from parity import rel_normwise as rel_err
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 KINDS_SYM = ["AR", "C", "DST2", "DST3"]
@@ -416,3 +417,25 @@ def test_2d_axis_passes_equal_kronecker(k0, k1):
     assert np.abs(Y.ravel() - K @ X.ravel()).max() < 1e-14
     Z = twod.inverse2d(k0, k1, X)
     assert np.abs(K @ Z.ravel() - X.ravel()).max() < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["C", "AR", "DST3"])
+def test_float64_reference_variants_agree_with_refined_ones(kind):
+    """The plain float64 variants (for million-pixel references) against the refined /
+    long-double ones: the residual of the system and the forward product."""
+    n = 1024
+    rng = np.random.default_rng(11)
+    Y = rng.standard_normal((3, n))
+    X0 = tr.inverse(kind, Y, refine_steps=0)
+    X3 = tr.inverse(kind, Y)
+    assert rel_err(X0, X3) < 1e-11
+    T = tr.transform_matrix(kind, n)
+    R = Y.astype(np.longdouble) - np.einsum("ij,bj->bi", T, X0.astype(np.longdouble))
+    # backward stability of LU: residual within a modest multiple of n eps |T| |x|
+    bound = n * np.finfo(float).eps * float(np.abs(T).sum(axis=1).max()) * np.abs(X0).max()
+    assert float(np.abs(R).max()) < bound
+    Xc = rng.standard_normal((3, n))
+    assert rel_err(tr.forward_f64(kind, Xc), tr.forward(kind, Xc)) < 1e-14
+    G = tk.gcv_values(X3[0], np.linspace(0.1, 1.0, n), np.ones(n), [1e-3, 1e-1], wide=False)
+    Gw = tk.gcv_values(X3[0], np.linspace(0.1, 1.0, n), np.ones(n), [1e-3, 1e-1])
+    assert np.abs(G - Gw).max() < 1e-13 * np.abs(Gw).max()
