@@ -223,21 +223,26 @@ int ht_batch_class_count(const ht_batch* batch, int size_class);
  * bands of the normalised core frequency j/(n-2) (band b holds j with
  * floor(64 j / (n-2)) = b; the two polynomial entries are excluded), then the means of
  * log10(|d_j|^2 + 1e-20) over 8 such bands of the blur eigenvalues (the floor keeps the
- * logarithms well conditioned where the spectrum vanishes).  Needs n >= 66.          */
+ * logarithms well conditioned where the spectrum vanishes; the logarithms are float32).
+ * spectrum [total_length] (nullable) receives the blur eigenvalues d in coefficient
+ * order, for ht_batch_restore_learned.  Needs n >= 66.                                 */
 ht_status ht_batch_features(const ht_batch* batch, const double* signal, const double* psf,
-                            double* coeff, float* features, hipStream_t stream);
+                            double* coeff, float* features, double* spectrum,
+                            hipStream_t stream);
 
 /* ht_batch_restore_learned -- coeff_restored holds the coefficients from
- * ht_batch_features on entry and the restorations on exit.  For every signal the grid
- * index k^ nearest to pred_log10_mu[b] is certified: G is evaluated on [k^-h, k^+h]
- * (h = cert_half in [1, K-1], clipped to the grid); with k_m its first minimum there,
- * the certificate holds if G(k^) <= 1.05 G(k_m) and k_m is not an interior edge of the
- * bracket, and then
- * mu = mu_{k_m}; otherwise the full grid is scanned (fallback[b] = 1) and mu is the
- * scan's choice.  G [count][K] (nullable) receives the evaluated values only.          */
+ * ht_batch_features on entry and the restorations on exit; spectrum (nullable) is the
+ * eigenvalue output of that same call (recomputed from psf when NULL).  For every signal
+ * the grid index k^ nearest to pred_log10_mu[b] is certified: G is evaluated on
+ * [k^-h, k^+h] (h = cert_half in [1, K-1], clipped to the grid); with k_m its first
+ * minimum there, the certificate holds if G(k^) <= 1.05 G(k_m) and k_m is not an
+ * interior edge of the bracket, and then mu = mu_{k_m}; otherwise the full grid is
+ * scanned (fallback[b] = 1) and mu is the scan's choice.  G [count][K] (nullable)
+ * receives the evaluated values only.                                                  */
 ht_status ht_batch_restore_learned(const ht_batch* batch, double* coeff_restored,
-                                   const double* psf, int norm, const double* mu_grid,
-                                   int32_t K, const float* pred_log10_mu, int32_t cert_half,
+                                   const double* psf, const double* spectrum, int norm,
+                                   const double* mu_grid, int32_t K,
+                                   const float* pred_log10_mu, int32_t cert_half,
                                    double* G, int32_t* k_best, double* mu_best,
                                    int32_t* fallback, hipStream_t stream);
 

@@ -54,6 +54,7 @@ struct RaggedArgs {
     int32_t* fallback;  // learned mode: 1 where the certificate failed and the full scan ran
     float* feat;        // feature mode: [count][NFEAT]
     int cert_half;      // learned mode: certificate bracket half-width in grid steps
+    double* spec;       // feature mode: blur eigenvalues written here; learned mode: read (or null)
 };
 
 // What one pass of the fused kernel does with each signal.
@@ -136,11 +137,7 @@ template <int LOGP, int S, int SL, int MODE>
 __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int cls, int start, int count) {
     constexpr int P = 1 << LOGP;
     constexpr int BLOCK = P / SL;
-    // cross-part GCV reduction buffer: only 64-thread groups can need more than one pass
-    // over the grid (K > 2 * BLOCK); otherwise the reduction reuses the staging buffer
-    constexpr int RED = BLOCK < BATCH_MAX_K / 2 ? 2 * BLOCK : 1;
     __shared__ double2 lds[P];
-    __shared__ double2 red_small[RED];
     __shared__ double Gs[BATCH_MAX_K];
     __shared__ double2 bc[3];
     __shared__ int s_item, s_kbest, s_fall;
@@ -246,7 +243,9 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
             if (j < N && j >= rank) {
                 const int num = kind == HT_KIND_C ? j : j + 1;  // frequency pi * num / den
                 double acc;
-                if (centred) {
+                if (MODE == MODE_LEARNED && a.spec) {
+                    acc = a.spec[sg.off + 1 + j];  // left by the feature pass
+                } else if (centred) {
                     // Re z = h_0 + sum_{t>0} (h_t + h_{-t}) cos(t theta)
                     acc = h[pc];
                     int r = 0;
@@ -276,21 +275,32 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
         if constexpr (MODE == MODE_FEATURES) {
             // band means of log10(|ghat_j|^2 + 1e-20) (64 bands) and log10(|d_j|^2 + 1e-20) (8 bands) over the
             // normalised core frequency j / N; band b holds j with floor(B j / N) = b
+            // (float32 logarithms: the features are float32)
             double2* lg = lds;
+            constexpr float LOG10_2 = 0.30102999566398120f;
 #pragma unroll
             for (int k = 0; k < SL; ++k) {
                 const int j = tid + k * BLOCK;
-                if (j < N) lg[j] = make_double2(log10(c[k] * c[k] + 1e-20), log10(dj[k] * dj[k] + 1e-20));
+                if (j < N) {
+                    const float lc = __builtin_amdgcn_logf(static_cast<float>(c[k] * c[k] + 1e-20)) * LOG10_2;
+                    const float ld = __builtin_amdgcn_logf(static_cast<float>(dj[k] * dj[k] + 1e-20)) * LOG10_2;
+                    lg[j] = make_double2(lc, ld);
+                    if (a.spec) a.spec[sg.off + 1 + j] = dj[k];
+                }
+            }
+            if (a.spec && tid == 0) {
+                a.spec[sg.off] = z0;
+                a.spec[sg.off + n - 1] = z0;
             }
             __syncthreads();
-            if (tid < NFEAT) {
-                const int nb = tid < NFEAT_G ? NFEAT_G : NFEAT_D;
-                const int b = tid < NFEAT_G ? tid : tid - NFEAT_G;
+            for (int fi = tid; fi < NFEAT; fi += BLOCK) {  // BLOCK may be 64 < NFEAT
+                const int nb = fi < NFEAT_G ? NFEAT_G : NFEAT_D;
+                const int b = fi < NFEAT_G ? fi : fi - NFEAT_G;
                 const int j0 = static_cast<int>((static_cast<int64_t>(b) * N + nb - 1) / nb);
                 const int j1 = static_cast<int>((static_cast<int64_t>(b + 1) * N + nb - 1) / nb);
                 double acc = 0.0;
-                for (int j = j0; j < j1; ++j) acc += tid < NFEAT_G ? lg[j].x : lg[j].y;
-                a.feat[static_cast<int64_t>(sg.item) * NFEAT + tid] = static_cast<float>(acc / (j1 - j0));
+                for (int j = j0; j < j1; ++j) acc += fi < NFEAT_G ? lg[j].x : lg[j].y;
+                a.feat[static_cast<int64_t>(sg.item) * NFEAT + fi] = static_cast<float>(acc / (j1 - j0));
             }
             __syncthreads();
             continue;
@@ -317,46 +327,38 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
         };
         const int K = a.K;
         const double* mus = a.mus + static_cast<int64_t>(sg.item) * K;
-        double2* red = lds;  // cross-part sums (after the staged pairs are no longer read)
-        // G_k for k in [klo, khi] into Gs (and a.G); two grid values per thread
+        // G_k for k in [klo, khi] into Gs (and a.G): one wave per pair of grid values, its
+        // lanes striding over the staged elements, then a fixed-order butterfly across the
+        // lanes.  The staged pairs are only read.
         auto eval_range = [&](int klo, int khi) {
+            constexpr int NW = BLOCK / 64;
             const int cnt = khi - klo + 1;
             const int Kh = (cnt + 1) / 2;
-            const int Kb = Kh < BLOCK ? Kh : BLOCK;
-            const int nparts = BLOCK / Kb;
-            const int part = tid / Kb, kl = tid - part * Kb;
-            const bool one_pass = Kh <= Kb;
-            double2* rbuf = one_pass ? red : red_small;
-            for (int k0 = 0; k0 < Kh; k0 += Kb) {
-                const int kk = k0 + kl;
-                double Na = 0.0, Da = 0.0, Nb = 0.0, Db = 0.0;
-                if (part < nparts && kk < Kh) {
+            const int wv = tid >> 6, lane = tid & 63;
+            for (int k0 = 0; k0 < Kh; k0 += NW) {
+                const int kk = k0 + wv;
+                if (kk < Kh) {  // uniform across the wave
                     const int ka = klo + 2 * kk, kb2 = ka + 1 <= khi ? ka + 1 : ka;
-                    gcv_two(stage, n, part, nparts, mus[ka], mus[kb2], Na, Da, Nb, Db);
-                }
-                if (one_pass) __syncthreads();
-                rbuf[2 * tid] = make_double2(Na, Da);
-                rbuf[2 * tid + 1] = make_double2(Nb, Db);
-                __syncthreads();
-                if (part == 0 && kk < Kh) {
-                    double2 A = rbuf[2 * kl], B = rbuf[2 * kl + 1];
-                    for (int p = 1; p < nparts; ++p) {
-                        const double2 va = rbuf[2 * (p * Kb + kl)], vb = rbuf[2 * (p * Kb + kl) + 1];
-                        A.x += va.x;
-                        A.y += va.y;
-                        B.x += vb.x;
-                        B.y += vb.y;
+                    double Na, Da, Nb, Db;
+                    gcv_two(stage, n, lane, 64, mus[ka], mus[kb2], Na, Da, Nb, Db);
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) {
+                        Na += __shfl_xor(Na, o, 64);
+                        Da += __shfl_xor(Da, o, 64);
+                        Nb += __shfl_xor(Nb, o, 64);
+                        Db += __shfl_xor(Db, o, 64);
                     }
-                    const int ka = klo + 2 * kk;
-                    Gs[ka] = A.x / (A.y * A.y);
-                    if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka] = Gs[ka];
-                    if (ka + 1 <= khi) {
-                        Gs[ka + 1] = B.x / (B.y * B.y);
-                        if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka + 1] = Gs[ka + 1];
+                    if (lane == 0) {
+                        Gs[ka] = Na / (Da * Da);
+                        if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka] = Gs[ka];
+                        if (ka + 1 <= khi) {
+                            Gs[ka + 1] = Nb / (Db * Db);
+                            if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka + 1] = Gs[ka + 1];
+                        }
                     }
                 }
-                __syncthreads();
             }
+            __syncthreads();
         };
         // first minimum over [klo, khi]; -1 if some G is not finite
         auto argmin_range = [&](int klo, int khi) {
@@ -388,18 +390,26 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
         int kstar;
         if constexpr (MODE == MODE_LEARNED) {
             // nearest grid index to the prediction, then the certificate bracket
-            if (tid == 0) {
+            if (tid < 64) {  // wave 0: lane-strided scan, then a first-index argmin across lanes
                 const double pr = static_cast<double>(a.pred[sg.item]);
-                int kh = 0;
-                double bd = fabs(log10(mus[0]) - pr);
-                for (int k = 1; k < K; ++k) {
+                int kh = K;
+                double bd = __builtin_inf();
+                for (int k = tid; k < K; k += 64) {
                     const double dd = fabs(log10(mus[k]) - pr);
                     if (dd < bd) {
                         bd = dd;
                         kh = k;
                     }
                 }
-                s_item = kh;  // reused as a broadcast slot (the queue index was already read)
+                for (int o = 32; o > 0; o >>= 1) {
+                    const double od = __shfl_xor(bd, o);
+                    const int ok = __shfl_xor(kh, o);
+                    if (od < bd || (od == bd && ok < kh)) {
+                        bd = od;
+                        kh = ok;
+                    }
+                }
+                if (tid == 0) s_item = kh;  // reused as a broadcast slot (the queue index was already read)
             }
             __syncthreads();
             const int khat = __builtin_amdgcn_readfirstlane(s_item);
@@ -415,9 +425,7 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
             if (ok) {
                 kstar = km;
             } else {
-                __syncthreads();
-                stage_fill();  // the reduction above reused the staging buffer
-                eval_range(0, K - 1);
+                eval_range(0, K - 1);  // the staged pairs are still in place
                 kstar = argmin_range(0, K - 1);
             }
             if (tid == 0) a.fallback[sg.item] = ok ? 0 : 1;
@@ -752,20 +760,21 @@ extern "C" ht_status ht_batch_restore(const ht_batch* bt, const double* signal, 
 }
 
 extern "C" ht_status ht_batch_features(const ht_batch* bt, const double* signal, const double* psf, double* coeff,
-                                       float* features, hipStream_t stream) {
+                                       float* features, double* spectrum, hipStream_t stream) {
     if (!bt) return fail(HT_ERR_INVALID_ARG, "ht_batch_features: null batch");
     if (!signal || !psf || !coeff || !features) return fail(HT_ERR_INVALID_ARG, "ht_batch_features: null argument");
     if (signal == coeff) return fail(HT_ERR_INVALID_ARG, "ht_batch_features: signal and coeff must not overlap");
     if (bt->min_n < NFEAT_G + 2) return fail(HT_ERR_UNSUPPORTED, "ht_batch_features: needs n >= 66 (64 bands)");
     RaggedArgs a{bt->d_axes, bt->d_sigs, bt->d_counters, signal, psf, nullptr, 1, HT_NORM_SECOND_DIFF, coeff, nullptr,
-                 nullptr, nullptr, bt->d_scratch, nullptr, nullptr, features, 0};
+                 nullptr, nullptr, bt->d_scratch, nullptr, nullptr, features, 0, spectrum};
     return run_classes(bt, a, MODE_FEATURES, stream);
 }
 
-extern "C" ht_status ht_batch_restore_learned(const ht_batch* bt, double* coeff_restored, const double* psf, int norm,
-                                              const double* mu_grid, int32_t K, const float* pred_log10_mu,
-                                              int32_t cert_half, double* G, int32_t* k_best, double* mu_best,
-                                              int32_t* fallback, hipStream_t stream) {
+extern "C" ht_status ht_batch_restore_learned(const ht_batch* bt, double* coeff_restored, const double* psf,
+                                              const double* spectrum, int norm, const double* mu_grid, int32_t K,
+                                              const float* pred_log10_mu, int32_t cert_half, double* G,
+                                              int32_t* k_best, double* mu_best, int32_t* fallback,
+                                              hipStream_t stream) {
     if (!bt) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_learned: null batch");
     if (!coeff_restored || !psf || !mu_grid || !pred_log10_mu || !k_best || !mu_best || !fallback)
         return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_learned: null argument");
@@ -775,6 +784,6 @@ extern "C" ht_status ht_batch_restore_learned(const ht_batch* bt, double* coeff_
     if (cert_half < 1 || cert_half >= K)
         return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_learned: cert_half must be in [1, K-1]");
     RaggedArgs a{bt->d_axes, bt->d_sigs, bt->d_counters, nullptr, psf, mu_grid, K, norm, coeff_restored, G, k_best,
-                 mu_best, bt->d_scratch, pred_log10_mu, fallback, nullptr, cert_half};
+                 mu_best, bt->d_scratch, pred_log10_mu, fallback, nullptr, cert_half, const_cast<double*>(spectrum)};
     return run_classes(bt, a, MODE_LEARNED, stream);
 }

@@ -317,8 +317,8 @@ def ht_batch_restore(batch, signal, psf, norm, mu_grid, restored=None, G=None, k
 def _learned_sigs(L):
     I64, I32, VP, F = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_float
     Ci = ctypes.c_int
-    L.ht_batch_features.argtypes = [VP, VP, VP, VP, VP, VP]
-    L.ht_batch_restore_learned.argtypes = [VP, VP, VP, Ci, VP, I32, VP, I32, VP, VP, VP, VP, VP]
+    L.ht_batch_features.argtypes = [VP, VP, VP, VP, VP, VP, VP]
+    L.ht_batch_restore_learned.argtypes = [VP, VP, VP, VP, Ci, VP, I32, VP, I32, VP, VP, VP, VP, VP]
     L.ht_gemm_bf16.argtypes = [Ci, Ci, Ci, VP, I64, I64, VP, I64, I64, VP, Ci, VP, VP, I64, VP, VP]
     L.ht_to_bf16.argtypes = [VP, VP, I64, Ci, VP, VP, VP]
     L.ht_from_bf16.argtypes = [VP, VP, I64, VP]
@@ -353,7 +353,8 @@ def _p(t, name, dtype=None):
 BF16 = torch.bfloat16
 
 
-def ht_batch_features(batch, signal, psf, coeff=None, features=None):
+def ht_batch_features(batch, signal, psf, coeff=None, features=None, spectrum=None):
+    """Returns (coeff, features); `spectrum` (optional, float64 [total_length]) receives d."""
     L = _llib()
     dev = signal.device
     if coeff is None:
@@ -361,14 +362,15 @@ def ht_batch_features(batch, signal, psf, coeff=None, features=None):
     if features is None:
         features = torch.empty((batch.count, 72), dtype=torch.float32, device=dev)
     _check(L.ht_batch_features(batch.handle, _p(signal, "signal", torch.float64), _p(psf, "psf", torch.float64),
-                               _p(coeff, "coeff", torch.float64), _p(features, "features", torch.float32), _stream()),
-           "ht_batch_features")
+                               _p(coeff, "coeff", torch.float64), _p(features, "features", torch.float32),
+                               _p(spectrum, "spectrum", torch.float64), _stream()), "ht_batch_features")
     return coeff, features
 
 
 def ht_batch_restore_learned(batch, coeff, psf, norm, mu_grid, pred, cert_half=8, G=None, kb=None, mb=None,
-                             fallback=None):
-    """coeff (from ht_batch_features) is overwritten with the restorations."""
+                             fallback=None, spectrum=None):
+    """coeff (from ht_batch_features) is overwritten with the restorations; `spectrum`
+    is the feature pass's eigenvalue output (or None: recomputed)."""
     L = _llib()
     dev = coeff.device
     K = mu_grid.shape[-1]
@@ -376,7 +378,7 @@ def ht_batch_restore_learned(batch, coeff, psf, norm, mu_grid, pred, cert_half=8
     mb = torch.empty(batch.count, dtype=torch.float64, device=dev) if mb is None else mb
     fallback = torch.empty(batch.count, dtype=torch.int32, device=dev) if fallback is None else fallback
     _check(L.ht_batch_restore_learned(batch.handle, _p(coeff, "coeff", torch.float64), _p(psf, "psf", torch.float64),
-                                      NORMS.get(norm, norm), _p(mu_grid, "mu_grid", torch.float64), int(K),
+                                      _p(spectrum, "spectrum", torch.float64), NORMS.get(norm, norm), _p(mu_grid, "mu_grid", torch.float64), int(K),
                                       _p(pred, "pred", torch.float32), int(cert_half), _p(G, "G", torch.float64),
                                       _p(kb, "k_best", torch.int32), _p(mb, "mu_best", torch.float64),
                                       _p(fallback, "fallback", torch.int32), _stream()), "ht_batch_restore_learned")

@@ -180,10 +180,14 @@ def labels_by_scan(batch, g, psf, mus, norm="D2"):
 CERT_HALF = 8  # certificate bracket: predicted grid index +- 8 (0.57 decades)
 
 
-def restore_learned(net, batch, g, psf, mus, norm="D2", coeff=None, feats=None, cert_half=CERT_HALF):
+def restore_learned(net, batch, g, psf, mus, norm="D2", coeff=None, feats=None, cert_half=CERT_HALF, spectrum=None):
     """Features -> prediction -> certified restore.  Returns (restored, k_best, mu_best,
-    fallback, pred)."""
-    coeff, feats = ht.ht_batch_features(batch, g, psf, coeff, feats)
+    fallback, pred).  `spectrum` (float64 [total_length]) carries the eigenvalues from the
+    feature pass to the restore pass; allocated when not given."""
+    if spectrum is None:
+        spectrum = torch.empty_like(g)
+    coeff, feats = ht.ht_batch_features(batch, g, psf, coeff, feats, spectrum)
     pred = net.forward(feats)
-    coeff, kb, mb, fb = ht.ht_batch_restore_learned(batch, coeff, psf, norm, mus, pred, cert_half)
+    coeff, kb, mb, fb = ht.ht_batch_restore_learned(batch, coeff, psf, norm, mus, pred, cert_half,
+                                                    spectrum=spectrum)
     return coeff, kb, mb, fb, pred

@@ -257,6 +257,44 @@ def ragged_batch(count=4096, n_lo=128, n_hi=8192, K=128, degrees=(1, 2, 3), conf
     )
 
 
+def concat_batches(parts):
+    """One RaggedBatch from several, in order."""
+    ns = np.concatenate([p.n for p in parts])
+    offs = np.zeros(ns.size + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(ns)
+    psf_lens = np.concatenate([np.diff(p.psf_offsets) for p in parts])
+    poffs = np.zeros(ns.size + 1, dtype=np.int64)
+    poffs[1:] = np.cumsum(psf_lens)
+    return RaggedBatch(
+        n=ns, offsets=offs,
+        g=np.concatenate([p.g for p in parts]),
+        f_true=np.concatenate([p.f_true for p in parts]),
+        degree=np.concatenate([p.degree for p in parts]),
+        psf=[x for p in parts for x in p.psf],
+        psf_flat=np.concatenate([p.psf_flat for p in parts]),
+        psf_offsets=poffs,
+        psf_center=np.concatenate([p.psf_center for p in parts]),
+        eta=np.concatenate([p.eta for p in parts]),
+        mus=np.concatenate([p.mus for p in parts]),
+    )
+
+
+def _learned_chunk(args):
+    return learned_batch(*args)
+
+
+def learned_batch_parallel(count, first_item=0, workers=8, chunk=4096):
+    """learned_batch(count, first_item) generated in worker processes (same items, same
+    order).  Must run before the calling process touches the GPU (the workers are forked)."""
+    import multiprocessing as mp
+    jobs = [(min(chunk, count - s), first_item + s) for s in range(0, count, chunk)]
+    if workers <= 1 or len(jobs) == 1:
+        return concat_batches([learned_batch(c, f) for c, f in jobs])
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_learned_chunk, jobs)
+    return concat_batches(parts)
+
+
 def learned_batch(count, first_item=0, K=128, grid=(-8.0, 1.0)):
     """Learned-mu workload: signals as the batched workload with n ~ U{256..4096} and the
     fixed grid of K log-spaced mu on [1e-8, 10]; item order kept."""

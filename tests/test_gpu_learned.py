@@ -114,8 +114,9 @@ def _oracle_item(rb, b, norm="D2"):
 def test_features_and_certified_restore_match_oracle(ht):
     from paper_0906_2704_amd import learned
     rb, bt, g, psf, mus = _small_batch(ht, 12, first_item=100)
-    coeff, feats = ht.ht_batch_features(bt, g, psf)
-    coeff_h, feats_h = coeff.cpu().numpy(), feats.cpu().numpy()
+    spec = torch.empty_like(g)
+    coeff, feats = ht.ht_batch_features(bt, g, psf, spectrum=spec)
+    coeff_h, feats_h, spec_h = coeff.cpu().numpy(), feats.cpu().numpy(), spec.cpu().numpy()
     # predictions: the scan's optimum shifted by a few grid steps (some inside, some
     # outside the certificate)
     _, Gs, kscan, _ = ht.ht_batch_restore(bt, g, psf, "D2", mus)
@@ -124,11 +125,12 @@ def test_features_and_certified_restore_match_oracle(ht):
     shifts = np.array([0, 1, -2, 3, 8, -9, 0, 2, -1, 20, 4, -4])
     kh = np.clip(kscan + shifts, 0, learned.GRID_K - 1)
     pred = torch.tensor(lm[kh].astype(np.float32), device=DEV)
-    out, kb, mb, fb = ht.ht_batch_restore_learned(bt, coeff, psf, "D2", mus, pred, cert_half=8)
+    out, kb, mb, fb = ht.ht_batch_restore_learned(bt, coeff, psf, "D2", mus, pred, cert_half=8, spectrum=spec)
     out, kb, fb = out.cpu().numpy(), kb.cpu().numpy(), fb.cpu().numpy()
     for b in range(rb.n.size):
         kind, d, s, ghat = _oracle_item(rb, b)
         assert rel_normwise(coeff_h[rb.offsets[b]:rb.offsets[b + 1]], ghat) < 1e-12
+        assert rel_normwise(spec_h[rb.offsets[b]:rb.offsets[b + 1]], d) < 1e-12
         fw = olearned.features(ghat, d)
         assert np.max(np.abs(feats_h[b] - fw)) < 1e-5 * max(1.0, np.max(np.abs(fw))), b
         Gw, kw, _ = tk.gcv_scan(ghat, d, s, rb.mus[b])
@@ -137,6 +139,24 @@ def test_features_and_certified_restore_match_oracle(ht):
         assert kb[b] == kc and bool(fb[b]) == fell, (b, kb[b], kc, fb[b], fell)
         fr = tr.forward(kind, tk.tikhonov_filter(ghat, d, s, rb.mus[b][kc])).real
         assert rel_normwise(out[rb.offsets[b]:rb.offsets[b + 1]], fr) < 1e-12
+
+
+def test_features_every_size_class(ht):
+    """Signals of every FFT size class, including the smallest (n = 256, 257: 64-thread
+    workgroups, fewer threads than features)."""
+    nv = [256, 257, 258, 511, 1000, 1030, 2000, 2050, 4096, 4000, 256, 300]
+    rb = synth.ragged_batch(len(nv), n_lo=256, n_hi=4096, config=4, first_item=900, sort_desc=False,
+                            n_values=nv, grid=(-8.0, 1.0))
+    bt = ht.Batch(rb.n, rb.degree, np.diff(rb.psf_offsets), rb.psf_center)
+    assert all(bt.class_count(c) > 0 for c in range(5))
+    feats = torch.full((len(nv), 72), float("nan"), dtype=torch.float32, device=DEV)
+    _, feats = ht.ht_batch_features(bt, torch.tensor(rb.g, device=DEV), torch.tensor(rb.psf_flat, device=DEV),
+                                    features=feats)
+    feats = feats.cpu().numpy()
+    for b in range(len(nv)):
+        kind, d, s, ghat = _oracle_item(rb, b)
+        fw = olearned.features(ghat, d)
+        assert np.max(np.abs(feats[b] - fw)) < 1e-5 * max(1.0, np.max(np.abs(fw))), (b, int(rb.n[b]))
 
 
 def test_trained_network_gains_over_scan(ht):
