@@ -293,14 +293,33 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
                 a.spec[sg.off + n - 1] = z0;
             }
             __syncthreads();
-            for (int fi = tid; fi < NFEAT; fi += BLOCK) {  // BLOCK may be 64 < NFEAT
-                const int nb = fi < NFEAT_G ? NFEAT_G : NFEAT_D;
-                const int b = fi < NFEAT_G ? fi : fi - NFEAT_G;
-                const int j0 = static_cast<int>((static_cast<int64_t>(b) * N + nb - 1) / nb);
-                const int j1 = static_cast<int>((static_cast<int64_t>(b + 1) * N + nb - 1) / nb);
+            // band sums by groups of aligned lanes (a fixed-order butterfly per group):
+            // 64 spectrum bands of ghat with BLOCK/64 lanes each, then 8 bands of d with up
+            // to 64 lanes each
+            {
+                constexpr int G1 = BLOCK / NFEAT_G;
+                const int b = tid / G1, r = tid - b * G1;
+                const int j0 = static_cast<int>((static_cast<int64_t>(b) * N + NFEAT_G - 1) / NFEAT_G);
+                const int j1 = static_cast<int>((static_cast<int64_t>(b + 1) * N + NFEAT_G - 1) / NFEAT_G);
                 double acc = 0.0;
-                for (int j = j0; j < j1; ++j) acc += fi < NFEAT_G ? lg[j].x : lg[j].y;
-                a.feat[static_cast<int64_t>(sg.item) * NFEAT + fi] = static_cast<float>(acc / (j1 - j0));
+                for (int j = j0 + r; j < j1; j += G1) acc += lg[j].x;
+#pragma unroll
+                for (int o = G1 / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+                if (r == 0) a.feat[static_cast<int64_t>(sg.item) * NFEAT + b] = static_cast<float>(acc / (j1 - j0));
+            }
+            {
+                constexpr int G2 = BLOCK / NFEAT_D < 64 ? BLOCK / NFEAT_D : 64;
+                if (tid < NFEAT_D * G2) {  // whole waves
+                    const int b = tid / G2, r = tid - b * G2;
+                    const int j0 = static_cast<int>((static_cast<int64_t>(b) * N + NFEAT_D - 1) / NFEAT_D);
+                    const int j1 = static_cast<int>((static_cast<int64_t>(b + 1) * N + NFEAT_D - 1) / NFEAT_D);
+                    double acc = 0.0;
+                    for (int j = j0 + r; j < j1; j += G2) acc += lg[j].y;
+#pragma unroll
+                    for (int o = G2 / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+                    if (r == 0)
+                        a.feat[static_cast<int64_t>(sg.item) * NFEAT + NFEAT_G + b] = static_cast<float>(acc / (j1 - j0));
+                }
             }
             __syncthreads();
             continue;

@@ -1,8 +1,9 @@
 // Kernels of the learned-mu predictor: a small MLP trained and evaluated on the GPU.
 //
 //   GEMM      C = act(A B + bias) with A, B in bfloat16 and float32 accumulation on the
-//             matrix cores (v_mfma_f32_16x16x16bf16_1k): one wave per 16 x 16 output tile,
-//             A and B addressed through strides so that transposed operands need no copy
+//             matrix cores (v_mfma_f32_16x16x16bf16_1k): 64 x 64 blocks of four waves with
+//             the contraction staged through LDS; A and B addressed through strides so that
+//             transposed operands need no copy
 //   GELU      exact, 0.5 x (1 + erf(x / sqrt 2)); derivative Phi(x) + x phi(x)
 //   reductions column sums (bias gradients) in a fixed order: deterministic
 //   Adam      float32 master weights and moments, bfloat16 copies for the GEMMs
@@ -48,43 +49,67 @@ struct Gemm {
     uint16_t* Cb;       // bfloat16 copy of the activated out (may be null)
 };
 
-// One wave computes C[ti*16 .. +16][tj*16 .. +16]; operands outside the matrices read 0.
-// Lane l supplies A rows l % 16, k = 4 (l / 16) + 0..3 and B columns l % 16, same k, and
-// receives D rows 4 (l / 16) + 0..3 of column l % 16.
+// A workgroup of four waves computes a 64 x 64 block of C; wave w owns rows 16w .. 16w+15
+// (four 16 x 16 MFMA tiles).  The contraction runs in chunks of 64 staged in LDS: A as
+// [row][k], B transposed to [col][k], so that every lane reads its four consecutive k in
+// one 8-byte access.  Lane l supplies A row l % 16, k = 4 (l / 16) + 0..3 and B column
+// l % 16, same k, and receives D rows 4 (l / 16) + 0..3 of column l % 16.  Operands
+// outside the matrices read 0.
+constexpr int GB = 64, GKC = 64, GPAD = GKC + 4;
+
 __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int ntj = (g.N + 15) / 16;
-    const int ntiles = ((g.M + 15) / 16) * ntj;
-    const int tile = blockIdx.x * 4 + wave;
-    if (tile >= ntiles) return;
-    const int ti = tile / ntj, tj = tile - ti * ntj;
+    __shared__ __attribute__((aligned(8))) uint16_t sA[GB][GPAD];
+    __shared__ __attribute__((aligned(8))) uint16_t sB[GB][GPAD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nbj = (g.N + GB - 1) / GB;
+    const int bi = blockIdx.x / nbj, bj = blockIdx.x - bi * nbj;
+    const int64_t row0 = static_cast<int64_t>(bi) * GB, col0 = static_cast<int64_t>(bj) * GB;
     const int r = lane & 15, q = lane >> 4;
-    const int ai = ti * 16 + r, bj = tj * 16 + r;
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
-        bf16x4 a, b;
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < g.K; k0 += GKC) {
+        // stage: element e = tid + 256 u of the 64 x 64 chunk; k fastest for A, column
+        // fastest for B (the contiguous direction of the usual layouts)
+#pragma unroll 4
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u;
+            const int ar = e >> 6, ak = e & 63;
+            const int64_t gi = row0 + ar;
+            const int gk = k0 + ak;
+            sA[ar][ak] = (gi < g.M && gk < g.K) ? g.A[gi * g.sa_i + gk * g.sa_k] : static_cast<uint16_t>(0);
+            const int bk = e >> 6, bc = e & 63;
+            const int64_t gj = col0 + bc;
+            const int gk2 = k0 + bk;
+            sB[bc][bk] = (gj < g.N && gk2 < g.K) ? g.B[gk2 * g.sb_k + gj * g.sb_j] : static_cast<uint16_t>(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GKC; kk += 16) {
+            const bf16x4 a = *reinterpret_cast<const bf16x4*>(&sA[16 * w + r][kk + 4 * q]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bf16x4 b = *reinterpret_cast<const bf16x4*>(&sB[16 * t + r][kk + 4 * q]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t cj = col0 + 16 * t + r;
+        if (cj >= g.N) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int k = k0 + 4 * q + i;
-            const bool ka = ai < g.M && k < g.K, kb = bj < g.N && k < g.K;
-            a[i] = ka ? static_cast<short>(g.A[ai * g.sa_i + k * g.sa_k]) : static_cast<short>(0);
-            b[i] = kb ? static_cast<short>(g.B[k * g.sb_k + bj * g.sb_j]) : static_cast<short>(0);
+            const int64_t ci = row0 + 16 * w + 4 * q + i;
+            if (ci >= g.M) continue;
+            float z = acc[t][i] + (g.bias ? g.bias[cj] : 0.0f);
+            if (g.Z) g.Z[ci * g.ldc + cj] = z;
+            const float y = g.act ? gelu(z) : z;
+            const uint16_t yb = f32_to_bf16(y);
+            if (g.C) g.C[ci * g.ldc + cj] = g.Cb ? bf16_to_f32(yb) : y;
+            if (g.Cb) g.Cb[ci * g.ldc + cj] = yb;
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
-    const int cj = tj * 16 + r;
-    if (cj >= g.N) return;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int ci = ti * 16 + 4 * q + i;
-        if (ci >= g.M) continue;
-        float z = acc[i] + (g.bias ? g.bias[cj] : 0.0f);
-        if (g.Z) g.Z[ci * g.ldc + cj] = z;
-        const float y = g.act ? gelu(z) : z;
-        const uint16_t yb = f32_to_bf16(y);
-        if (g.C) g.C[ci * g.ldc + cj] = g.Cb ? bf16_to_f32(yb) : y;
-        if (g.Cb) g.Cb[ci * g.ldc + cj] = yb;
     }
 }
 
@@ -187,10 +212,10 @@ extern "C" ht_status ht_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_
     if (M < 0 || N < 0 || K < 0 || (act != 0 && act != 1)) return fail(HT_ERR_INVALID_ARG, "ht_gemm_bf16: bad sizes");
     if (M == 0 || N == 0) return HT_OK;
     if (!A || !B || (!Z && !C && !Cb) || ldc < N) return fail(HT_ERR_INVALID_ARG, "ht_gemm_bf16: null argument or ldc < N");
-    const int64_t tiles = static_cast<int64_t>((M + 15) / 16) * ((N + 15) / 16);
-    if (tiles > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_gemm_bf16: too large");
+    const int64_t blocks = static_cast<int64_t>((M + GB - 1) / GB) * ((N + GB - 1) / GB);
+    if (blocks > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_gemm_bf16: too large");
     Gemm g{M, N, K, A, sa_i, sa_k, B, sb_k, sb_j, bias, act, Z, C, ldc, Cb};
-    hipLaunchKernelGGL(k_gemm, dim3(static_cast<unsigned>((tiles + 3) / 4)), dim3(256), 0, stream, g);
+    hipLaunchKernelGGL(k_gemm, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, g);
     return check_hip(hipGetLastError(), "ht_gemm_bf16 launch");
 }
 
