@@ -637,9 +637,9 @@ def csrc_hash():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(profile):
-    """HBM bytes per step from a committed rocprofv3 counter summary, if it was taken on
-    the kernels as they are now (same source hash); otherwise None."""
+def profiled_traffic(profile, stage):
+    """HBM bytes per step of `stage` from a committed rocprofv3 counter summary, if it was
+    taken on the kernels as they are now (same source hash); otherwise None."""
     path = os.path.join(ROOT, "profiles", profile)
     try:
         text = open(path).read()
@@ -647,7 +647,7 @@ def profiled_traffic(profile):
         return None
     import re
     mh = re.search(r"csrc_sha256=([0-9a-f]+)", text)
-    mt = re.search(r"TRAFFIC_BYTES_PER_STEP=([0-9.]+)", text)
+    mt = re.search(r"TRAFFIC_BYTES_PER_STEP\[%s\]=([0-9.]+)" % re.escape(stage), text)
     if not mh or not mt or mh.group(1) != csrc_hash():
         return None
     return float(mt.group(1))
@@ -767,7 +767,7 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": amount / sec / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = profiled_traffic(wl.profile) if getattr(wl, "profile", None) else None
+    roof["traffic"] = profiled_traffic(wl.profile, dom) if getattr(wl, "profile", None) else None
     roof["kernel"] = dom
 
     cpu = None
