@@ -4,7 +4,7 @@
 //   Y_k = post_k * sum_j b_{k-j} (pre_j x_j),  k < N,
 // a circular convolution of length M >= 2N - 1 done as FFT, pointwise product with the
 // precomputed spectrum B = FFT_M(b) / M, inverse FFT.  M = S * P with P = 2^LOGP held in
-// LDS; for S = 2 (M = 16384 = TWN) the length-M transforms are split by even / odd
+// LDS; for S = 2 (M = 2P > 8192) the length-M transforms are split by even / odd
 // frequency into two length-P halves (the input occupies the first P points only, and
 // only the first N <= P outputs are kept).  The first half's finished values are parked
 // by the caller (in its output buffer) and added back after the second half, so only
@@ -38,7 +38,7 @@ __device__ __forceinline__ void chirp_core(OutT (&out)[SL], const Chirp& ch, int
         for (int k = 0; k < SL; ++k) {
             const int j = tid + k * BLOCK;
             v[k] = j < N ? cmul(in(k, j), tload(ch.pre, j)) : make_double2(0.0, 0.0);
-            if (s == 1) v[k] = cmul(v[k], tload(tw, j));  // exp(-2 pi i j / M)
+            if (s == 1) v[k] = cmul(v[k], tload(tw, j * (TWN >> (LOGP + 1))));  // exp(-2 pi i j / M)
         }
         __builtin_amdgcn_sched_barrier(0);
         fft_slots<LOGP, -1, SL>(v, lds, tw);
@@ -53,7 +53,7 @@ __device__ __forceinline__ void chirp_core(OutT (&out)[SL], const Chirp& ch, int
             const int j = tid + k * BLOCK;
             if (j < N) {
                 double2 c = v[k];
-                if (s == 1) c = cmulc(c, tload(tw, j));  // exp(+2 pi i j / M)
+                if (s == 1) c = cmulc(c, tload(tw, j * (TWN >> (LOGP + 1))));  // exp(+2 pi i j / M)
                 const double2 y2 = cmul(c, tload(ch.post, j));
                 OutT y;
                 if constexpr (REAL)

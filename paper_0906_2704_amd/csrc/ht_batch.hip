@@ -137,7 +137,11 @@ template <int LOGP, int S, int SL, int MODE>
 __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int cls, int start, int count) {
     constexpr int P = 1 << LOGP;
     constexpr int BLOCK = P / SL;
+    // cross-part GCV reduction buffer: only 64-thread groups can need more than one pass
+    // over the grid (K > 2 * BLOCK); otherwise the reduction reuses the staging buffer
+    constexpr int RED = BLOCK < BATCH_MAX_K / 2 ? 2 * BLOCK : 1;
     __shared__ double2 lds[P];
+    __shared__ double2 red_small[RED];
     __shared__ double Gs[BATCH_MAX_K];
     __shared__ double2 bc[3];
     __shared__ int s_item, s_kbest, s_fall;
@@ -346,13 +350,57 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
         };
         const int K = a.K;
         const double* mus = a.mus + static_cast<int64_t>(sg.item) * K;
-        // G_k for k in [klo, khi] into Gs (and a.G): one wave per pair of grid values, its
-        // lanes striding over the staged elements, then a fixed-order butterfly across the
-        // lanes.  The staged pairs are only read.
-        auto eval_range = [&](int klo, int khi) {
-            constexpr int NW = BLOCK / 64;
+        // G_k for k in [klo, khi] into Gs (and a.G), two grid values per evaluation.  Long
+        // ranges: the lanes take different pairs and the workgroup splits the elements into
+        // at most MAX_PARTS parts (all lanes of a part read the same staged element), the
+        // parts are added in order through LDS (this overwrites the staged pairs).  Short
+        // ranges (would need more parts): one wave per pair, its lanes striding over the
+        // elements, a fixed-order butterfly across the lanes; the staged pairs survive.
+        // Returns whether the staged pairs are still in place.
+        double2* red = lds;
+        auto eval_range = [&](int klo, int khi) -> bool {
+            constexpr int MAX_PARTS = 16;
             const int cnt = khi - klo + 1;
             const int Kh = (cnt + 1) / 2;
+            const int Kb = Kh < BLOCK ? Kh : BLOCK;
+            const int nparts = BLOCK / Kb;
+            if (nparts <= MAX_PARTS) {
+                const int part = tid / Kb, kl = tid - part * Kb;
+                const bool one_pass = Kh <= Kb;
+                double2* rbuf = one_pass ? red : red_small;
+                for (int k0 = 0; k0 < Kh; k0 += Kb) {
+                    const int kk = k0 + kl;
+                    double Na = 0.0, Da = 0.0, Nb = 0.0, Db = 0.0;
+                    if (part < nparts && kk < Kh) {
+                        const int ka = klo + 2 * kk, kb2 = ka + 1 <= khi ? ka + 1 : ka;
+                        gcv_two(stage, n, part, nparts, mus[ka], mus[kb2], Na, Da, Nb, Db);
+                    }
+                    if (one_pass) __syncthreads();
+                    rbuf[2 * tid] = make_double2(Na, Da);
+                    rbuf[2 * tid + 1] = make_double2(Nb, Db);
+                    __syncthreads();
+                    if (part == 0 && kk < Kh) {
+                        double2 A = rbuf[2 * kl], B = rbuf[2 * kl + 1];
+                        for (int p = 1; p < nparts; ++p) {
+                            const double2 va = rbuf[2 * (p * Kb + kl)], vb = rbuf[2 * (p * Kb + kl) + 1];
+                            A.x += va.x;
+                            A.y += va.y;
+                            B.x += vb.x;
+                            B.y += vb.y;
+                        }
+                        const int ka = klo + 2 * kk;
+                        Gs[ka] = A.x / (A.y * A.y);
+                        if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka] = Gs[ka];
+                        if (ka + 1 <= khi) {
+                            Gs[ka + 1] = B.x / (B.y * B.y);
+                            if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka + 1] = Gs[ka + 1];
+                        }
+                    }
+                    __syncthreads();
+                }
+                return !one_pass;  // red_small leaves the staged pairs alone
+            }
+            constexpr int NW = BLOCK / 64;
             const int wv = tid >> 6, lane = tid & 63;
             for (int k0 = 0; k0 < Kh; k0 += NW) {
                 const int kk = k0 + wv;
@@ -378,6 +426,7 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
                 }
             }
             __syncthreads();
+            return true;
         };
         // first minimum over [klo, khi]; -1 if some G is not finite
         auto argmin_range = [&](int klo, int khi) {
@@ -437,14 +486,15 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
             const int lo = khat - half < 0 ? 0 : khat - half;
             const int hi = khat + half > K - 1 ? K - 1 : khat + half;
             stage_fill();
-            eval_range(lo, hi);
+            const bool staged = eval_range(lo, hi);
             const int km = argmin_range(lo, hi);
             const bool edge = (km == lo && lo > 0) || (km == hi && hi < K - 1);
             const bool ok = km >= 0 && !edge && Gs[khat] <= CERT_SLACK * Gs[km];
             if (ok) {
                 kstar = km;
             } else {
-                eval_range(0, K - 1);  // the staged pairs are still in place
+                if (!staged) stage_fill();  // the part sums went through the staging buffer
+                eval_range(0, K - 1);
                 kstar = argmin_range(0, K - 1);
             }
             if (tid == 0) a.fallback[sg.item] = ok ? 0 : 1;
@@ -539,6 +589,7 @@ namespace {
 constexpr int SPLIT_MAX_GRID = 1024;  // persistent workgroups of the split class (scratch rows)
 
 int class_logp(int c) { return c == 5 ? 13 : MIN_LOGP + c; }
+bool is_split(int c) { return c == 5; }
 bool has_variant(int c) { return class_logp(c) >= 12; }
 
 template <int LOGP, int S, int SL>
@@ -709,7 +760,7 @@ extern "C" ht_status ht_batch_create(int64_t count, const int64_t* n, const int*
     bool ok = hipMalloc(&bt->d_axes, sizeof(Axis) * nax) == hipSuccess &&
               hipMalloc(&bt->d_sigs, sizeof(RSig) * count) == hipSuccess &&
               hipMalloc(&bt->d_counters, sizeof(int) * NCLASS) == hipSuccess;
-    if (ok && bt->class_count[5] > 0)
+    if (ok && bt->class_count[5] > 0)  // the split class
         ok = hipMalloc(&bt->d_scratch, sizeof(double) * MAX_N * SPLIT_MAX_GRID) == hipSuccess;
     ok = ok && hipMemcpy(bt->d_axes, axes.data(), sizeof(Axis) * nax, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(bt->d_sigs, sigs.data(), sizeof(RSig) * count, hipMemcpyHostToDevice) == hipSuccess;
@@ -745,7 +796,7 @@ extern "C" ht_status ht_batch_schedule(ht_batch* bt, int size_class, int workgro
     }
     if (workgroups > 0) {
         int cap = std::max(1, bt->class_count[size_class]);
-        if (size_class == 5) cap = std::min(cap, SPLIT_MAX_GRID);
+        if (is_split(size_class)) cap = std::min(cap, SPLIT_MAX_GRID);
         bt->grid[size_class] = std::max(1, std::min(workgroups, cap));
     }
     if (cur_workgroups) *cur_workgroups = bt->grid[size_class];

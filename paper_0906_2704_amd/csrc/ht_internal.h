@@ -17,6 +17,10 @@ constexpr int TWN = 16384;
 constexpr int MAX_N = 8192;
 constexpr int MAX_LOGP = 13;  // largest LDS-resident FFT: 8192 complex doubles = 128 KiB
 constexpr int MIN_LOGP = 9;   // smallest FFT (one wave of 64 threads, 8 points each)
+// Convolution lengths M > 8192 run as two LDS-resident halves of M / 2 points (even and
+// odd frequencies).  (Splitting M = 8192 as well halves its LDS but measured slower: the
+// split kernel's registers then allow only one 512-thread workgroup per CU.)
+constexpr int SPLIT_M = 16384;
 
 enum OutMode { MODE_RE = 0, MODE_IM = 1, MODE_CPLX = 2 };
 

@@ -218,11 +218,11 @@ ht_status build_axis(int n, int kind, HostAxis& h) {
     int M = 512;
     while (M < 2 * N - 1) M <<= 1;
     h.M = M;
-    a.S = M > 8192 ? 2 : 1;
+    a.S = M >= SPLIT_M ? 2 : 1;
     const int P = M / a.S;
     a.logP = 0;
     while ((1 << a.logP) < P) ++a.logP;
-    if (a.logP < MIN_LOGP || a.logP > MAX_LOGP || (a.S == 2 && M != TWN))
+    if (a.logP < MIN_LOGP || a.logP > MAX_LOGP || M > TWN)
         return fail(HT_ERR_INVALID_ARG, "internal: unsupported FFT size");
     a.rank = kind == HT_KIND_DST2 ? 1 : kind == HT_KIND_DST3 ? 2 : 0;
 

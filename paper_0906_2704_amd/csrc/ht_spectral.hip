@@ -130,22 +130,63 @@ __device__ __forceinline__ double rcp_nr(double u) {
 // With sigma_i = |s_i|^2 / (|d_i|^2 + mu |s_i|^2) = 1 / (t_i + mu), t_i = |d_i|^2/|s_i|^2,
 // the two sums of eq. mugcv are D(mu) = sum_i 1/(t_i + mu), N(mu) = sum_i w_i/(t_i + mu)^2
 // with w_i = |ghat_i|^2.  Entries with s_i = 0 have sigma_i = 0; they are staged with
-// w = 0 and t = 1e300 so that their contribution to both sums rounds away exactly.
-// Thread (part, kl) accumulates mu_{k0 + kl} over the elements part, part + nparts, ...
-// of each staged chunk; chunk totals are added in order, parts are added in order: the
-// result does not depend on scheduling.
+// w = 0 and t = 1e150, so that their 1/(t + mu) ~ 1e-150 rounds away against the other
+// terms of D (and products of two staged t stay finite).
+// Sums of two grid values (mua, mub) over the staged pairs part, part + nparts, ... < len,
+// two elements at a time with one reciprocal per element pair and grid value:
+// 1/u0 = u1 / (u0 u1), 1/u1 = u0 / (u0 u1).  The staged t never exceeds 1e150, so the
+// products stay finite.
+__device__ __forceinline__ void gcv_pair_sums(const double2* stage, int len, int part, int nparts, double mua,
+                                              double mub, double& Na, double& Da, double& Nb, double& Db) {
+    double na0 = 0.0, na1 = 0.0, da0 = 0.0, da1 = 0.0;
+    double nb0 = 0.0, nb1 = 0.0, db0 = 0.0, db1 = 0.0;
+    int i = part;
+    for (; i + nparts < len; i += 2 * nparts) {
+        const double2 p0 = stage[i], p1 = stage[i + nparts];
+        const double ua0 = p0.x + mua, ua1 = p1.x + mua;
+        const double ub0 = p0.x + mub, ub1 = p1.x + mub;
+        const double ra = rcp_nr(ua0 * ua1), rb = rcp_nr(ub0 * ub1);
+        const double ra0 = ua1 * ra, ra1 = ua0 * ra, rb0 = ub1 * rb, rb1 = ub0 * rb;
+        da0 += ra0;
+        da1 += ra1;
+        db0 += rb0;
+        db1 += rb1;
+        na0 = fma(p0.y, ra0 * ra0, na0);
+        na1 = fma(p1.y, ra1 * ra1, na1);
+        nb0 = fma(p0.y, rb0 * rb0, nb0);
+        nb1 = fma(p1.y, rb1 * rb1, nb1);
+    }
+    if (i < len) {
+        const double2 p0 = stage[i];
+        const double ra = rcp_nr(p0.x + mua), rb = rcp_nr(p0.x + mub);
+        da0 += ra;
+        db0 += rb;
+        na0 = fma(p0.y, ra * ra, na0);
+        nb0 = fma(p0.y, rb * rb, nb0);
+    }
+    Na = na0 + na1;
+    Da = da0 + da1;
+    Nb = nb0 + nb1;
+    Db = db0 + db1;
+}
+
+// Thread (part, kl) accumulates the grid values 2 (k0 + kl) and 2 (k0 + kl) + 1 over the
+// staged elements part, part + nparts, ... of each chunk; chunk totals are added in order,
+// parts are added in order: the result does not depend on scheduling.
 __device__ void gcv_accumulate(const Spec& sp, const void* coeff, int64_t b, int64_t e_begin,
                                int64_t e_end, const double* mus, int K, double2* part_out,
                                double2* stage, double2* red) {
     const int tid = threadIdx.x;
-    const int Kb = K < GCV_THREADS ? K : GCV_THREADS;
+    const int Kh = (K + 1) / 2;
+    const int Kb = Kh < GCV_THREADS ? Kh : GCV_THREADS;
     const int nparts = GCV_THREADS / Kb;
     const int part = tid / Kb, kl = tid - part * Kb;
-    for (int k0 = 0; k0 < K; k0 += Kb) {
-        const int k = k0 + kl;
-        const bool active = part < nparts && k < K;
-        const double mu = active ? mus[k] : 1.0;
-        double Nt = 0.0, Dt = 0.0;
+    for (int k0 = 0; k0 < Kh; k0 += Kb) {
+        const int kk = k0 + kl;
+        const bool active = part < nparts && kk < Kh;
+        const int ka = 2 * kk, kb2 = ka + 1 < K ? ka + 1 : ka;
+        const double mua = active ? mus[ka] : 1.0, mub = active ? mus[kb2] : 1.0;
+        double Nat = 0.0, Dat = 0.0, Nbt = 0.0, Dbt = 0.0;
         for (int64_t c0 = e_begin; c0 < e_end; c0 += GCV_CHUNK) {
             const int len = static_cast<int>((e_end - c0) < GCV_CHUNK ? (e_end - c0) : GCV_CHUNK);
             __syncthreads();
@@ -156,7 +197,7 @@ __device__ void gcv_accumulate(const Spec& sp, const void* coeff, int64_t b, int
                 spec_at(sp, b, e, dd, ss);
                 const double2 g = cload(coeff, b * sp.per_item + e, sp.cplx);
                 const double s2 = ss * ss;
-                double t = 1e300, w = 0.0;
+                double t = 1e150, w = 0.0;
                 if (s2 != 0.0) {
                     t = fma(dd.x, dd.x, dd.y * dd.y) / s2;
                     w = fma(g.x, g.x, g.y * g.y);
@@ -165,28 +206,31 @@ __device__ void gcv_accumulate(const Spec& sp, const void* coeff, int64_t b, int
             }
             __syncthreads();
             if (active) {
-                double Nc = 0.0, Dc = 0.0;
-                for (int i = part; i < len; i += nparts) {
-                    const double2 tw = stage[i];
-                    const double r = rcp_nr(tw.x + mu);
-                    Dc += r;
-                    Nc = fma(tw.y, r * r, Nc);
-                }
-                Nt += Nc;
-                Dt += Dc;
+                double Na, Da, Nb, Db;
+                gcv_pair_sums(stage, len, part, nparts, mua, mub, Na, Da, Nb, Db);
+                Nat += Na;
+                Dat += Da;
+                Nbt += Nb;
+                Dbt += Db;
             }
         }
         __syncthreads();
-        if (part < nparts) red[part * Kb + kl] = make_double2(Nt, Dt);
+        if (part < nparts) {
+            red[2 * (part * Kb + kl)] = make_double2(Nat, Dat);
+            red[2 * (part * Kb + kl) + 1] = make_double2(Nbt, Dbt);
+        }
         __syncthreads();
-        if (part == 0 && k < K) {
-            double2 acc = red[kl];
+        if (part == 0 && kk < Kh) {
+            double2 A = red[2 * kl], B = red[2 * kl + 1];
             for (int p = 1; p < nparts; ++p) {
-                const double2 v = red[p * Kb + kl];
-                acc.x += v.x;
-                acc.y += v.y;
+                const double2 va = red[2 * (p * Kb + kl)], vb = red[2 * (p * Kb + kl) + 1];
+                A.x += va.x;
+                A.y += va.y;
+                B.x += vb.x;
+                B.y += vb.y;
             }
-            part_out[k] = acc;
+            part_out[ka] = A;
+            if (ka + 1 < K) part_out[ka + 1] = B;
         }
     }
     __syncthreads();
@@ -252,7 +296,7 @@ struct GcvOut {
 
 __global__ __launch_bounds__(GCV_THREADS) void k_gcv_single(Spec sp, const void* __restrict__ coeff, GcvOut o) {
     __shared__ double2 stage[GCV_CHUNK];
-    __shared__ double2 red[GCV_THREADS];
+    __shared__ double2 red[2 * GCV_THREADS];
     __shared__ double2 sums[1024];
     __shared__ double Gs[1024];
     __shared__ int kshared;
@@ -266,7 +310,7 @@ __global__ __launch_bounds__(GCV_THREADS) void k_gcv_single(Spec sp, const void*
 __global__ __launch_bounds__(GCV_THREADS) void k_gcv_partial(Spec sp, const void* __restrict__ coeff, GcvOut o,
                                                              int64_t span, double2* part) {
     __shared__ double2 stage[GCV_CHUNK];
-    __shared__ double2 red[GCV_THREADS];
+    __shared__ double2 red[2 * GCV_THREADS];
     const int64_t w = blockIdx.x, b = blockIdx.y;
     const int64_t e0 = w * span;
     int64_t e1 = e0 + span;

@@ -168,7 +168,7 @@ template <int LOGP>
 static hipError_t launch_one(const Axis& ax, const double2* tw, bool inverse, const View& in,
                              const View& out, int64_t count, hipStream_t stream) {
     const dim3 grid(static_cast<unsigned>(count)), block(fft_block_for(LOGP));
-    if constexpr (LOGP == MAX_LOGP) {
+    if constexpr (LOGP == MAX_LOGP) {  // split convolutions (M = 16384)
         if (ax.S == 2) {
             if (inverse)
                 hipLaunchKernelGGL((k_inverse<LOGP, 2>), grid, block, 0, stream, ax, in, out, tw);
