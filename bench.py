@@ -288,13 +288,16 @@ class Learned1D:
     the prediction (full scan where it fails), filter and forward transform, as one
     hipGraph replay.  The plain GCV scan runs on the same inputs for comparison."""
 
-    stages = ["features", "predict", "certified_restore"]
     profile = "k_restore_learned65536.md"
 
-    def __init__(self, torch, ht, synth, batch, train=200000, epochs=25, graph=True, workers=16):
+    def __init__(self, torch, ht, synth, batch, train=200000, epochs=25, graph=True, workers=16, path="two-pass"):
         self.torch, self.ht, self.synth = torch, ht, synth
         self.batch, self.train_count, self.epochs = batch, train, epochs
         self.graph = graph
+        self.path = path
+        # fused: one kernel pass per signal (features, network, certificate, filter, forward);
+        # two-pass: feature kernel -> batched network GEMMs -> certified-restore kernel
+        self.stages = ["fused_restore"] if path == "fused" else ["features", "predict", "certified_restore"]
         self.name = "1d_learned_mu_n256-4096_K128_x%d" % batch
         self.kind = "AR/C/DST3"
         # host data first: the generator forks worker processes, before any GPU use
@@ -337,6 +340,9 @@ class Learned1D:
         self.mb = torch.empty(self.batch, dtype=torch.float64, device=dev)
         self.fb = torch.empty(self.batch, dtype=torch.int32, device=dev)
         self.f_scan = torch.empty_like(self.g)
+        self.f_fused = torch.empty_like(self.g)
+        self.pred_fused = torch.empty(self.batch, dtype=torch.float32, device=dev)
+        self.net_weights = self.net.weights()
         self.kb_scan = torch.empty_like(self.kb)
         self.mb_scan = torch.empty_like(self.mb)
         self._launch()  # allocates the network's buffers outside any capture
@@ -363,7 +369,15 @@ class Learned1D:
                                          self.learned.CERT_HALF, kb=self.kb, mb=self.mb, fallback=self.fb,
                                          spectrum=self.spec)
 
+    def _fused(self):
+        self.ht.ht_batch_restore_fused(self.bt, self.g, self.psf, "D2", self.mus, self.net_weights,
+                                       self.learned.CERT_HALF, restored=self.f_fused, kb=self.kb, mb=self.mb,
+                                       fallback=self.fb, pred=self.pred_fused)
+
     def _launch(self):
+        if self.path == "fused":
+            self._fused()
+            return
         self._features()
         self._predict()
         self._certified()
@@ -375,12 +389,16 @@ class Learned1D:
     def step(self, t):
         t.start_step()
         if t.active or self.cuda_graph is None:
-            self._features()
-            t.mark()
-            self._predict()
-            t.mark()
-            self._certified()
-            t.mark()
+            if self.path == "fused":
+                self._fused()
+                t.mark()
+            else:
+                self._features()
+                t.mark()
+                self._predict()
+                t.mark()
+                self._certified()
+                t.mark()
         else:
             self.cuda_graph.replay()
             t.mark()
@@ -402,7 +420,7 @@ class Learned1D:
     def quality(self):
         """Mean restoration error of both paths against the true signals, fallback rate."""
         rb = self.rb
-        f_l = self.coeff.cpu().numpy()
+        f_l = (self.f_fused if self.path == "fused" else self.coeff).cpu().numpy()
         f_s = self.f_scan.cpu().numpy()
         o = rb.offsets
         err = lambda f: np.array([np.linalg.norm(f[o[b]:o[b + 1]] - rb.f_true[o[b]:o[b + 1]])
@@ -417,7 +435,7 @@ class Learned1D:
     def config(self):
         return {"workload": self.name, "batch": self.batch, "n": "U{256..4096}", "sum_n": int(self.rb.n.sum()),
                 "degree": "U{1,2,3}", "norm": "D2", "K": self.K, "grid": "1e-8..10", "graph": self.graph,
-                "certificate_half_width": self.learned.CERT_HALF, "training": self.train_info}
+                "path": self.path, "certificate_half_width": self.learned.CERT_HALF, "training": self.train_info}
 
     def work(self):
         """Algorithmic HBM bytes of each stage (one read of every input and one write of
@@ -426,6 +444,7 @@ class Learned1D:
         B, K = self.batch, self.K
         psf = float(self.rb.psf_flat.size) * 8
         return {
+            "fused_restore": ("hbm", S * 16 + psf + B * K * 8 + B * 24),
             "features": ("hbm", S * 24 + psf + B * 72 * 4),
             "predict": ("mfma", 2.0 * B * (72 * 256 + 2 * 256 * 256 + 256)),
             "certified_restore": ("hbm", S * 24 + psf + B * K * 8 + B * 4 + B * 20),
@@ -448,9 +467,14 @@ class Learned1D:
         params = self.net.params_numpy()
         mean = self.net.mean.cpu().numpy()
         std = self.net.std.cpu().numpy()
-        f = self.coeff.cpu().numpy()
+        if self.path == "fused":  # the fused pass's own features, for the comparison below
+            self.ht.ht_batch_restore_fused(self.bt, self.g, self.psf, "D2", self.mus, self.net_weights,
+                                           self.learned.CERT_HALF, restored=self.f_fused, kb=self.kb, mb=self.mb,
+                                           fallback=self.fb, pred=self.pred_fused, features=self.feats)
+            self.torch.cuda.synchronize()
+        f = (self.f_fused if self.path == "fused" else self.coeff).cpu().numpy()
         kb = self.kb.cpu().numpy()
-        pred = self.pred.cpu().numpy()
+        pred = (self.pred_fused if self.path == "fused" else self.pred).cpu().numpy()
         feats = self.feats.cpu().numpy()
         worst = 0.0
         self.pred_diff = 0.0
@@ -673,6 +697,8 @@ def main():
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x3"], help="mixed: core arithmetic")
     ap.add_argument("--train", type=int, default=200000, help="learned: training problems")
     ap.add_argument("--epochs", type=int, default=25, help="learned: training epochs")
+    ap.add_argument("--learned-path", default="two-pass", choices=["two-pass", "fused"],
+                    help="learned: one fused pass per signal, or feature pass + network + certified pass")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -692,7 +718,7 @@ def main():
     if args.workload == "learned":
         # host data before anything touches the GPU (the generator forks workers)
         pre = Learned1D(None, None, synth, args.batch or 65536, train=args.train, epochs=args.epochs,
-                        graph=not args.no_graph, workers=min(16, os.cpu_count() or 1))
+                        graph=not args.no_graph, workers=min(16, os.cpu_count() or 1), path=args.learned_path)
 
     import torch
     from paper_0906_2704_amd import ht

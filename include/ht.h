@@ -246,6 +246,29 @@ ht_status ht_batch_restore_learned(const ht_batch* batch, double* coeff_restored
                                    double* G, int32_t* k_best, double* mu_best,
                                    int32_t* fallback, hipStream_t stream);
 
+/* The network of the learned-mu predictor as device pointers: weights w[l] bfloat16
+ * (uint16_t bit patterns) row-major [in][out] for the layers 72 -> 256 -> 256 -> 256 -> 1,
+ * biases b[l] float32 [out], feature standardisation mean / std float32 [72].           */
+typedef struct {
+    const uint16_t* w[4];
+    const float* b[4];
+    const float* mean;
+    const float* std;
+} ht_mlp_weights;
+
+/* ht_batch_restore_fused -- the learned-mu restoration in one pass per signal: inverse
+ * transform, eigenvalues, the 72 features of ht_batch_features, the network's prediction
+ * of log10 mu (exact GELU, bfloat16 rounding of the standardised features and of every
+ * hidden activation, float32 accumulation: the rounding points of ht_gemm_bf16 with
+ * act = 1 and Cb), then the certificate and fallback of ht_batch_restore_learned, the
+ * filter and the forward transform.  restored [total_length] must not overlap signal;
+ * pred [count] and features [count][72] (float32) are optional outputs.  Needs n >= 66. */
+ht_status ht_batch_restore_fused(const ht_batch* batch, const double* signal, const double* psf,
+                                 int norm, const double* mu_grid, int32_t K,
+                                 const ht_mlp_weights* net, int32_t cert_half, double* restored,
+                                 int32_t* k_best, double* mu_best, int32_t* fallback, float* pred,
+                                 float* features, hipStream_t stream);
+
 /* Network kernels (row-major matrices; bfloat16 stored as uint16_t bit patterns):
  * ht_gemm_bf16: C = act(A B + bias), A(i,k) = A[i sa_i + k sa_k], B(k,j) = B[k sb_k + j sb_j]
  *   (bfloat16), float32 accumulation on the matrix cores; act 0 = none, 1 = GELU

@@ -55,15 +55,26 @@ struct RaggedArgs {
     float* feat;        // feature mode: [count][NFEAT]
     int cert_half;      // learned mode: certificate bracket half-width in grid steps
     double* spec;       // feature mode: blur eigenvalues written here; learned mode: read (or null)
+    // fused mode: the network 72 -> 256 -> 256 -> 256 -> 1 (bfloat16 weights [in][out],
+    // float32 biases, feature standardisation); pred / feat receive the prediction and the
+    // features when non-null
+    const uint16_t* w[4];
+    const float* bias[4];
+    const float* fmean;
+    const float* fstd;
+    float* pred_out;
 };
 
 // What one pass of the fused kernel does with each signal.
 enum BatchMode {
     MODE_SCAN = 0,      // inverse, eigenvalues, full GCV scan, filter, forward
     MODE_FEATURES = 1,  // inverse, eigenvalues, band statistics; the coefficients go to f
-    MODE_LEARNED = 2    // coefficients from f, eigenvalues, GCV certificate around the
+    MODE_LEARNED = 2,   // coefficients from f, eigenvalues, GCV certificate around the
                         // predicted mu (full scan if it fails), filter, forward
+    MODE_FUSED = 3      // inverse, eigenvalues, features, the network's prediction, then as
+                        // MODE_LEARNED: one pass per signal
 };
+constexpr int MLP_H = 256;  // hidden width of the network
 constexpr int NFEAT_G = 64, NFEAT_D = 8, NFEAT = NFEAT_G + NFEAT_D;
 constexpr double CERT_SLACK = 1.05;   // G(predicted) may exceed the bracket minimum by 5%
 
@@ -133,6 +144,54 @@ __device__ __forceinline__ T uniform_load(const T* p) {
     return out;
 }
 
+// float32 -> bfloat16 (round to nearest even) -> float32, and the exact GELU: the rounding
+// points and activation of the network kernels of the learned-mu predictor.
+__device__ __forceinline__ float bf16_round(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+__device__ __forceinline__ float bf16_load(const uint16_t* p, int i) {
+    return __uint_as_float(static_cast<uint32_t>(p[i]) << 16);
+}
+__device__ __forceinline__ float gelu_exact(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+
+// One dense layer of the network for one signal, in LDS: out[j] = act(sum_k in[k] W[k][j]
+// + b[j]) for j < 256.  With BLOCK >= 256 the contraction is split into BLOCK / 256 equal
+// ranges whose float32 partial sums are added in order; smaller workgroups give each
+// thread 256 / BLOCK outputs.  act: 1 = GELU then bfloat16 rounding, 0 = none.
+template <int BLOCK>
+__device__ __forceinline__ void mlp_layer(const float* in, int K, const uint16_t* __restrict__ W,
+                                          const float* __restrict__ b, float* out, float* part, int act) {
+    const int tid = threadIdx.x;
+    if constexpr (BLOCK >= MLP_H) {
+        constexpr int G = BLOCK / MLP_H;
+        const int j = tid % MLP_H, gi = tid / MLP_H;
+        const int k0 = gi * K / G, k1 = (gi + 1) * K / G;
+        float acc = 0.0f;
+#pragma unroll 2
+        for (int k = k0; k < k1; ++k) acc = fmaf(in[k], bf16_load(W, k * MLP_H + j), acc);
+        part[gi * MLP_H + j] = acc;
+        __syncthreads();
+        if (gi == 0) {
+            float z = part[j];
+#pragma unroll
+            for (int q = 1; q < G; ++q) z += part[q * MLP_H + j];
+            z += b[j];
+            out[j] = act ? bf16_round(gelu_exact(z)) : z;
+        }
+    } else {
+        for (int j = tid; j < MLP_H; j += BLOCK) {
+            float acc = 0.0f;
+#pragma unroll 2
+            for (int k = 0; k < K; ++k) acc = fmaf(in[k], bf16_load(W, k * MLP_H + j), acc);
+            const float z = acc + b[j];
+            out[j] = act ? bf16_round(gelu_exact(z)) : z;
+        }
+    }
+    __syncthreads();
+}
+
 template <int LOGP, int S, int SL, int MODE>
 __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int cls, int start, int count) {
     constexpr int P = 1 << LOGP;
@@ -145,6 +204,7 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
     __shared__ double Gs[BATCH_MAX_K];
     __shared__ double2 bc[3];
     __shared__ int s_item, s_kbest, s_fall;
+    __shared__ float s_pred;
     const int tid = threadIdx.x;
     double* scratch = a.scratch + static_cast<int64_t>(blockIdx.x) * MAX_N;
     for (;;) {
@@ -276,7 +336,8 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
         }
         __syncthreads();
 
-        if constexpr (MODE == MODE_FEATURES) {
+        __shared__ float s_feat[NFEAT];
+        if constexpr (MODE == MODE_FEATURES || MODE == MODE_FUSED) {
             // band means of log10(|ghat_j|^2 + 1e-20) (64 bands) and log10(|d_j|^2 + 1e-20) (8 bands) over the
             // normalised core frequency j / N; band b holds j with floor(B j / N) = b
             // (float32 logarithms: the features are float32)
@@ -309,7 +370,11 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
                 for (int j = j0 + r; j < j1; j += G1) acc += lg[j].x;
 #pragma unroll
                 for (int o = G1 / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-                if (r == 0) a.feat[static_cast<int64_t>(sg.item) * NFEAT + b] = static_cast<float>(acc / (j1 - j0));
+                if (r == 0) {
+                    const float v = static_cast<float>(acc / (j1 - j0));
+                    if (MODE == MODE_FUSED) s_feat[b] = v;
+                    if (a.feat) a.feat[static_cast<int64_t>(sg.item) * NFEAT + b] = v;
+                }
             }
             {
                 constexpr int G2 = BLOCK / NFEAT_D < 64 ? BLOCK / NFEAT_D : 64;
@@ -321,12 +386,37 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
                     for (int j = j0 + r; j < j1; j += G2) acc += lg[j].y;
 #pragma unroll
                     for (int o = G2 / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-                    if (r == 0)
-                        a.feat[static_cast<int64_t>(sg.item) * NFEAT + NFEAT_G + b] = static_cast<float>(acc / (j1 - j0));
+                    if (r == 0) {
+                        const float v = static_cast<float>(acc / (j1 - j0));
+                        if (MODE == MODE_FUSED) s_feat[NFEAT_G + b] = v;
+                        if (a.feat) a.feat[static_cast<int64_t>(sg.item) * NFEAT + NFEAT_G + b] = v;
+                    }
                 }
             }
             __syncthreads();
-            continue;
+            if constexpr (MODE == MODE_FEATURES) continue;
+            // ---- the network's log10 mu for this signal (fused mode), computed in LDS:
+            // activations at [0, 256) and [256, 512) floats, layer partial sums behind them
+            float* act = reinterpret_cast<float*>(lds);
+            float* part = act + 2 * MLP_H;
+            for (int i = tid; i < NFEAT; i += BLOCK) act[i] = bf16_round((s_feat[i] - a.fmean[i]) / a.fstd[i]);
+            __syncthreads();
+            mlp_layer<BLOCK>(act, NFEAT, a.w[0], a.bias[0], act + MLP_H, part, 1);
+            mlp_layer<BLOCK>(act + MLP_H, MLP_H, a.w[1], a.bias[1], act, part, 1);
+            mlp_layer<BLOCK>(act, MLP_H, a.w[2], a.bias[2], act + MLP_H, part, 1);
+            if (tid < 64) {  // output layer: four inputs per lane, then a fixed-order butterfly
+                float y = 0.0f;
+#pragma unroll
+                for (int k = 4 * tid; k < 4 * tid + 4; ++k) y = fmaf(act[MLP_H + k], bf16_load(a.w[3], k), y);
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) y += __shfl_xor(y, o, 64);
+                if (tid == 0) {
+                    y += a.bias[3][0];
+                    s_pred = y;
+                    if (a.pred_out) a.pred_out[sg.item] = y;
+                }
+            }
+            __syncthreads();
         }
 
         __builtin_amdgcn_sched_barrier(0);
@@ -456,10 +546,10 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
             return __builtin_amdgcn_readfirstlane(s_kbest);
         };
         int kstar;
-        if constexpr (MODE == MODE_LEARNED) {
+        if constexpr (MODE == MODE_LEARNED || MODE == MODE_FUSED) {
             // nearest grid index to the prediction, then the certificate bracket
             if (tid < 64) {  // wave 0: lane-strided scan, then a first-index argmin across lanes
-                const double pr = static_cast<double>(a.pred[sg.item]);
+                const double pr = static_cast<double>(MODE == MODE_FUSED ? s_pred : a.pred[sg.item]);
                 int kh = K;
                 double bd = __builtin_inf();
                 for (int k = tid; k < K; k += 64) {
@@ -622,6 +712,8 @@ void launch_class(const RaggedArgs& a, int mode, int c, int start, int cnt, int 
         hipLaunchKernelGGL((k_restore<LOGP, S, SL, MODE_FEATURES>), g, b, 0, stream, a, c, start, cnt);
     else if (mode == MODE_LEARNED)
         hipLaunchKernelGGL((k_restore<LOGP, S, SL, MODE_LEARNED>), g, b, 0, stream, a, c, start, cnt);
+    else if (mode == MODE_FUSED)
+        hipLaunchKernelGGL((k_restore<LOGP, S, SL, MODE_FUSED>), g, b, 0, stream, a, c, start, cnt);
     else
         hipLaunchKernelGGL((k_restore<LOGP, S, SL, MODE_SCAN>), g, b, 0, stream, a, c, start, cnt);
 }
@@ -785,6 +877,31 @@ extern "C" ht_status ht_batch_destroy(ht_batch* bt) {
 
 extern "C" int64_t ht_batch_total_length(const ht_batch* bt) { return bt ? bt->total_n : -1; }
 extern "C" int64_t ht_batch_psf_total(const ht_batch* bt) { return bt ? bt->total_psf : -1; }
+
+extern "C" ht_status ht_batch_restore_fused(const ht_batch* bt, const double* signal, const double* psf, int norm,
+                                            const double* mu_grid, int32_t K, const ht_mlp_weights* net,
+                                            int32_t cert_half, double* restored, int32_t* k_best, double* mu_best,
+                                            int32_t* fallback, float* pred, float* features, hipStream_t stream) {
+    if (!bt) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_fused: null batch");
+    if (bt->count == 0) return HT_OK;
+    if (!signal || !psf || !mu_grid || !net || !restored || !k_best || !mu_best || !fallback)
+        return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_fused: null argument");
+    for (int l = 0; l < 4; ++l)
+        if (!net->w[l] || !net->b[l]) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_fused: null network weight");
+    if (!net->mean || !net->std) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_fused: null standardisation");
+    if (signal == restored) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_fused: signal and restored must not overlap");
+    if (norm != HT_NORM_IDENTITY && norm != HT_NORM_SECOND_DIFF)
+        return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_fused: bad norm");
+    if (K < 1 || K > BATCH_MAX_K) return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_fused: K must be in [1, 256]");
+    if (cert_half < 1 || cert_half >= K)
+        return fail(HT_ERR_INVALID_ARG, "ht_batch_restore_fused: cert_half must be in [1, K-1]");
+    if (bt->min_n < NFEAT_G + 2) return fail(HT_ERR_UNSUPPORTED, "ht_batch_restore_fused: needs n >= 66 (64 bands)");
+    RaggedArgs a{bt->d_axes, bt->d_sigs, bt->d_counters, signal, psf, mu_grid, K, norm, restored, nullptr, k_best,
+                 mu_best, bt->d_scratch, nullptr, fallback, features, cert_half, nullptr,
+                 {net->w[0], net->w[1], net->w[2], net->w[3]}, {net->b[0], net->b[1], net->b[2], net->b[3]},
+                 net->mean, net->std, pred};
+    return run_classes(bt, a, MODE_FUSED, stream);
+}
 
 extern "C" ht_status ht_batch_schedule(ht_batch* bt, int size_class, int workgroups, int variant,
                                        int* cur_workgroups, int* cur_variant) {

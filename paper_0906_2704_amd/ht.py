@@ -319,6 +319,8 @@ def _learned_sigs(L):
     Ci = ctypes.c_int
     L.ht_batch_features.argtypes = [VP, VP, VP, VP, VP, VP, VP]
     L.ht_batch_restore_learned.argtypes = [VP, VP, VP, VP, Ci, VP, I32, VP, I32, VP, VP, VP, VP, VP]
+    L.ht_batch_restore_fused.argtypes = [VP, VP, VP, Ci, VP, I32, ctypes.POINTER(MlpWeights), I32, VP, VP, VP, VP, VP,
+                                         VP, VP]
     L.ht_gemm_bf16.argtypes = [Ci, Ci, Ci, VP, I64, I64, VP, I64, I64, VP, Ci, VP, VP, I64, VP, VP]
     L.ht_to_bf16.argtypes = [VP, VP, I64, Ci, VP, VP, VP]
     L.ht_from_bf16.argtypes = [VP, VP, I64, VP]
@@ -327,7 +329,7 @@ def _learned_sigs(L):
     L.ht_mse_grad.argtypes = [VP, VP, VP, VP, I64, VP]
     L.ht_outer.argtypes = [VP, VP, VP, I64, Ci, VP]
     L.ht_adam.argtypes = [VP, VP, VP, VP, I64, F, F, F, F, I64, VP, VP]
-    for name in ("ht_batch_features", "ht_batch_restore_learned", "ht_gemm_bf16", "ht_to_bf16", "ht_from_bf16",
+    for name in ("ht_batch_features", "ht_batch_restore_learned", "ht_batch_restore_fused", "ht_gemm_bf16", "ht_to_bf16", "ht_from_bf16",
                  "ht_gelu_backward", "ht_colsum", "ht_mse_grad", "ht_outer", "ht_adam"):
         getattr(L, name).restype = ctypes.c_int
 
@@ -351,6 +353,45 @@ def _p(t, name, dtype=None):
 
 
 BF16 = torch.bfloat16
+
+
+class MlpWeights(ctypes.Structure):
+    """ht_mlp_weights: device pointers of the network (bfloat16 weights [in][out], float32
+    biases, feature standardisation)."""
+    _fields_ = [("w", ctypes.c_void_p * 4), ("b", ctypes.c_void_p * 4), ("mean", ctypes.c_void_p),
+                ("std", ctypes.c_void_p)]
+
+
+def mlp_weights(wb, biases, mean, std):
+    """MlpWeights from four bfloat16 weight tensors, four float32 bias tensors, mean, std."""
+    m = MlpWeights()
+    for l in range(4):
+        m.w[l] = _p(wb[l], "w%d" % l, torch.bfloat16).value
+        m.b[l] = _p(biases[l], "b%d" % l, torch.float32).value
+    m.mean = _p(mean, "mean", torch.float32).value
+    m.std = _p(std, "std", torch.float32).value
+    return m
+
+
+def ht_batch_restore_fused(batch, signal, psf, norm, mu_grid, net, cert_half=8, restored=None, kb=None, mb=None,
+                           fallback=None, pred=None, features=None):
+    """One-pass learned-mu restoration (features, network, certificate, filter, forward).
+    `net` is an MlpWeights.  Returns (restored, k_best, mu_best, fallback, pred)."""
+    L = _llib()
+    dev = signal.device
+    K = mu_grid.shape[-1]
+    restored = torch.empty_like(signal) if restored is None else restored
+    kb = torch.empty(batch.count, dtype=torch.int32, device=dev) if kb is None else kb
+    mb = torch.empty(batch.count, dtype=torch.float64, device=dev) if mb is None else mb
+    fallback = torch.empty(batch.count, dtype=torch.int32, device=dev) if fallback is None else fallback
+    pred = torch.empty(batch.count, dtype=torch.float32, device=dev) if pred is None else pred
+    _check(L.ht_batch_restore_fused(batch.handle, _p(signal, "signal", torch.float64), _p(psf, "psf", torch.float64),
+                                    NORMS.get(norm, norm), _p(mu_grid, "mu_grid", torch.float64), int(K),
+                                    ctypes.byref(net), int(cert_half), _p(restored, "restored", torch.float64),
+                                    _p(kb, "k_best", torch.int32), _p(mb, "mu_best", torch.float64),
+                                    _p(fallback, "fallback", torch.int32), _p(pred, "pred", torch.float32),
+                                    _p(features, "features", torch.float32), _stream()), "ht_batch_restore_fused")
+    return restored, kb, mb, fallback, pred
 
 
 def ht_batch_features(batch, signal, psf, coeff=None, features=None, spectrum=None):

@@ -6,7 +6,9 @@ by the GCV scan (ht_batch_restore), with mean squared error and Adam.  Weights a
 masters with bfloat16 copies; every product runs in ht_gemm_bf16 (matrix cores, float32
 accumulation) and every other step in the library's kernels; this module only allocates
 buffers, orders the calls and moves minibatches.  Inference: features -> network ->
-ht_batch_restore_learned (GCV certificate around the prediction, full-scan fallback).
+ht_batch_restore_learned (GCV certificate around the prediction, full-scan fallback), or
+all of it in one fused pass per signal (ht_batch_restore_fused, the network evaluated inside
+the restore kernel with the same rounding points).
 """
 
 import numpy as np
@@ -109,6 +111,10 @@ class Net:
                 ht.ht_gemm_bf16(B, H, H, dZb, (H, 1), self.Pb[l], (1, H), C=dH)
         return sq
 
+    def weights(self):
+        """The network as ht.MlpWeights (device pointers into this object's tensors)."""
+        return ht.mlp_weights(self.Pb, [self.P[1], self.P[3], self.P[5], self.P[7]], self.mean, self.std)
+
     def adam_step(self, lr):
         self.step_count += 1
         for i, p in enumerate(self.P):
@@ -178,6 +184,13 @@ def labels_by_scan(batch, g, psf, mus, norm="D2"):
 
 
 CERT_HALF = 8  # certificate bracket: predicted grid index +- 8 (0.57 decades)
+
+
+def restore_fused(net, batch, g, psf, mus, norm="D2", cert_half=CERT_HALF, restored=None, weights=None, **out):
+    """The learned-mu restoration in one fused pass per signal (features, network,
+    certificate, filter, forward).  Returns (restored, k_best, mu_best, fallback, pred)."""
+    weights = net.weights() if weights is None else weights
+    return ht.ht_batch_restore_fused(batch, g, psf, norm, mus, weights, cert_half, restored=restored, **out)
 
 
 def restore_learned(net, batch, g, psf, mus, norm="D2", coeff=None, feats=None, cert_half=CERT_HALF, spectrum=None):

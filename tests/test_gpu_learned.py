@@ -159,6 +159,45 @@ def test_features_every_size_class(ht):
         assert np.max(np.abs(feats[b] - fw)) < 1e-5 * max(1.0, np.max(np.abs(fw))), (b, int(rb.n[b]))
 
 
+def test_fused_restore_matches_oracle(ht):
+    """The one-pass learned restoration on every FFT size class: features and prediction
+    (network evaluated in the kernel) against the oracle, certificate and restoration."""
+    from paper_0906_2704_amd import learned
+    nv = [256, 257, 300, 511, 1000, 1030, 2000, 2050, 4096, 3000, 700, 260]
+    rb = synth.ragged_batch(len(nv), n_lo=256, n_hi=4096, config=4, first_item=1300, sort_desc=False,
+                            n_values=nv, grid=(-8.0, 1.0))
+    bt = ht.Batch(rb.n, rb.degree, np.diff(rb.psf_offsets), rb.psf_center)
+    g = torch.tensor(rb.g, device=DEV)
+    psf = torch.tensor(rb.psf_flat, device=DEV)
+    mus = torch.tensor(rb.mus, device=DEV)
+    rng = np.random.default_rng(5)
+    params = omlp.init_params(rng)
+    for i in (1, 3, 5):
+        params[i] = (0.1 * rng.standard_normal(params[i].shape)).astype(np.float32)
+    params[7] = np.array([-3.5], dtype=np.float32)  # predictions inside the grid
+    net = learned.Net(DEV)
+    net.set_params(params)
+    _, feats0 = ht.ht_batch_features(bt, g, psf)
+    learned.fit_standardisation(net, feats0)
+    feats = torch.empty((len(nv), 72), dtype=torch.float32, device=DEV)
+    out, kb, mb, fb, pred = learned.restore_fused(net, bt, g, psf, mus, features=feats)
+    out, kb, fb, pred, feats = (t.cpu().numpy() for t in (out, kb, fb, pred, feats))
+    mean, std = net.mean.cpu().numpy(), net.std.cpu().numpy()
+    for b in range(len(nv)):
+        kind, d, s, ghat = _oracle_item(rb, b)
+        fw = olearned.features(ghat, d)
+        assert np.max(np.abs(feats[b] - fw)) < 1e-5 * max(1.0, np.max(np.abs(fw))), b
+        x = (feats[b] - mean) / std  # float32, as the kernel standardises
+        yw, _ = omlp.forward(params, x[None].astype(np.float32), bf=True)
+        assert abs(float(yw.ravel()[0]) - float(pred[b])) < 2e-3 * max(1.0, abs(float(pred[b]))), b
+        Gw = tk.gcv_values(ghat, d, s, rb.mus[b])
+        khat = olearned.nearest_index(rb.mus[b], float(pred[b]))
+        kc, fell = olearned.certify(Gw, khat, half=learned.CERT_HALF)
+        assert kb[b] == kc and bool(fb[b]) == fell, (b, kb[b], kc, fb[b], fell)
+        fr = tr.forward(kind, tk.tikhonov_filter(ghat, d, s, rb.mus[b][kc])).real
+        assert rel_normwise(out[rb.offsets[b]:rb.offsets[b + 1]], fr) < 1e-12, b
+
+
 def test_trained_network_gains_over_scan(ht):
     """Train on problems the method labels itself; on held-out problems the certified
     learned path evaluates far fewer GCV points than the scan at restoration error within
