@@ -203,7 +203,7 @@ __global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int 
     __shared__ double2 red_small[RED];
     __shared__ double Gs[BATCH_MAX_K];
     __shared__ double2 bc[3];
-    __shared__ int s_item, s_kbest, s_fall;
+    __shared__ int s_item, s_kbest;
     __shared__ float s_pred;
     const int tid = threadIdx.x;
     double* scratch = a.scratch + static_cast<int64_t>(blockIdx.x) * MAX_N;
