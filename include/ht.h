@@ -97,17 +97,26 @@ int ht_plan_is_complex(const ht_plan* plan);
  *                        x = x_hi + x_lo into two bfloat16 parts, and the product is
  *                        A_hi B_hi + A_hi B_lo + A_lo B_hi accumulated in float32.
  *   HT_PRECISION_F16X3   the same with float16 parts and a power-of-two scale per row.
+ *   HT_PRECISION_F32     the chirp-z FFT core in float32 (tables rounded from the float64
+ *                        ones), any kind including T_F; the interior correction is rounded
+ *                        to float32 on entry to the core, the result widened on exit.
  * The 2x2 boundary solve, the interior correction, the boundary columns of the forward
  * transform and all inputs and outputs stay float64.  Relative error of one 1D pass is
- * of order 2^-16 (bfloat16) or 2^-21 (float16) of the vector's norm instead of 2^-52. */
-typedef enum { HT_PRECISION_F64 = 0, HT_PRECISION_BF16X3 = 1, HT_PRECISION_F16X3 = 2 } ht_precision;
+ * of order 2^-16 (bfloat16), 2^-21 (float16) or 2^-20 (float32 core) of the vector's
+ * norm instead of 2^-52.                                                                */
+typedef enum {
+    HT_PRECISION_F64 = 0,
+    HT_PRECISION_BF16X3 = 1,
+    HT_PRECISION_F16X3 = 2,
+    HT_PRECISION_F32 = 3
+} ht_precision;
 
 /* ht_plan_set_precision -- choose the core arithmetic of `plan` (ht_precision).  The
  * split-precision cores need real cores on every axis (T_C, antireflective, DST family;
  * HT_ERR_UNSUPPORTED for T_F) and the plan's device current.  Builds the dense split
  * core matrices (2 n^2 x 4 bytes per axis) and a workspace for max_batch signals or
- * images; blocking (synchronises the device).  Not to be called while the plan is in use
- * on a stream.  HT_PRECISION_F64 releases them.                                       */
+ * images, or the float32 tables; blocking (synchronises the device).  Not to be called
+ * while the plan is in use on a stream.  HT_PRECISION_F64 releases them.               */
 ht_status ht_plan_set_precision(ht_plan* plan, int precision);
 /* The plan's ht_precision, or -1 for a null plan. */
 int ht_plan_precision(const ht_plan* plan);

@@ -24,20 +24,24 @@ __device__ __forceinline__ double2 select_out(double2 y, int mode) {
 // in(k, j) returns x_j for the slot k holding j = tid + k * BLOCK < N; the result goes to
 // out[k].  OutT = double2 keeps the complex result (selected by `mode`), OutT = double the
 // real or imaginary part only.  The workgroup has 2^LOGP / SL threads.
-template <int LOGP, int S, int SL, class OutT, class In, class Park, class Unpark>
-__device__ __forceinline__ void chirp_core(OutT (&out)[SL], const Chirp& ch, int mode, int N,
-                                           double2* lds, const double2* __restrict__ tw, In in,
-                                           Park park, Unpark unpark) {
+template <int LOGP, int S, int SL, class OutT, class In, class Park, class Unpark, class C>
+__device__ __forceinline__ void chirp_core(OutT (&out)[SL], const ChirpT<C>& ch, int mode, int N, C* lds,
+                                           const C* __restrict__ tw, In in, Park park, Unpark unpark) {
     constexpr int BLOCK = (1 << LOGP) / SL;
     constexpr bool REAL = sizeof(OutT) == sizeof(double);
     const int tid = threadIdx.x;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        double2 v[SL];
+        C v[SL];
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
             const int j = tid + k * BLOCK;
-            v[k] = j < N ? cmul(in(k, j), tload(ch.pre, j)) : make_double2(0.0, 0.0);
+            if (j < N) {
+                const double2 x = in(k, j);  // float64 input, rounded to the core's type
+                v[k] = cmul(cmake<C>(x.x, x.y), tload(ch.pre, j));
+            } else {
+                v[k] = cmake<C>(0.0, 0.0);
+            }
             if (s == 1) v[k] = cmul(v[k], tload(tw, j * (TWN >> (LOGP + 1))));  // exp(-2 pi i j / M)
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -52,9 +56,10 @@ __device__ __forceinline__ void chirp_core(OutT (&out)[SL], const Chirp& ch, int
         for (int k = 0; k < SL; ++k) {
             const int j = tid + k * BLOCK;
             if (j < N) {
-                double2 c = v[k];
+                C c = v[k];
                 if (s == 1) c = cmulc(c, tload(tw, j * (TWN >> (LOGP + 1))));  // exp(+2 pi i j / M)
-                const double2 y2 = cmul(c, tload(ch.post, j));
+                const C yc = cmul(c, tload(ch.post, j));
+                const double2 y2 = make_double2(yc.x, yc.y);
                 OutT y;
                 if constexpr (REAL)
                     y = mode == MODE_IM ? y2.y : y2.x;

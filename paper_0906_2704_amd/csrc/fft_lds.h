@@ -1,4 +1,5 @@
-// Workgroup-wide complex float64 FFT of a power-of-two length P held in LDS.
+// Workgroup-wide complex FFT (float64, or float32 for the reduced-precision core) of a
+// power-of-two length P held in LDS.
 //
 // Layout: the workgroup has BLOCK = P / SLOTS threads (SLOTS = 8 or 16); thread t owns
 // the "slots" t + s * BLOCK, s = 0..SLOTS-1, held in registers between passes.  Each pass is a Stockham
@@ -18,6 +19,7 @@
 
 namespace ht {
 
+// Complex arithmetic for float64 (double2) and float32 (float2) elements.
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -28,29 +30,58 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
 }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
+}
+
+template <class C>
+__device__ __forceinline__ C cmake(double re, double im);
+template <>
+__device__ __forceinline__ double2 cmake<double2>(double re, double im) { return make_double2(re, im); }
+template <>
+__device__ __forceinline__ float2 cmake<float2>(double re, double im) {
+    return make_float2(static_cast<float>(re), static_cast<float>(im));
+}
+
 // Table read with a 32-bit unsigned element index: lets the compiler address the table
 // as scalar base + 32-bit lane offset instead of a 64-bit address per lane.
 __device__ __forceinline__ double2 tload(const double2* __restrict__ base, unsigned idx) {
     return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + (idx << 4));
 }
-
-// multiply by exp(DIR * i pi / 2): -i for the forward direction, +i for the inverse
-template <int DIR>
-__device__ __forceinline__ double2 rot90(double2 a) {
-    return DIR < 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
+__device__ __forceinline__ float2 tload(const float2* __restrict__ base, unsigned idx) {
+    return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base) + (idx << 3));
 }
 
-template <int DIR>
-__device__ __forceinline__ void dft2(double2& a, double2& b) {
-    double2 t = a;
+// multiply by exp(DIR * i pi / 2): -i for the forward direction, +i for the inverse
+template <int DIR, class C>
+__device__ __forceinline__ C rot90(C a) {
+    C r;
+    if (DIR < 0) {
+        r.x = a.y;
+        r.y = -a.x;
+    } else {
+        r.x = -a.y;
+        r.y = a.x;
+    }
+    return r;
+}
+
+template <int DIR, class C>
+__device__ __forceinline__ void dft2(C& a, C& b) {
+    C t = a;
     a = cadd(t, b);
     b = csub(t, b);
 }
 
-template <int DIR>
-__device__ __forceinline__ void dft4(double2& x0, double2& x1, double2& x2, double2& x3) {
-    double2 a = cadd(x0, x2), b = csub(x0, x2);
-    double2 c = cadd(x1, x3), d = rot90<DIR>(csub(x1, x3));
+template <int DIR, class C>
+__device__ __forceinline__ void dft4(C& x0, C& x1, C& x2, C& x3) {
+    C a = cadd(x0, x2), b = csub(x0, x2);
+    C c = cadd(x1, x3), d = rot90<DIR>(csub(x1, x3));
     x0 = cadd(a, c);
     x2 = csub(a, c);
     x1 = cadd(b, d);
@@ -58,17 +89,25 @@ __device__ __forceinline__ void dft4(double2& x0, double2& x1, double2& x2, doub
 }
 
 // multiply by exp(DIR * i pi / 4)
-template <int DIR>
-__device__ __forceinline__ double2 rot45(double2 a) {
-    const double h = 0.70710678118654752440;  // 1 / sqrt(2)
-    return DIR < 0 ? make_double2((a.x + a.y) * h, (a.y - a.x) * h)
-                   : make_double2((a.x - a.y) * h, (a.x + a.y) * h);
+template <int DIR, class C>
+__device__ __forceinline__ C rot45(C a) {
+    using R = decltype(a.x);
+    const R h = static_cast<R>(0.70710678118654752440);  // 1 / sqrt(2)
+    C r;
+    if (DIR < 0) {
+        r.x = (a.x + a.y) * h;
+        r.y = (a.y - a.x) * h;
+    } else {
+        r.x = (a.x - a.y) * h;
+        r.y = (a.x + a.y) * h;
+    }
+    return r;
 }
 
-template <int DIR>
-__device__ __forceinline__ void dft8(double2 (&u)[8]) {
-    double2 e0 = u[0], e1 = u[2], e2 = u[4], e3 = u[6];
-    double2 o0 = u[1], o1 = u[3], o2 = u[5], o3 = u[7];
+template <int DIR, class C>
+__device__ __forceinline__ void dft8(C (&u)[8]) {
+    C e0 = u[0], e1 = u[2], e2 = u[4], e3 = u[6];
+    C o0 = u[1], o1 = u[3], o2 = u[5], o3 = u[7];
     dft4<DIR>(e0, e1, e2, e3);
     dft4<DIR>(o0, o1, o2, o3);
     o1 = rot45<DIR>(o1);
@@ -80,20 +119,15 @@ __device__ __forceinline__ void dft8(double2 (&u)[8]) {
     u[3] = cadd(e3, o3); u[7] = csub(e3, o3);
 }
 
-template <int R, int DIR>
-__device__ __forceinline__ void dftR(double2 (&u)[R]);
-template <>
-__device__ __forceinline__ void dftR<2, -1>(double2 (&u)[2]) { dft2<-1>(u[0], u[1]); }
-template <>
-__device__ __forceinline__ void dftR<2, 1>(double2 (&u)[2]) { dft2<1>(u[0], u[1]); }
-template <>
-__device__ __forceinline__ void dftR<4, -1>(double2 (&u)[4]) { dft4<-1>(u[0], u[1], u[2], u[3]); }
-template <>
-__device__ __forceinline__ void dftR<4, 1>(double2 (&u)[4]) { dft4<1>(u[0], u[1], u[2], u[3]); }
-template <>
-__device__ __forceinline__ void dftR<8, -1>(double2 (&u)[8]) { dft8<-1>(u); }
-template <>
-__device__ __forceinline__ void dftR<8, 1>(double2 (&u)[8]) { dft8<1>(u); }
+template <int R, int DIR, class C>
+__device__ __forceinline__ void dftR(C (&u)[R]) {
+    if constexpr (R == 2)
+        dft2<DIR>(u[0], u[1]);
+    else if constexpr (R == 4)
+        dft4<DIR>(u[0], u[1], u[2], u[3]);
+    else
+        dft8<DIR>(u);
+}
 
 // Threads per workgroup for an LDS FFT of 2^LOGP points: 8 points per thread up to 4096
 // points, 16 per thread for 8192 (512 threads, so that each wave may use 256 VGPRs).
@@ -102,39 +136,38 @@ __host__ __device__ constexpr int fft_block_for(int logp) { return (1 << logp) /
 
 // One Stockham pass of radix R with Ns = product of the radices of earlier passes (Ns = 1:
 // no twiddles).  LAST: the outputs stay in the thread's own slots.
-template <int R, int DIR, int BLOCK, int SLOTS, bool LAST>
-__device__ __forceinline__ void stockham_pass(double2 (&v)[SLOTS], double2* lds,
-                                              const double2* __restrict__ tw, int Ns) {
-    constexpr int C = SLOTS / R;  // butterflies per thread
+template <int R, int DIR, int BLOCK, int SLOTS, bool LAST, class C>
+__device__ __forceinline__ void stockham_pass(C (&v)[SLOTS], C* lds, const C* __restrict__ tw, int Ns) {
+    constexpr int NB = SLOTS / R;  // butterflies per thread
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
+    for (int c = 0; c < NB; ++c) {
         const int t = tid + c * BLOCK;
-        double2 u[R];
+        C u[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) u[r] = v[c + r * C];
+        for (int r = 0; r < R; ++r) u[r] = v[c + r * NB];
         const int k = t & (Ns - 1);
         if (Ns > 1) {
             // w^r, r = 1..R-1, w = exp(-2 pi i k / (Ns R)): powers 1, 2, 4 from the table,
             // the others as products of two of them (a few ulp, far below the tolerance)
             const unsigned step = static_cast<unsigned>((TWN / R) / Ns * k);
-            const double2 w1 = tload(tw, step);
+            const C w1 = tload(tw, step);
             if constexpr (R == 2) {
                 u[1] = DIR < 0 ? cmul(u[1], w1) : cmulc(u[1], w1);
             } else {
-                const double2 w2 = tload(tw, 2u * step);
+                const C w2 = tload(tw, 2u * step);
                 u[1] = DIR < 0 ? cmul(u[1], w1) : cmulc(u[1], w1);
                 u[2] = DIR < 0 ? cmul(u[2], w2) : cmulc(u[2], w2);
-                const double2 w3 = cmul(w1, w2);
+                const C w3 = cmul(w1, w2);
                 u[3] = DIR < 0 ? cmul(u[3], w3) : cmulc(u[3], w3);
                 if constexpr (R == 8) {
-                    const double2 w4 = tload(tw, 4u * step);
+                    const C w4 = tload(tw, 4u * step);
                     u[4] = DIR < 0 ? cmul(u[4], w4) : cmulc(u[4], w4);
-                    const double2 w5 = cmul(w1, w4);
+                    const C w5 = cmul(w1, w4);
                     u[5] = DIR < 0 ? cmul(u[5], w5) : cmulc(u[5], w5);
-                    const double2 w6 = cmul(w2, w4);
+                    const C w6 = cmul(w2, w4);
                     u[6] = DIR < 0 ? cmul(u[6], w6) : cmulc(u[6], w6);
-                    const double2 w7 = cmul(w3, w4);
+                    const C w7 = cmul(w3, w4);
                     u[7] = DIR < 0 ? cmul(u[7], w7) : cmulc(u[7], w7);
                 }
             }
@@ -142,7 +175,7 @@ __device__ __forceinline__ void stockham_pass(double2 (&v)[SLOTS], double2* lds,
         dftR<R, DIR>(u);
         if (LAST) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[c + r * C] = u[r];
+            for (int r = 0; r < R; ++r) v[c + r * NB] = u[r];
         } else {
             const int base = (t - k) * R + k;
 #pragma unroll
@@ -161,8 +194,8 @@ __device__ __forceinline__ void stockham_pass(double2 (&v)[SLOTS], double2* lds,
 // Full FFT of length P = 2^LOGP on the slots v (natural order in, natural order out),
 // SL points per thread, P / SL threads.  The radix-8 passes run as a loop that is not
 // unrolled, so only one pass's addresses are live at a time.
-template <int LOGP, int DIR, int SL = fft_slots_for(LOGP)>
-__device__ __forceinline__ void fft_slots(double2 (&v)[SL], double2* lds, const double2* __restrict__ tw) {
+template <int LOGP, int DIR, int SL = fft_slots_for(LOGP), class C>
+__device__ __forceinline__ void fft_slots(C (&v)[SL], C* lds, const C* __restrict__ tw) {
     constexpr int BL = (1 << LOGP) / SL;
     static_assert(SL == 8 || SL == 16, "8 or 16 points per thread");
     static_assert(LOGP >= 9 && LOGP <= 13, "FFT length out of range");

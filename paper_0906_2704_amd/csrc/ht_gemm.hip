@@ -1064,15 +1064,25 @@ using namespace ht;
 
 extern "C" ht_status ht_plan_set_precision(ht_plan* p, int precision) {
     if (!p) return fail(HT_ERR_INVALID_ARG, "ht_plan_set_precision: null plan");
-    if (precision != HT_PRECISION_F64 && precision != HT_PRECISION_BF16X3 && precision != HT_PRECISION_F16X3)
+    if (precision != HT_PRECISION_F64 && precision != HT_PRECISION_BF16X3 && precision != HT_PRECISION_F16X3 &&
+        precision != HT_PRECISION_F32)
         return fail(HT_ERR_INVALID_ARG, "ht_plan_set_precision: unknown precision");
     if (precision != HT_PRECISION_F64) {
-        for (int a = 0; a < p->ndim; ++a)
-            if (p->ax[a].kind == HT_KIND_F)
-                return fail(HT_ERR_UNSUPPORTED, "ht_plan_set_precision: the split-precision core needs a real core (not T_F)");
+        if (precision != HT_PRECISION_F32)
+            for (int a = 0; a < p->ndim; ++a)
+                if (p->ax[a].kind == HT_KIND_F)
+                    return fail(HT_ERR_UNSUPPORTED,
+                                "ht_plan_set_precision: the split-precision core needs a real core (not T_F)");
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
             return fail(HT_ERR_INVALID_ARG, "ht_plan_set_precision: the plan's device must be current");
+    }
+    if (precision == HT_PRECISION_F32) {
+        ht_status st = plan_build_f32(p);
+        if (st != HT_OK) return st;
+        gemm_release(p->gemm);
+        p->gemm = nullptr;
+        return HT_OK;
     }
     GemmState* g = nullptr;
     if (precision != HT_PRECISION_F64) {
@@ -1081,10 +1091,12 @@ extern "C" ht_status ht_plan_set_precision(ht_plan* p, int precision) {
     }
     gemm_release(p->gemm);
     p->gemm = g;
+    plan_release_f32(p);
     return HT_OK;
 }
 
 extern "C" int ht_plan_precision(const ht_plan* p) {
     if (!p) return -1;
+    if (p->f32) return HT_PRECISION_F32;
     return p->gemm ? p->gemm->prec : HT_PRECISION_F64;
 }

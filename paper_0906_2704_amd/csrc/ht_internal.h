@@ -27,12 +27,15 @@ enum OutMode { MODE_RE = 0, MODE_IM = 1, MODE_CPLX = 2 };
 // Tables of one core direction (analysis X or synthesis X^{-1}) computed as a chirp-z
 // transform: Y_k = post_k * sum_j b_{k-j} (pre_j x_j), evaluated by FFT convolution of
 // length M = S * P with the precomputed spectrum B = FFT_M(b) / M.
-struct Chirp {
-    const double2* pre;   // [N]
-    const double2* post;  // [N]
-    const double2* B;     // [M]
+template <class C>
+struct ChirpT {
+    const C* pre;         // [N]
+    const C* post;        // [N]
+    const C* B;           // [M]
     int mode;             // OutMode of the core output for a real result
 };
+using Chirp = ChirpT<double2>;
+using Chirp32 = ChirpT<float2>;  // float32 copies (HT_PRECISION_F32 cores)
 
 // Everything a kernel needs about one 1D transform of length n (passed by value).
 struct Axis {
@@ -48,6 +51,8 @@ struct Axis {
     const double* bub;    // [rank][N] bubble columns (DST2/3)
     const double* U;      // [rank][N] K - E, K = Q * bubbles
     Chirp ana, syn;
+    Chirp32 ana32, syn32; // float32 tables, set by ht_plan_set_precision(HT_PRECISION_F32)
+    const float2* tw32;   // float32 twiddle table (same)
     int den;              // eigenvalue grid: angles pi * r / den
     const double* tcos;   // [2 den] cos(pi r / den)
     const double* tsin;   // [2 den] sin(pi r / den)
@@ -80,6 +85,8 @@ struct ht_plan {
     int64_t gcv_part_elems = 0;
     const double2* tw = nullptr;       // global twiddle table of this device
     ht::GemmState* gemm = nullptr;     // set by ht_plan_set_precision (null: float64 core)
+    int f32 = 0;                       // float32 chirp-z cores (HT_PRECISION_F32)
+    void* arena32 = nullptr;           // their tables
 };
 
 namespace ht {
@@ -94,8 +101,12 @@ ht_status gemm_transform(const ht_plan* p, bool inverse, const double* in, doubl
                          hipStream_t stream);
 void gemm_release(GemmState* g);
 
+// float32 chirp-z cores (ht_plan.hip)
+ht_status plan_build_f32(ht_plan* p);
+void plan_release_f32(ht_plan* p);
+
 // launchers (ht_transform.hip)
 ht_status launch_core(const Axis& ax, const double2* tw, bool inverse, const View& in,
-                      const View& out, int64_t count, hipStream_t stream);
+                      const View& out, int64_t count, hipStream_t stream, bool f32 = false);
 
 }  // namespace ht

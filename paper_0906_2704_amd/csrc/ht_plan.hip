@@ -402,6 +402,83 @@ ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* a
     return HT_OK;
 }
 
+// ---------------------------------------------------------------- float32 cores
+
+void plan_release_f32(ht_plan* p) {
+    if (p->arena32) (void)hipFree(p->arena32);
+    p->arena32 = nullptr;
+    p->f32 = 0;
+    for (int a = 0; a < 2; ++a) {
+        p->ax[a].ana32 = Chirp32{};
+        p->ax[a].syn32 = Chirp32{};
+        p->ax[a].tw32 = nullptr;
+    }
+}
+
+// float32 copies (rounded from the exact-angle float64 values) of the plan's chirp tables
+// and of the twiddle table, for HT_PRECISION_F32.
+ht_status plan_build_f32(ht_plan* p) {
+    std::vector<HostAxis> hs(p->ndim);
+    for (int a = 0; a < p->ndim; ++a) {
+        ht_status st = build_axis(p->ax[a].n, p->ax[a].kind, hs[a]);
+        if (st != HT_OK) return st;
+    }
+    size_t bytes = 0;
+    auto reserve = [&](size_t n2) {
+        const size_t off = bytes;
+        bytes += (sizeof(float2) * n2 + 255) & ~static_cast<size_t>(255);
+        return off;
+    };
+    const size_t otw = reserve(TWN);
+    struct Offs { size_t apre, apost, aB, spre, spost, sB; } o[2];
+    for (int a = 0; a < p->ndim; ++a) {
+        const size_t N = hs[a].ax.N, M = hs[a].M;
+        o[a] = {reserve(N), reserve(N), reserve(M), reserve(N), reserve(N), reserve(M)};
+    }
+    std::vector<float2> host(bytes / sizeof(float2));
+    auto at = [&](size_t off) { return host.data() + off / sizeof(float2); };
+    for (int m = 0; m < TWN; ++m) {
+        const cd w = cis_exact(-m, TWN);
+        at(otw)[m] = make_float2(static_cast<float>(w.real()), static_cast<float>(w.imag()));
+    }
+    auto putc = [&](size_t off, const std::vector<cd>& v) {
+        for (size_t i = 0; i < v.size(); ++i)
+            at(off)[i] = make_float2(static_cast<float>(v[i].real()), static_cast<float>(v[i].imag()));
+    };
+    auto putc_split = [&](size_t off, const std::vector<cd>& v, int S) {  // as the float64 tables
+        const size_t P = v.size() / S;
+        for (int sidx = 0; sidx < S; ++sidx)
+            for (size_t u = 0; u < P; ++u) {
+                const cd w = v[S * u + sidx];
+                at(off)[sidx * P + u] = make_float2(static_cast<float>(w.real()), static_cast<float>(w.imag()));
+            }
+    };
+    for (int a = 0; a < p->ndim; ++a) {
+        putc(o[a].apre, hs[a].ana.pre);
+        putc(o[a].apost, hs[a].ana.post);
+        putc_split(o[a].aB, hs[a].ana.B, hs[a].ax.S);
+        putc(o[a].spre, hs[a].syn.pre);
+        putc(o[a].spost, hs[a].syn.post);
+        putc_split(o[a].sB, hs[a].syn.B, hs[a].ax.S);
+    }
+    char* dev = nullptr;
+    if (hipMalloc(&dev, bytes) != hipSuccess) return fail(HT_ERR_OOM, "float32 table allocation failed");
+    if (hipMemcpy(dev, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dev);
+        return fail(HT_ERR_HIP, "float32 table upload failed");
+    }
+    plan_release_f32(p);
+    p->arena32 = dev;
+    p->f32 = 1;
+    auto ptr = [&](size_t off) { return reinterpret_cast<const float2*>(dev + off); };
+    for (int a = 0; a < p->ndim; ++a) {
+        p->ax[a].ana32 = Chirp32{ptr(o[a].apre), ptr(o[a].apost), ptr(o[a].aB), p->ax[a].ana.mode};
+        p->ax[a].syn32 = Chirp32{ptr(o[a].spre), ptr(o[a].spost), ptr(o[a].sB), p->ax[a].syn.mode};
+        p->ax[a].tw32 = ptr(otw);
+    }
+    return HT_OK;
+}
+
 }  // namespace ht
 
 using namespace ht;
@@ -462,6 +539,7 @@ extern "C" ht_status ht_plan_destroy(ht_plan* p) {
     if (p->work) (void)hipFree(p->work);
     if (p->gcv_part) (void)hipFree(p->gcv_part);
     gemm_release(p->gemm);
+    plan_release_f32(p);
     delete p;
     return HT_OK;
 }

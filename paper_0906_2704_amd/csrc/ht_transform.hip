@@ -37,13 +37,25 @@ __device__ __forceinline__ int64_t vbase(const View& v, int64_t b) {
     return (b / v.per_img) * v.img_stride + (b % v.per_img) * v.sig_stride;
 }
 
-template <int LOGP, int S>
+// The core's tables for the element type C (float64 or float32 copies).
+template <class C>
+__device__ __forceinline__ const ChirpT<C>& core_of(const Axis& ax, bool analysis);
+template <>
+__device__ __forceinline__ const Chirp& core_of<double2>(const Axis& ax, bool analysis) {
+    return analysis ? ax.ana : ax.syn;
+}
+template <>
+__device__ __forceinline__ const Chirp32& core_of<float2>(const Axis& ax, bool analysis) {
+    return analysis ? ax.ana32 : ax.syn32;
+}
+
+template <int LOGP, int S, class C>
 __global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View in, View out,
-                                                             const double2* __restrict__ tw) {
+                                                             const C* __restrict__ tw) {
     constexpr int P = 1 << LOGP;
     constexpr int SL = fft_slots_for(LOGP);
     constexpr int BLOCK = fft_block_for(LOGP);
-    __shared__ double2 lds[P];
+    __shared__ C lds[P];
     __shared__ double2 corr[2];
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
@@ -76,7 +88,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View i
     auto unpark = [&](int j) { return vload(out, ob, j + 1); };
     const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ax.ana.mode;
     double2 acc[SL];
-    chirp_core<LOGP, S, SL>(acc, ax.ana, mode, N, lds, tw, in_fn, park, unpark);
+    chirp_core<LOGP, S, SL>(acc, core_of<C>(ax, true), mode, N, lds, tw, in_fn, park, unpark);
     if (ax.rank > 0) {  // DST family: x_mid -= U (E^T K)^{-1} E^T x_mid
         if (tid < ax.rank) corr[tid] = acc[0];
         __syncthreads();
@@ -110,13 +122,13 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View i
     }
 }
 
-template <int LOGP, int S>
+template <int LOGP, int S, class C>
 __global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View in, View out,
-                                                             const double2* __restrict__ tw) {
+                                                             const C* __restrict__ tw) {
     constexpr int P = 1 << LOGP;
     constexpr int SL = fft_slots_for(LOGP);
     constexpr int BLOCK = fft_block_for(LOGP);
-    __shared__ double2 lds[P];
+    __shared__ C lds[P];
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
     const int n = ax.n, N = ax.N;
@@ -131,7 +143,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View i
     auto unpark = [&](int j) { return vload(out, ob, j + 1); };
     const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ax.syn.mode;
     double2 u[SL];
-    chirp_core<LOGP, S, SL>(u, ax.syn, mode, N, lds, tw, in_fn, park, unpark);
+    chirp_core<LOGP, S, SL>(u, core_of<C>(ax, false), mode, N, lds, tw, in_fn, park, unpark);
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;
@@ -164,39 +176,46 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View i
     }
 }
 
-template <int LOGP>
-static hipError_t launch_one(const Axis& ax, const double2* tw, bool inverse, const View& in,
-                             const View& out, int64_t count, hipStream_t stream) {
+template <int LOGP, class C>
+static hipError_t launch_one(const Axis& ax, const C* tw, bool inverse, const View& in, const View& out,
+                             int64_t count, hipStream_t stream) {
     const dim3 grid(static_cast<unsigned>(count)), block(fft_block_for(LOGP));
     if constexpr (LOGP == MAX_LOGP) {  // split convolutions (M = 16384)
         if (ax.S == 2) {
             if (inverse)
-                hipLaunchKernelGGL((k_inverse<LOGP, 2>), grid, block, 0, stream, ax, in, out, tw);
+                hipLaunchKernelGGL((k_inverse<LOGP, 2, C>), grid, block, 0, stream, ax, in, out, tw);
             else
-                hipLaunchKernelGGL((k_forward<LOGP, 2>), grid, block, 0, stream, ax, in, out, tw);
+                hipLaunchKernelGGL((k_forward<LOGP, 2, C>), grid, block, 0, stream, ax, in, out, tw);
             return hipGetLastError();
         }
     }
     {
         if (inverse)
-            hipLaunchKernelGGL((k_inverse<LOGP, 1>), grid, block, 0, stream, ax, in, out, tw);
+            hipLaunchKernelGGL((k_inverse<LOGP, 1, C>), grid, block, 0, stream, ax, in, out, tw);
         else
-            hipLaunchKernelGGL((k_forward<LOGP, 1>), grid, block, 0, stream, ax, in, out, tw);
+            hipLaunchKernelGGL((k_forward<LOGP, 1, C>), grid, block, 0, stream, ax, in, out, tw);
     }
     return hipGetLastError();
 }
 
+template <int LOGP>
+static hipError_t launch_prec(const Axis& ax, const double2* tw, bool inverse, const View& in, const View& out,
+                              int64_t count, hipStream_t stream, bool f32) {
+    if (f32) return launch_one<LOGP, float2>(ax, ax.tw32, inverse, in, out, count, stream);
+    return launch_one<LOGP, double2>(ax, tw, inverse, in, out, count, stream);
+}
+
 ht_status launch_core(const Axis& ax, const double2* tw, bool inverse, const View& in,
-                      const View& out, int64_t count, hipStream_t stream) {
+                      const View& out, int64_t count, hipStream_t stream, bool f32) {
     if (count <= 0) return HT_OK;
     if (count > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "too many transforms in one call");
     hipError_t e;
     switch (ax.logP) {
-        case 9: e = launch_one<9>(ax, tw, inverse, in, out, count, stream); break;
-        case 10: e = launch_one<10>(ax, tw, inverse, in, out, count, stream); break;
-        case 11: e = launch_one<11>(ax, tw, inverse, in, out, count, stream); break;
-        case 12: e = launch_one<12>(ax, tw, inverse, in, out, count, stream); break;
-        case 13: e = launch_one<13>(ax, tw, inverse, in, out, count, stream); break;
+        case 9: e = launch_prec<9>(ax, tw, inverse, in, out, count, stream, f32); break;
+        case 10: e = launch_prec<10>(ax, tw, inverse, in, out, count, stream, f32); break;
+        case 11: e = launch_prec<11>(ax, tw, inverse, in, out, count, stream, f32); break;
+        case 12: e = launch_prec<12>(ax, tw, inverse, in, out, count, stream, f32); break;
+        case 13: e = launch_prec<13>(ax, tw, inverse, in, out, count, stream, f32); break;
         default: return fail(HT_ERR_INVALID_ARG, "internal: FFT size out of range");
     }
     return check_hip(e, "transform launch");
@@ -221,7 +240,7 @@ extern "C" ht_status ht_transform_inv(const ht_plan* plan, const double* signal,
         const Axis& a = plan->ax[0];
         View in{const_cast<double*>(signal), 0, a.n, 1, batch, 0};
         View out{coeff, 0, a.n, 1, batch, cp};
-        return launch_core(a, plan->tw, true, in, out, batch, stream);
+        return launch_core(a, plan->tw, true, in, out, batch, stream, plan->f32 != 0);
     }
     if (batch > plan->max_batch) return fail(HT_ERR_INVALID_ARG, "ht_transform_inv: batch exceeds the plan's max_batch");
     const Axis& a0 = plan->ax[0];
@@ -230,12 +249,12 @@ extern "C" ht_status ht_transform_inv(const ht_plan* plan, const double* signal,
     // axis 1: every row, signal -> workspace
     View r_in{const_cast<double*>(signal), 0, a1.n, 1, batch * a0.n, 0};
     View r_out{plan->work, 0, a1.n, 1, batch * a0.n, cp};
-    ht_status st = launch_core(a1, plan->tw, true, r_in, r_out, batch * a0.n, stream);
+    ht_status st = launch_core(a1, plan->tw, true, r_in, r_out, batch * a0.n, stream, plan->f32 != 0);
     if (st != HT_OK) return st;
     // axis 0: every column, workspace -> coeff
     View c_in{plan->work, img, 1, a1.n, a1.n, cp};
     View c_out{coeff, img, 1, a1.n, a1.n, cp};
-    return launch_core(a0, plan->tw, true, c_in, c_out, batch * a1.n, stream);
+    return launch_core(a0, plan->tw, true, c_in, c_out, batch * a1.n, stream, plan->f32 != 0);
 }
 
 extern "C" ht_status ht_transform_fwd(const ht_plan* plan, const void* coeff, double* signal,
@@ -253,7 +272,7 @@ extern "C" ht_status ht_transform_fwd(const ht_plan* plan, const void* coeff, do
         const Axis& a = plan->ax[0];
         View in{const_cast<void*>(coeff), 0, a.n, 1, batch, cp};
         View out{signal, 0, a.n, 1, batch, 0};
-        return launch_core(a, plan->tw, false, in, out, batch, stream);
+        return launch_core(a, plan->tw, false, in, out, batch, stream, plan->f32 != 0);
     }
     if (batch > plan->max_batch) return fail(HT_ERR_INVALID_ARG, "ht_transform_fwd: batch exceeds the plan's max_batch");
     const Axis& a0 = plan->ax[0];
@@ -262,10 +281,10 @@ extern "C" ht_status ht_transform_fwd(const ht_plan* plan, const void* coeff, do
     // axis 0: every column, coeff -> workspace (complex for F, real otherwise)
     View c_in{const_cast<void*>(coeff), img, 1, a1.n, a1.n, cp};
     View c_out{plan->work, img, 1, a1.n, a1.n, cp};
-    ht_status st = launch_core(a0, plan->tw, false, c_in, c_out, batch * a1.n, stream);
+    ht_status st = launch_core(a0, plan->tw, false, c_in, c_out, batch * a1.n, stream, plan->f32 != 0);
     if (st != HT_OK) return st;
     // axis 1: every row, workspace -> signal (real part)
     View r_in{plan->work, 0, a1.n, 1, batch * a0.n, cp};
     View r_out{signal, 0, a1.n, 1, batch * a0.n, 0};
-    return launch_core(a1, plan->tw, false, r_in, r_out, batch * a0.n, stream);
+    return launch_core(a1, plan->tw, false, r_in, r_out, batch * a0.n, stream, plan->f32 != 0);
 }
