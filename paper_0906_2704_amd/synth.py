@@ -14,6 +14,7 @@ from dataclasses import dataclass
 
 import numpy as np
 from scipy.ndimage import convolve1d
+from scipy.signal import fftconvolve
 
 SEED_BASE = 0x0906_2704
 
@@ -32,6 +33,35 @@ def gaussian_psf(m, sigma, shift=0.0):
 
 def box_psf(m):
     return np.full(2 * m + 1, 1.0 / (2 * m + 1)), m
+
+
+def disk_psf(radius):
+    """Out-of-focus blur: equal weights on the pixels whose centre lies within ``radius``
+    of the origin, unit sum.  Even in each axis.  Returns (H, c0, c1) with H[a, b] the tap
+    at offset (a - c0, b - c1)."""
+    r = int(np.floor(radius))
+    j = np.arange(-r, r + 1)
+    H = ((j[:, None] ** 2 + j[None, :] ** 2) <= radius * radius).astype(np.float64)
+    return H / H.sum(), r, r
+
+
+def motion_psf(length, angle_deg):
+    """Linear motion blur: a segment of ``length`` pixels that starts at the origin and
+    points at ``angle_deg`` (0 = along axis 1, 90 = along axis 0), rasterised from 8
+    samples per pixel rounded to the nearest pixel, unit sum.  One-sided, so not even in
+    any axis unless the segment is degenerate.  Returns (H, c0, c1)."""
+    t = np.linspace(0.0, float(length), 8 * int(np.ceil(length)) + 1)
+    a = np.deg2rad(angle_deg)
+    p0 = np.rint(t * np.sin(a)).astype(np.int64)
+    p1 = np.rint(t * np.cos(a)).astype(np.int64)
+    lo0, lo1 = int(p0.min()), int(p1.min())
+    H = np.zeros((int(p0.max()) - lo0 + 1, int(p1.max()) - lo1 + 1))
+    np.add.at(H, (p0 - lo0, p1 - lo1), 1.0)
+    return H / H.sum(), -lo0, -lo1
+
+
+def mask_halfwidths(H, c0, c1):
+    return max(c0, H.shape[0] - 1 - c0), max(c1, H.shape[1] - 1 - c1)
 
 
 def delta_psf():
@@ -106,6 +136,19 @@ def observe_2d(F_ext, h0, c0, h1, c1, shape):
     n0, n1 = shape
     tmp = _observe_axis(F_ext, h1, c1, n1, 1)       # along axis 1
     return _observe_axis(tmp, h0, c0, n0, 0)        # along axis 0
+
+
+def observe_2d_mask(F_ext, H, c0, c1, shape):
+    """Blur by a general 2D mask over the field of view: g[p, q] = sum_{a,b} H[a, b]
+    f[p - (a - c0), q - (b - c1)], with F_ext the true image extended by the half-widths
+    (m0, m1) of ``mask_halfwidths`` on each side.  Full linear convolution by FFT, then the
+    field-of-view window."""
+    n0, n1 = shape
+    m0, m1 = mask_halfwidths(H, c0, c1)
+    assert F_ext.shape == (n0 + 2 * m0, n1 + 2 * m1)
+    full = fftconvolve(F_ext, np.asarray(H, dtype=np.float64), mode="full")
+    # full[i, j] = sum H[a, b] F_ext[i - a, j - b]; p sits at i = p + m0 + c0
+    return full[m0 + c0:m0 + c0 + n0, m1 + c1:m1 + c1 + n1].copy()
 
 
 def add_noise(rng, g, eta):
@@ -193,6 +236,28 @@ def config3(item, n=2048):
     F_ext = piecewise_poly_image(rng, (n + 2 * m, n + 2 * m))
     g = add_noise(rng, observe_2d(F_ext, h, c, h, c, (n, n)), 0.01)
     return Problem2D(F_ext[m:m + n, m:m + n].copy(), g, h, c, h, c, 0.01, mu_grid(-6.0, 0.0, 128))
+
+
+@dataclass
+class ProblemMask2D:
+    f_true: np.ndarray
+    g: np.ndarray
+    H: np.ndarray
+    c0: int
+    c1: int
+    eta: float
+    mus: np.ndarray
+
+
+def disk_image(item, n=512, radius=6.0, eta=0.001, config=4):
+    """Out-of-focus deblurring (the 2D experiment of Section 6): piecewise-quadratic
+    n x n image, disk PSF of the given radius, 0.1% noise, 128 mu on [1e-6, 1]."""
+    rng = rng_for(config, item)
+    H, c0, c1 = disk_psf(radius)
+    m0, m1 = mask_halfwidths(H, c0, c1)
+    F_ext = piecewise_poly_image(rng, (n + 2 * m0, n + 2 * m1))
+    g = add_noise(rng, observe_2d_mask(F_ext, H, c0, c1, (n, n)), eta)
+    return ProblemMask2D(F_ext[m0:m0 + n, m1:m1 + n].copy(), g, H, c0, c1, eta, mu_grid(-6.0, 0.0, 128))
 
 
 @dataclass
