@@ -136,6 +136,34 @@ ht_status ht_eigs(const ht_plan* plan, const double* psf, const int64_t* psf_len
                   const int64_t* psf_center, int norm, void* d, double* s, int64_t batch,
                   hipStream_t stream);
 
+/* ht_eigs2d -- eigenvalues for a general (non-separable) 2D PSF mask on a 2D plan, by
+ * the three steps of Section 6: the marginal 1D masks (the sums of the columns and of the
+ * rows of the mask) give the entries whose index along one axis is a preserved
+ * polynomial column (the edges of the array; the corners get the mask's sum), and the 2D
+ * transform of the mask at the grid frequencies of both axes gives the inner entries.
+ * Computed as one formula: polynomial columns have frequency 0, where the 2D sum reduces
+ * to the marginal's 1D sum.  Real kinds use the part of the mask even in each axis,
+ * sum H[a,b] cos((a-c0) t_i) cos((b-c1) u_j) (the eigen relation needs a mask even in
+ * each axis, e.g. a disk); T_F uses the 2D symbol at (-t_i, -u_j) (any mask, e.g. motion
+ * blur).  Direct sums with exactly reduced angles, O(len0 n1 len1 + n0 n1 len0) per mask.
+ *   psf: device [batch][len0][len1], tap (a, b) at offset (a - center0, b - center1).
+ *   d: device [batch][n0][n1] (complex128 for T_F plans, else float64); s: [batch][n0][n1]
+ *   with s_ij = s0_i + s1_j for HT_NORM_SECOND_DIFF (0 on polynomial columns), 1 for
+ *   HT_NORM_IDENTITY.  The HT_SPECTRUM_FULL layout of ht_tikhonov_filter / ht_gcv_scan.
+ *   1 <= batch <= the plan's max_batch; 2m+1 <= n-2 per axis, m = max(center,
+ *   len-1-center) (HT_ERR_PSF_TOO_WIDE).  Uses the plan's 2D workspace: calls on one plan
+ *   must be ordered on one stream, as for its transforms.                               */
+ht_status ht_eigs2d(const ht_plan* plan, const double* psf, int64_t psf_len0, int64_t psf_len1,
+                    int64_t psf_center0, int64_t psf_center1, int norm, void* d, double* s,
+                    int64_t batch, hipStream_t stream);
+
+/* Layout of the spectra d and s of a 2D plan for ht_tikhonov_filter / ht_gcv_scan (1D
+ * plans ignore it: their spectra are [eig_batch][n]).                                  */
+typedef enum {
+    HT_SPECTRUM_FACTORS = 0,  /* [d0 (n0) | d1 (n1)], [s0 | s1] of ht_eigs (separable mask) */
+    HT_SPECTRUM_FULL = 1      /* [eig_batch][n0][n1] of ht_eigs2d (any mask)                */
+} ht_spectrum_layout;
+
 /* ht_transform_inv -- coeff = T^{-1} signal (Theorem th:inv): the 2x2 boundary system in
  * float64, the interior correction, one core analysis transform (DST-I, DCT-II or DFT of
  * order n-2) and, for DST2/DST3, the rank-(degree-1) correction.  In 2D the 1D transform
@@ -152,21 +180,23 @@ ht_status ht_transform_fwd(const ht_plan* plan, const void* coeff, double* signa
 
 /* ht_tikhonov_filter -- fhat_i = conj(d_i) coeff_i / (|d_i|^2 + mu |s_i|^2), i.e.
  * Phi D^{-1} coeff of eq. freg (reblurred Tikhonov, eq. nerebl), in float64.
- *   d, s: eig_batch = 1 (shared by every item) or eig_batch = batch (one per item).
+ *   d, s: eig_batch = 1 (shared by every item) or eig_batch = batch (one per item); 2D
+ *   plans: layout (ht_spectrum_layout) HT_SPECTRUM_FACTORS takes eig_batch = 1.
  *   mu:   device [batch], mu > 0.  fhat may alias coeff.                               */
 ht_status ht_tikhonov_filter(const ht_plan* plan, const void* coeff, const void* d,
-                             const double* s, int64_t eig_batch, const double* mu,
+                             const double* s, int64_t eig_batch, int layout, const double* mu,
                              void* fhat, int64_t batch, hipStream_t stream);
 
 /* ht_gcv_scan -- G(mu_k) = sum_i |sigma_i coeff_i|^2 / (sum_i sigma_i)^2 with
  * sigma_i = |s_i|^2 / (|d_i|^2 + mu_k |s_i|^2) (eqs. gcv2, mugcv) for every mu_k of the
  * grid, and the index of its first minimum.  Sums are float64 in a fixed order, so the
- * result is bitwise reproducible run to run.
+ * result is bitwise reproducible run to run.  d, s, eig_batch, layout as for
+ * ht_tikhonov_filter.
  *   mu_grid: device [K] (grid_per_item = 0) or [batch][K] (grid_per_item = 1), mu_k > 0.
  *   G: device [batch][K] or NULL.  k_best: device int32 [batch] (-1 if some G_k is not
  *   finite).  mu_best: device [batch] or NULL (NaN when k_best = -1).  1 <= K <= 1024.  */
 ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const void* d, const double* s,
-                      int64_t eig_batch, const double* mu_grid, int32_t K, int grid_per_item,
+                      int64_t eig_batch, int layout, const double* mu_grid, int32_t K, int grid_per_item,
                       double* G, int32_t* k_best, double* mu_best, int64_t batch,
                       hipStream_t stream);
 

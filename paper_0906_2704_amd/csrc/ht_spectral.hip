@@ -55,20 +55,134 @@ __global__ void k_eigs(Axis ax, const double* __restrict__ psf, int64_t plen, in
     s[o] = sv;
 }
 
+// ------------------------------------------------------------- eigenvalues, 2D masks
+
+// Frequency number of column i (angle pi * num / den), 0 on the polynomial columns.
+__device__ __forceinline__ int64_t freq_num(const Axis& ax, int i) {
+    const bool poly = (i == 0) || (i == ax.n - 1) || (i >= 1 && i <= ax.rank);
+    if (poly) return 0;
+    if (ax.kind == HT_KIND_C) return i - 1;
+    if (ax.kind == HT_KIND_F) return -2 * static_cast<int64_t>(i - 1);
+    return i;
+}
+
+// angle index of offset * num modulo 2 den, in [0, 2 den)
+__device__ __forceinline__ int64_t angle_index(int64_t offset, int64_t num, int64_t period) {
+    int64_t r = (offset * num) % period;
+    return r < 0 ? r + period : r;
+}
+
+// Step one of the factorisation: W[b][a][j] = sum_k H[b][a][k] e^{i (k - c1) u_j} over
+// the taps of mask row a, at the axis-1 frequency u_j of column j (cos only for the real
+// kinds: the part of the row even about c1).  One thread per (j, a, b); the angle index
+// advances by num_j per tap, so the loop has no division.
+template <bool CPLX>
+__global__ void k_eigs2d_rows(Axis ax1, const double* __restrict__ psf, int64_t len0, int64_t len1,
+                              int64_t c1, double2* __restrict__ W) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t a = blockIdx.y, b = blockIdx.z;
+    if (j >= ax1.n) return;
+    const double* h = psf + (b * len0 + a) * len1;
+    const int64_t period = 2 * static_cast<int64_t>(ax1.den);
+    const int64_t num = freq_num(ax1, j);
+    const int64_t step = angle_index(1, num, period);
+    int64_t r = angle_index(-c1, num, period);
+    double wr = 0.0, wi = 0.0;
+    for (int64_t k = 0; k < len1; ++k) {
+        wr = fma(h[k], ax1.tcos[r], wr);
+        if (CPLX) wi = fma(h[k], ax1.tsin[r], wi);
+        r += step;
+        if (r >= period) r -= period;
+    }
+    W[(b * len0 + a) * ax1.n + j] = make_double2(wr, wi);
+}
+
+constexpr int E2_TJ = 64;     // columns per tile (one per lane)
+constexpr int E2_RG = 4;      // row groups (waves) per tile
+constexpr int E2_RPT = 16;    // rows per thread
+constexpr int E2_TI = E2_RG * E2_RPT;
+constexpr int E2_AC = 32;     // mask rows per LDS chunk
+
+// Step two: d[b][i][j] = sum_a W[b][a][j] e^{i (a - c0) t_i} (real kinds: cos and the
+// real part of W, i.e. sum H cos cos), and s[b][i][j].  A 64 x 64 tile per block: lane j
+// of wave g owns rows g, g + 4, ... of the tile; the factors e^{i (a - c0) t_i} of a
+// chunk of mask rows are staged in LDS, W[a][j] is read once per tile from global memory.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_eigs2d_cols(Axis ax0, Axis ax1, const double2* __restrict__ W,
+                                                     int64_t len0, int64_t c0, int norm, void* d, double* s) {
+    __shared__ double2 E[E2_AC][E2_TI];
+    const int jj = threadIdx.x & (E2_TJ - 1), g = threadIdx.x / E2_TJ;
+    const int j = blockIdx.x * E2_TJ + jj;
+    const int i0 = blockIdx.y * E2_TI;
+    const int64_t b = blockIdx.z;
+    const int n0 = ax0.n, n1 = ax1.n;
+    const int64_t period0 = 2 * static_cast<int64_t>(ax0.den);
+    double2 acc[E2_RPT];
+#pragma unroll
+    for (int r = 0; r < E2_RPT; ++r) acc[r] = make_double2(0.0, 0.0);
+    const double2* Wb = W + b * len0 * n1;
+    for (int64_t a0 = 0; a0 < len0; a0 += E2_AC) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < E2_AC * E2_TI; e += 256) {
+            const int aa = e / E2_TI, ii = e - aa * E2_TI;
+            const int i = i0 + ii;
+            const int64_t num = i < n0 ? freq_num(ax0, i) : 0;
+            const int64_t r = angle_index(a0 + aa - c0, num, period0);
+            E[aa][ii] = make_double2(ax0.tcos[r], ax0.tsin[r]);
+        }
+        __syncthreads();
+        const int na = static_cast<int>(len0 - a0 < E2_AC ? len0 - a0 : E2_AC);
+        if (j < n1) {
+            for (int aa = 0; aa < na; ++aa) {
+                const double2 w = Wb[(a0 + aa) * n1 + j];
+#pragma unroll
+                for (int r = 0; r < E2_RPT; ++r) {
+                    const double2 e = E[aa][g + E2_RG * r];
+                    if (CPLX) {
+                        acc[r].x = fma(w.x, e.x, fma(-w.y, e.y, acc[r].x));
+                        acc[r].y = fma(w.x, e.y, fma(w.y, e.x, acc[r].y));
+                    } else {
+                        acc[r].x = fma(w.x, e.x, acc[r].x);
+                    }
+                }
+            }
+        }
+    }
+    if (j >= n1) return;
+    const int64_t num1 = freq_num(ax1, j);
+    const double s1 = num1 == 0 ? 0.0 : 2.0 - 2.0 * ax1.tcos[angle_index(1, num1, 2 * static_cast<int64_t>(ax1.den))];
+#pragma unroll
+    for (int r = 0; r < E2_RPT; ++r) {
+        const int i = i0 + g + E2_RG * r;
+        if (i >= n0) break;
+        const int64_t o = (b * n0 + i) * n1 + j;
+        if (CPLX)
+            static_cast<double2*>(d)[o] = acc[r];
+        else
+            static_cast<double*>(d)[o] = acc[r].x;
+        double sv = 1.0;
+        if (norm != HT_NORM_IDENTITY) {
+            const int64_t num0 = freq_num(ax0, i);
+            sv = (num0 == 0 ? 0.0 : 2.0 - 2.0 * ax0.tcos[angle_index(1, num0, period0)]) + s1;
+        }
+        s[o] = sv;
+    }
+}
+
 // ------------------------------------------------------------------- shared accessors
 
 struct Spec {          // how to find d_i and s_i of element e of item b
     const void* d;
     const double* s;
-    int ndim;
-    int n0, n1;        // 2D factor lengths (n0 = n for 1D)
-    int64_t eig_stride;  // 1D: 0 (shared) or n (per item)
+    int factored;      // 2D separable factors [d0 | d1]; else one entry per element
+    int n0, n1;        // 2D factor lengths
+    int64_t eig_stride;  // 0 (shared) or per_item (one spectrum per item)
     int64_t per_item;    // elements per item (n or n0 * n1)
     int cplx;
 };
 
 __device__ __forceinline__ void spec_at(const Spec& sp, int64_t b, int64_t e, double2& dd, double& ss) {
-    if (sp.ndim == 1) {
+    if (!sp.factored) {
         const int64_t o = b * sp.eig_stride + e;
         dd = sp.cplx ? static_cast<const double2*>(sp.d)[o]
                      : make_double2(static_cast<const double*>(sp.d)[o], 0.0);
@@ -339,17 +453,30 @@ __global__ __launch_bounds__(GCV_THREADS) void k_gcv_finalize(GcvOut o, int64_t 
                o.mubest ? o.mubest + b : nullptr, Gs, &kshared);
 }
 
-static Spec make_spec(const ht_plan* plan, const void* d, const double* s, int64_t eig_batch) {
+static Spec make_spec(const ht_plan* plan, const void* d, const double* s, int64_t eig_batch, int layout) {
     Spec sp;
     sp.d = d;
     sp.s = s;
-    sp.ndim = plan->ndim;
+    sp.factored = plan->ndim == 2 && layout == HT_SPECTRUM_FACTORS;
     sp.n0 = plan->ax[0].n;
     sp.n1 = plan->ndim == 2 ? plan->ax[1].n : 1;
     sp.per_item = plan->ndim == 2 ? static_cast<int64_t>(sp.n0) * sp.n1 : sp.n0;
-    sp.eig_stride = (plan->ndim == 1 && eig_batch > 1) ? sp.n0 : 0;
+    sp.eig_stride = (!sp.factored && eig_batch > 1) ? sp.per_item : 0;
     sp.cplx = plan->cplx;
     return sp;
+}
+
+// shared argument checks of the filter and the GCV scan
+static ht_status check_spectrum(const ht_plan* plan, int64_t eig_batch, int layout, int64_t batch, const char* who) {
+    if (!(eig_batch == 1 || eig_batch == batch))
+        return fail(HT_ERR_INVALID_ARG, std::string(who) + ": eig_batch must be 1 or batch");
+    if (plan->ndim == 2) {
+        if (layout != HT_SPECTRUM_FACTORS && layout != HT_SPECTRUM_FULL)
+            return fail(HT_ERR_INVALID_ARG, std::string(who) + ": bad spectrum layout");
+        if (layout == HT_SPECTRUM_FACTORS && eig_batch != 1)
+            return fail(HT_ERR_INVALID_ARG, std::string(who) + ": separable 2D factors are shared (eig_batch = 1)");
+    }
+    return HT_OK;
 }
 
 }  // namespace ht
@@ -393,17 +520,46 @@ extern "C" ht_status ht_eigs(const ht_plan* plan, const double* psf, const int64
     return HT_OK;
 }
 
+extern "C" ht_status ht_eigs2d(const ht_plan* plan, const double* psf, int64_t len0, int64_t len1,
+                               int64_t c0, int64_t c1, int norm, void* d, double* s, int64_t batch,
+                               hipStream_t stream) {
+    if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_eigs2d: null plan");
+    if (plan->ndim != 2) return fail(HT_ERR_INVALID_ARG, "ht_eigs2d: needs a 2D plan");
+    if (norm != HT_NORM_IDENTITY && norm != HT_NORM_SECOND_DIFF) return fail(HT_ERR_INVALID_ARG, "ht_eigs2d: bad norm");
+    if (batch < 0 || batch > plan->max_batch) return fail(HT_ERR_INVALID_ARG, "ht_eigs2d: batch must be in [0, max_batch]");
+    if (batch == 0) return HT_OK;
+    if (!psf || !d || !s) return fail(HT_ERR_INVALID_ARG, "ht_eigs2d: null argument");
+    const int64_t lens[2] = {len0, len1}, cens[2] = {c0, c1};
+    for (int a = 0; a < 2; ++a) {
+        if (lens[a] < 1 || cens[a] < 0 || cens[a] >= lens[a]) return fail(HT_ERR_INVALID_ARG, "ht_eigs2d: bad mask shape or center");
+        const int64_t m = cens[a] > lens[a] - 1 - cens[a] ? cens[a] : lens[a] - 1 - cens[a];
+        if (2 * m + 1 > plan->ax[a].n - 2) return fail(HT_ERR_PSF_TOO_WIDE, "ht_eigs2d: PSF half-width m needs 2m+1 <= n-2 per axis");
+    }
+    const Axis& ax0 = plan->ax[0];
+    const Axis& ax1 = plan->ax[1];
+    // W [batch][len0][n1] fits the [max_batch][n0][n1] workspace: len0 <= n0 - 2
+    double2* W = plan->work;
+    hipLaunchKernelGGL(plan->cplx ? k_eigs2d_rows<true> : k_eigs2d_rows<false>,
+                       dim3((ax1.n + 255) / 256, static_cast<unsigned>(len0), static_cast<unsigned>(batch)), dim3(256), 0,
+                       stream, ax1, psf, len0, len1, c1, W);
+    ht_status st = check_hip(hipGetLastError(), "ht_eigs2d rows launch");
+    if (st != HT_OK) return st;
+    hipLaunchKernelGGL(plan->cplx ? k_eigs2d_cols<true> : k_eigs2d_cols<false>,
+                       dim3((ax1.n + E2_TJ - 1) / E2_TJ, (ax0.n + E2_TI - 1) / E2_TI, static_cast<unsigned>(batch)),
+                       dim3(256), 0, stream, ax0, ax1, static_cast<const double2*>(W), len0, c0, norm, d, s);
+    return check_hip(hipGetLastError(), "ht_eigs2d launch");
+}
+
 extern "C" ht_status ht_tikhonov_filter(const ht_plan* plan, const void* coeff, const void* d,
-                                        const double* s, int64_t eig_batch, const double* mu,
+                                        const double* s, int64_t eig_batch, int layout, const double* mu,
                                         void* fhat, int64_t batch, hipStream_t stream) {
     if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: null plan");
     if (batch < 0) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: negative batch");
     if (batch == 0) return HT_OK;
     if (!coeff || !d || !s || !mu || !fhat) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: null argument");
-    if (!(eig_batch == 1 || eig_batch == batch)) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: eig_batch must be 1 or batch");
-    if (plan->ndim == 2 && eig_batch != 1) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: 2D spectra are shared (eig_batch = 1)");
-    if (batch == 0) return HT_OK;
-    const Spec sp = make_spec(plan, d, s, eig_batch);
+    ht_status st = check_spectrum(plan, eig_batch, layout, batch, "ht_tikhonov_filter");
+    if (st != HT_OK) return st;
+    const Spec sp = make_spec(plan, d, s, eig_batch, layout);
     const int64_t total = batch * sp.per_item;
     const int64_t blocks = (total + 255) / 256;
     if (blocks > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_tikhonov_filter: batch too large");
@@ -413,7 +569,7 @@ extern "C" ht_status ht_tikhonov_filter(const ht_plan* plan, const void* coeff, 
 }
 
 extern "C" ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const void* d, const double* s,
-                                 int64_t eig_batch, const double* mu_grid, int32_t K, int grid_per_item,
+                                 int64_t eig_batch, int layout, const double* mu_grid, int32_t K, int grid_per_item,
                                  double* G, int32_t* k_best, double* mu_best, int64_t batch,
                                  hipStream_t stream) {
     if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: null plan");
@@ -421,10 +577,9 @@ extern "C" ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const v
     if (batch < 0 || batch > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: batch out of range");
     if (batch == 0) return HT_OK;
     if (!coeff || !d || !s || !mu_grid || !k_best) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: null argument");
-    if (!(eig_batch == 1 || eig_batch == batch)) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: eig_batch must be 1 or batch");
-    if (plan->ndim == 2 && eig_batch != 1) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: 2D spectra are shared (eig_batch = 1)");
-    if (batch == 0) return HT_OK;
-    const Spec sp = make_spec(plan, d, s, eig_batch);
+    ht_status st0 = check_spectrum(plan, eig_batch, layout, batch, "ht_gcv_scan");
+    if (st0 != HT_OK) return st0;
+    const Spec sp = make_spec(plan, d, s, eig_batch, layout);
     GcvOut o{mu_grid, grid_per_item ? static_cast<int64_t>(K) : 0, K, G, k_best, mu_best};
     if (plan->ndim == 1) {
         hipLaunchKernelGGL(k_gcv_single, dim3(static_cast<unsigned>(batch)), dim3(GCV_THREADS), 0, stream, sp, coeff, o);

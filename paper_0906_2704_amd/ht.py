@@ -20,6 +20,7 @@ KIND_NAMES = {1: "AR", 2: "C", 3: "F", 4: "DST2", 5: "DST3"}
 NORMS = {"I": HT_NORM_IDENTITY, "D2": HT_NORM_SECOND_DIFF}
 FAMILIES = {"paper": HT_FAMILY_PAPER, "dst": HT_FAMILY_DST, "paper+dst3": 2}
 PRECISIONS = {"f64": 0, "bf16x3": 1, "f16x3": 2, "f32": 3}
+SPECTRUM_FACTORS, SPECTRUM_FULL = 0, 1
 
 _lib = None
 
@@ -45,14 +46,15 @@ def lib():
     L.ht_eigs.argtypes = [P, VP, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.c_int, VP, VP, I64, VP]
     L.ht_transform_inv.argtypes = [P, VP, VP, I64, VP]
     L.ht_transform_fwd.argtypes = [P, VP, VP, I64, VP]
-    L.ht_tikhonov_filter.argtypes = [P, VP, VP, VP, I64, VP, VP, I64, VP]
-    L.ht_gcv_scan.argtypes = [P, VP, VP, VP, I64, VP, I32, ctypes.c_int, VP, VP, VP, I64, VP]
+    L.ht_eigs2d.argtypes = [P, VP, I64, I64, I64, I64, ctypes.c_int, VP, VP, I64, VP]
+    L.ht_tikhonov_filter.argtypes = [P, VP, VP, VP, I64, ctypes.c_int, VP, VP, I64, VP]
+    L.ht_gcv_scan.argtypes = [P, VP, VP, VP, I64, ctypes.c_int, VP, I32, ctypes.c_int, VP, VP, VP, I64, VP]
     L.ht_plan_set_precision.argtypes = [P, ctypes.c_int]
     L.ht_plan_precision.argtypes = [P]
     L.ht_status_str.argtypes = [ctypes.c_int]
     L.ht_status_str.restype = ctypes.c_char_p
     L.ht_last_error.restype = ctypes.c_char_p
-    for name in ("ht_plan_create", "ht_plan_destroy", "ht_eigs", "ht_transform_inv", "ht_transform_fwd",
+    for name in ("ht_plan_create", "ht_plan_destroy", "ht_eigs", "ht_eigs2d", "ht_transform_inv", "ht_transform_fwd",
                  "ht_tikhonov_filter", "ht_gcv_scan", "ht_plan_set_precision", "ht_plan_precision"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -149,6 +151,38 @@ def ht_eigs(plan, psf, psf_len, psf_center, norm, batch=1, d=None, s=None):
     return d, s
 
 
+def ht_eigs2d(plan, psf, psf_center, norm, d=None, s=None):
+    """Eigenvalues for general 2D masks (see include/ht.h): psf float64 device tensor
+    [batch, len0, len1] or [len0, len1]; returns d, s of shape [batch, n0, n1]."""
+    L = lib()
+    if plan.ndim != 2:
+        raise ValueError("ht_eigs2d needs a 2D plan")
+    H = psf if psf.dim() == 3 else psf.unsqueeze(0)
+    batch, len0, len1 = H.shape
+    n0, n1 = plan.n
+    if d is None:
+        d = torch.empty((batch, n0, n1), dtype=plan.coeff_dtype, device=psf.device)
+    if s is None:
+        s = torch.empty((batch, n0, n1), dtype=torch.float64, device=psf.device)
+    _check(L.ht_eigs2d(plan.handle, _ptr(H, torch.float64, "psf"), int(len0), int(len1), int(psf_center[0]),
+                       int(psf_center[1]), NORMS.get(norm, norm), _ptr(d, plan.coeff_dtype, "d"),
+                       _ptr(s, torch.float64, "s"), int(batch), _stream()), "ht_eigs2d")
+    return d, s
+
+
+def _spectrum(plan, d):
+    """(eig_batch, layout) of a spectrum tensor: 2D plans take the factors of ht_eigs
+    (n0 + n1 entries) or the full [eig_batch, n0, n1] arrays of ht_eigs2d."""
+    if plan.ndim == 2:
+        img = _item(plan)
+        if d.numel() == plan.spectrum_len():
+            return 1, SPECTRUM_FACTORS
+        if d.numel() % img == 0:
+            return d.numel() // img, SPECTRUM_FULL
+        raise ValueError("spectrum of %d entries fits neither layout" % d.numel())
+    return d.numel() // plan.spectrum_len(), SPECTRUM_FULL
+
+
 def ht_transform_inv(plan, signal, out=None):
     L = lib()
     batch = signal.numel() // _item(plan)
@@ -172,11 +206,11 @@ def ht_transform_fwd(plan, coeff, out=None):
 def ht_tikhonov_filter(plan, coeff, d, s, mu, out=None):
     L = lib()
     batch = coeff.numel() // _item(plan)
-    eig_batch = d.numel() // plan.spectrum_len()
+    eig_batch, layout = _spectrum(plan, d)
     if out is None:
         out = torch.empty_like(coeff)
     _check(L.ht_tikhonov_filter(plan.handle, _ptr(coeff, plan.coeff_dtype, "coeff"),
-                                _ptr(d, plan.coeff_dtype, "d"), _ptr(s, torch.float64, "s"), eig_batch,
+                                _ptr(d, plan.coeff_dtype, "d"), _ptr(s, torch.float64, "s"), eig_batch, layout,
                                 _ptr(mu, torch.float64, "mu"), _ptr(out, plan.coeff_dtype, "fhat"),
                                 batch, _stream()), "ht_tikhonov_filter")
     return out
@@ -186,7 +220,7 @@ def ht_gcv_scan(plan, coeff, d, s, mu_grid, want_G=True, G=None, kb=None, mb=Non
     """Returns (G or None, k_best int32 [batch], mu_best float64 [batch])."""
     L = lib()
     batch = coeff.numel() // _item(plan)
-    eig_batch = d.numel() // plan.spectrum_len()
+    eig_batch, layout = _spectrum(plan, d)
     K = mu_grid.shape[-1]
     per_item = 1 if mu_grid.dim() == 2 else 0
     dev = coeff.device
@@ -197,7 +231,7 @@ def ht_gcv_scan(plan, coeff, d, s, mu_grid, want_G=True, G=None, kb=None, mb=Non
     if mb is None:
         mb = torch.empty(batch, dtype=torch.float64, device=dev)
     _check(L.ht_gcv_scan(plan.handle, _ptr(coeff, plan.coeff_dtype, "coeff"), _ptr(d, plan.coeff_dtype, "d"),
-                         _ptr(s, torch.float64, "s"), eig_batch, _ptr(mu_grid, torch.float64, "mu_grid"),
+                         _ptr(s, torch.float64, "s"), eig_batch, layout, _ptr(mu_grid, torch.float64, "mu_grid"),
                          int(K), per_item, _ptr(G, torch.float64, "G"), _ptr(kb, torch.int32, "k_best"),
                          _ptr(mb, torch.float64, "mu_best"), batch, _stream()), "ht_gcv_scan")
     return G, kb, mb
