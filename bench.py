@@ -650,6 +650,120 @@ class Mixed2D:
         return 1.0 / el, "image 0 of the batch, plain float64 dense solves and products, float64 GCV sums"
 
 
+class Mask2D:
+    """Out-of-focus deblurring with a non-separable mask (the 2D experiment of Section 6):
+    a batch of 16 piecewise-quadratic images 1024 x 1024, disk PSF of radius 8 (a 17 x 17
+    mask, not separable), 0.1% noise, degree 2 on both axes (T_C x T_C), L = I, GCV over
+    128 mu on [1e-6, 1]; the eigenvalues by the three steps of Section 6 (ht_eigs2d), all
+    in float64."""
+
+    stages = ["eigs", "transform_inv", "gcv_scan", "tikhonov_filter", "transform_fwd"]
+
+    def __init__(self, torch, ht, synth, batch=16, n=1024, radius=8.0):
+        self.torch, self.ht, self.synth = torch, ht, synth
+        self.batch, self.n, self.radius = batch, n, radius
+        self.name = "2d_disk_r%g_tc_%dx%d_x%d" % (radius, n, n, batch)
+        self.kind = "C"
+
+    def setup(self):
+        torch, ht, synth = self.torch, self.ht, self.synth
+        self.imgs = [synth.disk_image(i, self.n, self.radius) for i in range(self.batch)]
+        p0 = self.imgs[0]
+        dev = "cuda"
+        self.plan = ht.Plan((self.n, self.n), 2, psf_symmetric=True, max_batch=self.batch)
+        self.g = torch.tensor(np.stack([p.g for p in self.imgs]), device=dev)
+        self.psf = torch.tensor(p0.H, device=dev)
+        self.center = (p0.c0, p0.c1)
+        self.mus_host = p0.mus
+        self.mus = torch.tensor(p0.mus, device=dev)
+        n = self.n
+        self.d = torch.empty((1, n, n), dtype=torch.float64, device=dev)
+        self.s = torch.empty((1, n, n), dtype=torch.float64, device=dev)
+        self.ghat = torch.empty_like(self.g)
+        self.fhat = torch.empty_like(self.g)
+        self.f = torch.empty_like(self.g)
+        self.Gv = torch.empty((self.batch, len(p0.mus)), dtype=torch.float64, device=dev)
+        self.kb = torch.empty(self.batch, dtype=torch.int32, device=dev)
+        self.mb = torch.empty(self.batch, dtype=torch.float64, device=dev)
+
+    def step(self, t):
+        ht = self.ht
+        t.start_step()
+        ht.ht_eigs2d(self.plan, self.psf, self.center, "I", d=self.d, s=self.s)
+        t.mark()
+        ht.ht_transform_inv(self.plan, self.g, out=self.ghat)
+        t.mark()
+        ht.ht_gcv_scan(self.plan, self.ghat, self.d, self.s, self.mus, G=self.Gv, kb=self.kb, mb=self.mb)
+        t.mark()
+        ht.ht_tikhonov_filter(self.plan, self.ghat, self.d, self.s, self.mb, out=self.fhat)
+        t.mark()
+        ht.ht_transform_fwd(self.plan, self.fhat, out=self.f)
+        t.mark()
+
+    def config(self):
+        L = self.imgs[0].H.shape
+        return {"workload": self.name, "batch": self.batch, "n": [self.n, self.n], "kind": "C x C", "norm": "I",
+                "K": len(self.mus_host), "psf": "disk radius %g (%dx%d mask)" % (self.radius, L[0], L[1])}
+
+    def work(self):
+        B, n, K = self.batch, self.n, len(self.mus_host)
+        L0, L1 = self.imgs[0].H.shape
+        px = B * n * n
+        return {
+            # one fused multiply-add per (mask row, column, tap) and per (row, column, mask row)
+            "eigs": ("alu", 2.0 * (L0 * n * L1 + n * n * L0)),
+            "transform_inv": ("hbm", px * 16),
+            "gcv_scan": ("alu", px * K * GCV_FLOPS_PER_PAIR),
+            "tikhonov_filter": ("hbm", px * 16 + n * n * 16 + B * 8),
+            "transform_fwd": ("hbm", px * 16),
+        }
+
+    def check(self):
+        """Images 0 and B-1 against the oracle (plain float64 solves and products, the
+        3-step eigenvalues in long double, float64 GCV sums), and the restoration error
+        against the true images."""
+        from oracle import tikhonov as tk
+        from oracle import twod
+        n = self.n
+        worst = {}
+        for i in (0, self.batch - 1):
+            p = self.imgs[i]
+            gh = twod.inverse2d("C", "C", p.g, refine_steps=0)
+            d = twod.eigs2d_general("C", "C", n, n, p.H, p.c0, p.c1)
+            G = tk.gcv_values(gh.ravel(), d.ravel(), np.ones(n * n), p.mus, wide=False)
+            k = int(self.kb[i])
+            ko = int(np.argmin(G))
+            fo = twod.forward2d("C", "C", tk.tikhonov_filter(gh, d, np.ones((n, n)), float(p.mus[ko])), wide=False)
+            e = {"d": float(np.abs(self.d[0].cpu().numpy() - d).max() / np.abs(p.H).sum()),
+                 "ghat": float(np.linalg.norm(self.ghat[i].cpu().numpy() - gh) / np.linalg.norm(gh)),
+                 "G": float(np.max(np.abs(self.Gv[i].cpu().numpy() - G) / G)),
+                 "f": float(np.linalg.norm(self.f[i].cpu().numpy() - fo) / np.linalg.norm(fo)),
+                 "k_match": k == ko}
+            for key, v in e.items():
+                worst[key] = v if key not in worst else (max(worst[key], v) if key != "k_match" else worst[key] and v)
+        f = self.f.cpu().numpy()
+        rre = [float(np.linalg.norm(f[i] - p.f_true) / np.linalg.norm(p.f_true)) for i, p in enumerate(self.imgs)]
+        worst["rre_mean"] = float(np.mean(rre))
+        self.errors = worst
+        return worst["f"]
+
+    def cpu_baseline(self, budget_s):
+        """The oracle's restoration of one image: dense float64 solves and products along
+        both axes, the 3-step eigenvalues, float64 GCV sums."""
+        from oracle import tikhonov as tk
+        from oracle import twod
+        n = self.n
+        p = self.imgs[0]
+        t0 = time.perf_counter()
+        gh = twod.inverse2d("C", "C", p.g, refine_steps=0)
+        d = twod.eigs2d_general("C", "C", n, n, p.H, p.c0, p.c1)
+        G = tk.gcv_values(gh.ravel(), d.ravel(), np.ones(n * n), p.mus, wide=False)
+        mu = float(p.mus[int(np.argmin(G))])
+        twod.forward2d("C", "C", tk.tikhonov_filter(gh, d, np.ones((n, n)), mu), wide=False)
+        el = time.perf_counter() - t0
+        return 1.0 / el, "image 0 of the batch, plain float64 dense solves and products, float64 GCV sums"
+
+
 def csrc_hash():
     import glob
     import hashlib
@@ -693,7 +807,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="learned", choices=["learned", "ragged", "uniform", "mixed"])
+    ap.add_argument("--workload", default="learned", choices=["learned", "ragged", "uniform", "mixed", "mask"])
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x3"], help="mixed: core arithmetic")
     ap.add_argument("--train", type=int, default=200000, help="learned: training problems")
     ap.add_argument("--epochs", type=int, default=25, help="learned: training epochs")
@@ -729,6 +843,8 @@ def main():
         wl.torch, wl.ht = torch, ht
     elif args.workload == "mixed":
         wl = Mixed2D(torch, ht, synth, args.batch or 16, precision=args.precision)
+    elif args.workload == "mask":
+        wl = Mask2D(torch, ht, synth, args.batch or 16)
     elif args.workload == "ragged":
         wl = Ragged1D(torch, ht, synth, args.batch or 4096, graph=not args.no_graph, autotune=not args.no_autotune)
     else:
@@ -767,6 +883,8 @@ def main():
     err = None if args.no_check else wl.check()
 
     extra = {}
+    if isinstance(wl, Mask2D):
+        extra["errors_vs_oracle"] = getattr(wl, "errors", None)
     if isinstance(wl, Mixed2D):
         extra["errors_vs_oracle"] = getattr(wl, "errors", None)
         gf = wl.gemm_flops()
