@@ -10,8 +10,11 @@ rotated by 180 degrees) and L = T diag(s) T^{-1}:
               sigma_i = |s_i|^2 / (|d_i|^2 + mu |s_i|^2), ghat = T^{-1} g; mu_GCV is the
               minimiser over the caller's grid, the first one on ties (R9), and the modulus
               is taken for complex coefficients (R6).
-* eq. gcv     the exact functional ||g - A f_reg||^2 / trace(I - A T Phi D^{-1} T^{-1})^2
-              (diagnostic only: the method minimises the eq. mugcv approximation).
+* eq. gcv     the exact functional ||g - A f_reg||^2 / trace(I - A T Phi D^{-1} T^{-1})^2.
+              The residual is g - A f_reg = T (I - Phi) ghat (eq. gcnum before its
+              approximation) and the trace is sum_i (1 - Phi_i) = mu sum_i sigma_i (R8), so
+              eq. gcv = ||T (sigma ghat)||^2 / (sum_i sigma_i)^2: eq. gcv2 with the norm of
+              T applied to sigma ghat instead of the norm of sigma ghat (``gcv_exact_values``).
 """
 
 import numpy as np
@@ -47,6 +50,25 @@ def gcv_values(ghat, d, s, mus, wide=True):
     for k, mu in enumerate(mus):
         sigma = s2 / (d2 + R(mu) * s2)
         out[k] = np.float64(np.sum(sigma * sigma * g2) / np.sum(sigma) ** 2)
+    return out
+
+
+def gcv_exact_values(kind, ghat, d, s, mus):
+    """Eq. gcv for every mu_k of the grid: ||T (sigma ghat)||^2 / (sum_i sigma_i)^2 with the
+    dense transform T of the kind (long double), i.e. the exact residual norm of eq. gcnum
+    instead of its approximation, on the same scale as ``gcv_values`` (the factors mu^2 of
+    numerator and denominator cancel).  1D, any kind; O(n^2) per grid value."""
+    n = len(ghat)
+    T = tr.transform_matrix(kind, n).astype(np.clongdouble)
+    gl = np.asarray(ghat).astype(np.clongdouble)
+    dl = np.asarray(d).astype(np.clongdouble)
+    s2 = np.asarray(s).astype(LD) ** 2
+    d2 = (dl * np.conj(dl)).real
+    out = np.empty(len(mus), dtype=np.float64)
+    for k, mu in enumerate(mus):
+        sigma = s2 / (d2 + LD(mu) * s2)
+        r = T @ (sigma * gl)
+        out[k] = np.float64(np.sum((r * np.conj(r)).real) / np.sum(sigma) ** 2)
     return out
 
 
