@@ -66,10 +66,10 @@ class Uniform1D:
 
     stages = ["eigs", "transform_inv", "gcv_scan", "tikhonov_filter", "transform_fwd"]
 
-    def __init__(self, torch, ht, synth, batch, n=256, degree=2):
+    def __init__(self, torch, ht, synth, batch, n=256, degree=2, gcv="approx"):
         self.torch, self.ht, self.synth = torch, ht, synth
-        self.batch, self.n, self.degree = batch, n, degree
-        self.name = "1d_uniform_n%d_d%d_x%d" % (n, degree, batch)
+        self.batch, self.n, self.degree, self.gcv = batch, n, degree, gcv
+        self.name = "1d_uniform_n%d_d%d_x%d%s" % (n, degree, batch, "_exact_gcv" if gcv == "exact" else "")
 
     def setup(self):
         torch, ht, synth = self.torch, self.ht, self.synth
@@ -98,7 +98,8 @@ class Uniform1D:
         t.mark()
         ht.ht_transform_inv(self.plan, self.g, out=self.ghat)
         t.mark()
-        ht.ht_gcv_scan(self.plan, self.ghat, self.d, self.s, self.mus, G=self.Gv, kb=self.kb, mb=self.mb)
+        scan = ht.ht_gcv_scan_exact if self.gcv == "exact" else ht.ht_gcv_scan
+        scan(self.plan, self.ghat, self.d, self.s, self.mus, G=self.Gv, kb=self.kb, mb=self.mb)
         t.mark()
         ht.ht_tikhonov_filter(self.plan, self.ghat, self.d, self.s, self.mb, out=self.fhat)
         t.mark()
@@ -107,16 +108,19 @@ class Uniform1D:
 
     def config(self):
         return {"workload": self.name, "batch": self.batch, "n": self.n, "kind": self.kind, "norm": "D2",
-                "K": len(self.mus_host)}
+                "K": len(self.mus_host), "gcv": "eq. gcv (exact)" if self.gcv == "exact" else "eq. mugcv"}
 
     def work(self):
         """Algorithmic bytes / flops per launch of each stage."""
         B, n, K = self.batch, self.n, len(self.mus_host)
         cb = 16 if self.plan.is_complex else 8
+        # the exact functional adds one fused multiply-add per (element, mu, fixed vector):
+        # 4 vectors for T_C (two boundary columns, two ghost rows)
+        per_pair = GCV_FLOPS_PER_PAIR + (2 * 4 if self.gcv == "exact" else 0)
         return {
             "eigs": ("hbm", (len(self.h) * 8 + n * (cb + 8))),
             "transform_inv": ("hbm", B * n * (8 + cb)),
-            "gcv_scan": ("alu", B * n * K * GCV_FLOPS_PER_PAIR),
+            "gcv_scan": ("alu", B * n * K * per_pair),
             "tikhonov_filter": ("hbm", B * n * 2 * cb + B * 8),
             "transform_fwd": ("hbm", B * n * (cb + 8)),
         }
@@ -132,7 +136,12 @@ class Uniform1D:
         worst = 0.0
         for b in (0, self.batch // 2, self.batch - 1):
             gw = tr.inverse(self.kind, self.G_host[b])
-            _, kw, muw = tk.gcv_scan(gw, d, s, self.mus_host)
+            if self.gcv == "exact":
+                Gx = tk.gcv_exact_values(self.kind, gw, d, s, self.mus_host)
+                kw = tk.gcv_argmin(Gx)
+                muw = float(self.mus_host[kw])
+            else:
+                _, kw, muw = tk.gcv_scan(gw, d, s, self.mus_host)
             assert kw == kb[b], (b, kw, kb[b])
             fw = tr.forward(self.kind, tk.tikhonov_filter(gw, d, s, muw)).real
             worst = max(worst, float(np.max(np.abs(f[b] - fw)) / np.max(np.abs(fw))))
@@ -150,7 +159,10 @@ class Uniform1D:
         while time.perf_counter() - t0 < budget_s and done < self.batch:
             g = self.G_host[done]
             gw = tr.inverse(self.kind, g)
-            _, _, muw = tk.gcv_scan(gw, d, s, self.mus_host)
+            if self.gcv == "exact":
+                muw = float(self.mus_host[tk.gcv_argmin(tk.gcv_exact_values(self.kind, gw, d, s, self.mus_host))])
+            else:
+                _, _, muw = tk.gcv_scan(gw, d, s, self.mus_host)
             tr.forward(self.kind, tk.tikhonov_filter(gw, d, s, muw))
             done += 1
         el = time.perf_counter() - t0
@@ -809,6 +821,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="learned", choices=["learned", "ragged", "uniform", "mixed", "mask"])
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x3"], help="mixed: core arithmetic")
+    ap.add_argument("--gcv", default="approx", choices=["approx", "exact"],
+                    help="uniform: the eq. mugcv scan or the exact eq. gcv functional")
     ap.add_argument("--train", type=int, default=200000, help="learned: training problems")
     ap.add_argument("--epochs", type=int, default=25, help="learned: training epochs")
     ap.add_argument("--learned-path", default="two-pass", choices=["two-pass", "fused"],
@@ -848,7 +862,7 @@ def main():
     elif args.workload == "ragged":
         wl = Ragged1D(torch, ht, synth, args.batch or 4096, graph=not args.no_graph, autotune=not args.no_autotune)
     else:
-        wl = Uniform1D(torch, ht, synth, args.batch or 65536)
+        wl = Uniform1D(torch, ht, synth, args.batch or 65536, gcv=args.gcv)
     print("setup %s" % wl.name, file=sys.stderr, flush=True)
     wl.setup()
     if args.copy_calibration_mib > 0:

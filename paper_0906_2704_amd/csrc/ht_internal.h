@@ -71,6 +71,22 @@ struct View {
 
 struct GemmState;  // split-precision matrix-core cores of a plan (ht_gemm.hip)
 
+// Exact GCV of a 1D plan (eq. gcv): with T = [t0 | core columns | t_{n-1}], interior rows
+// T_I = S v_mid + R_C v_C (S the orthonormal core of order N, R_C the interior parts of the
+// boundary and replaced columns C) and the two boundary rows,
+//   ||T v||^2 = ||v_mid||^2 + 2 Re sum_c conj(P_c) v_c + v_C^H Gam v_C + |y_0|^2 + |y_{n-1}|^2,
+//   P_c = (S^H R_c)^H v_mid,  y_0 = t0_0 v_0 + tn_0 v_{n-1} + a . v_mid  (y_{n-1} with b).
+// vec[k][j] (k < nv, j < N) holds the factors f with P_c = sum_j f_j v_j:
+// conj(S^H R_c) for the columns of C, then a and b when the core has ghost rows.
+constexpr int XG_MAXC = 4;
+struct XgcvParams {
+    const double2* vec;   // [nv][N]
+    int nc, nv, rows;     // |C|, number of vectors, 1 if a and b are present
+    int cidx[XG_MAXC];    // coefficient index of each column of C
+    double gam[XG_MAXC][XG_MAXC];
+    double t00, t0n, tn0, tnn;  // T[0][0], T[0][n-1], T[n-1][0], T[n-1][n-1]
+};
+
 }  // namespace ht
 
 struct ht_plan {
@@ -87,6 +103,8 @@ struct ht_plan {
     ht::GemmState* gemm = nullptr;     // set by ht_plan_set_precision (null: float64 core)
     int f32 = 0;                       // float32 chirp-z cores (HT_PRECISION_F32)
     void* arena32 = nullptr;           // their tables
+    ht::XgcvParams xg{};               // 1D: exact GCV tables (vec in xg_mem)
+    void* xg_mem = nullptr;
 };
 
 namespace ht {
@@ -100,6 +118,10 @@ const double2* device_twiddles(int device, ht_status* st);
 ht_status gemm_transform(const ht_plan* p, bool inverse, const double* in, double* out, int64_t batch,
                          hipStream_t stream);
 void gemm_release(GemmState* g);
+
+// exact GCV tables of a 1D plan (ht_plan.hip)
+struct HostAxis;
+ht_status build_exact_gcv(const HostAxis& h, ht_plan* p);
 
 // float32 chirp-z cores (ht_plan.hip)
 ht_status plan_build_f32(ht_plan* p);

@@ -165,20 +165,29 @@ static void make_chirp(int kind, bool synthesis, int N, int M, HostChirp& hc) {
     hc.B.swap(bc);
 }
 
-// Host replica of the chirp-z core (used at plan creation only, for K = Q * bubbles).
-static std::vector<double> host_core(const HostChirp& hc, const std::vector<double>& x, int M) {
+// Host replica of the chirp-z core (used at plan creation only): the core transform of a
+// real vector, as the device core returns it (real part, imaginary part for the sine
+// core, or the complex value for the DFT analysis).
+static std::vector<cd> host_core_c(const HostChirp& hc, const std::vector<double>& x, int M) {
     const int N = static_cast<int>(x.size());
     std::vector<cd> a(M, cd());
     for (int j = 0; j < N; ++j) a[j] = x[j] * hc.pre[j];
     host_fft(a, -1);
     for (int k = 0; k < M; ++k) a[k] *= hc.B[k];
     host_fft(a, 1);
-    std::vector<double> y(N);
+    std::vector<cd> y(N);
     for (int k = 0; k < N; ++k) {
         const cd v = a[k] * hc.post[k];
-        y[k] = hc.mode == MODE_IM ? v.imag() : v.real();
+        y[k] = hc.mode == MODE_IM ? cd(v.imag(), 0.0) : hc.mode == MODE_RE ? cd(v.real(), 0.0) : v;
     }
     return y;
+}
+
+static std::vector<double> host_core(const HostChirp& hc, const std::vector<double>& x, int M) {
+    const std::vector<cd> y = host_core_c(hc, x, M);
+    std::vector<double> r(y.size());
+    for (size_t k = 0; k < y.size(); ++k) r[k] = y[k].real();
+    return r;
 }
 
 // ----------------------------------------------------------------------- axis tables
@@ -312,6 +321,88 @@ ht_status build_axis(int n, int kind, HostAxis& h) {
         h.tcos[r] = w.real();
         h.tsin[r] = w.imag();
     }
+    return HT_OK;
+}
+
+// Tables of the exact GCV (eq. gcv) of a 1D plan: the columns R_c (interior parts of the
+// boundary columns, bubble minus the sine column it replaces), M_c = S^H R_c by the host
+// core, their Gram matrix, the ghost rows a, b of the cosine / Fourier cores and the corner
+// entries of T.
+ht_status build_exact_gcv(const HostAxis& h, ht_plan* p) {
+    const Axis& ax = h.ax;
+    const int n = ax.n, N = ax.N, kind = ax.kind;
+    XgcvParams xp{};
+    std::vector<std::vector<double>> R;
+    std::vector<std::vector<cd>> Mc;
+    std::vector<double> qi(N), jqi(N);
+    for (int k = 0; k < N; ++k) {
+        qi[k] = h.q[k + 1];
+        jqi[k] = h.q[n - 2 - k];
+    }
+    R.push_back(qi);
+    R.push_back(jqi);
+    Mc.push_back(host_core_c(h.ana, qi, h.M));
+    Mc.push_back(host_core_c(h.ana, jqi, h.M));
+    xp.cidx[0] = 0;
+    xp.cidx[1] = n - 1;
+    for (int c = 0; c < ax.rank; ++c) {
+        // bubble c replaces sine column c+1: R = bub - s, S^H R = K - e_c = U[c]
+        std::vector<double> r(N);
+        const ld sc = sqrtl(2.0L / (N + 1));
+        for (int k = 0; k < N; ++k) {
+            const cd w = cis_exact(static_cast<int64_t>(c + 1) * (k + 1), 2LL * (N + 1), sc);  // sqrt(2/(N+1)) e^{i pi (c+1)(k+1)/(N+1)}
+            r[k] = h.bub[static_cast<size_t>(c) * N + k] - w.imag();
+        }
+        R.push_back(r);
+        std::vector<cd> m(N);
+        for (int k = 0; k < N; ++k) m[k] = cd(h.U[static_cast<size_t>(c) * N + k], 0.0);
+        Mc.push_back(m);
+        xp.cidx[2 + c] = c + 1;
+    }
+    xp.nc = static_cast<int>(R.size());
+    xp.rows = (kind == HT_KIND_C || kind == HT_KIND_F) ? 1 : 0;
+    xp.nv = xp.nc + 2 * xp.rows;  // 2 (AR), 3 (DST2), 4 (C, F, DST3)
+    if (xp.nv > 4) return fail(HT_ERR_INVALID_ARG, "internal: too many exact GCV vectors");
+    for (int i = 0; i < xp.nc; ++i)
+        for (int j = 0; j < xp.nc; ++j) {
+            ld acc = 0.0L;
+            for (int k = 0; k < N; ++k) acc += static_cast<ld>(R[i][k]) * R[j][k];
+            xp.gam[i][j] = static_cast<double>(acc);
+        }
+    xp.t00 = h.q[0];
+    xp.t0n = h.q[n - 1];
+    xp.tn0 = h.q[n - 1];
+    xp.tnn = h.q[0];
+    std::vector<double2> host(static_cast<size_t>(xp.nv) * N);
+    for (int c = 0; c < xp.nc; ++c)
+        for (int k = 0; k < N; ++k) host[static_cast<size_t>(c) * N + k] = make_double2(Mc[c][k].real(), -Mc[c][k].imag());
+    if (xp.rows) {
+        double2* av = &host[static_cast<size_t>(xp.nc) * N];
+        double2* bv = &host[static_cast<size_t>(xp.nc + 1) * N];
+        for (int m = 0; m < N; ++m) {
+            if (kind == HT_KIND_C) {
+                // column m of the DCT-III core at the ghost points x = -pi/(2N), (2N+1) pi/(2N)
+                const ld wm = sqrtl((m == 0 ? 1.0L : 2.0L) / N);
+                const cd e = cis_exact(m, 4LL * N, wm);
+                av[m] = make_double2(e.real(), 0.0);
+                bv[m] = make_double2((m & 1) ? -e.real() : e.real(), 0.0);
+            } else {
+                // column m of the inverse DFT core at x = -2 pi/N and x = 2 pi
+                const cd e = cis_exact(-static_cast<int64_t>(m), N, 1.0L / sqrtl(static_cast<ld>(N)));
+                av[m] = make_double2(e.real(), e.imag());
+                bv[m] = make_double2(static_cast<double>(1.0L / sqrtl(static_cast<ld>(N))), 0.0);
+            }
+        }
+    }
+    void* mem = nullptr;
+    if (hipMalloc(&mem, sizeof(double2) * host.size()) != hipSuccess) return fail(HT_ERR_OOM, "exact GCV table allocation failed");
+    if (hipMemcpy(mem, host.data(), sizeof(double2) * host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(mem);
+        return fail(HT_ERR_HIP, "exact GCV table upload failed");
+    }
+    xp.vec = static_cast<const double2*>(mem);
+    p->xg = xp;
+    p->xg_mem = mem;
     return HT_OK;
 }
 
@@ -517,6 +608,13 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
         return st;
     }
     for (int a = 0; a < ndim; ++a) p->ax[a].tw = tw;
+    if (ndim == 1) {
+        st = build_exact_gcv(hs[0], p);
+        if (st != HT_OK) {
+            ht_plan_destroy(p);
+            return st;
+        }
+    }
     if (ndim == 2) {
         const int64_t img = n[0] * n[1];
         if (hipMalloc(&p->work, sizeof(double2) * img * max_batch) != hipSuccess) {
@@ -538,6 +636,7 @@ extern "C" ht_status ht_plan_destroy(ht_plan* p) {
     if (p->arena) (void)hipFree(p->arena);
     if (p->work) (void)hipFree(p->work);
     if (p->gcv_part) (void)hipFree(p->gcv_part);
+    if (p->xg_mem) (void)hipFree(p->xg_mem);
     gemm_release(p->gemm);
     plan_release_f32(p);
     delete p;

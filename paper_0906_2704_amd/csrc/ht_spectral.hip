@@ -453,6 +453,165 @@ __global__ __launch_bounds__(GCV_THREADS) void k_gcv_finalize(GcvOut o, int64_t 
                o.mubest ? o.mubest + b : nullptr, Gs, &kshared);
 }
 
+// ----------------------------------------------------------------------- exact GCV
+
+// Eq. gcv for a 1D batch: G(mu) = ||T (sigma ghat)||^2 / (sum sigma)^2 (the residual norm
+// of eq. gcnum without its approximation), ||T v||^2 from the structure of T (XgcvParams).
+// One block per signal.  Per chunk of the core range j = 1..N the block stages t_j,
+// w_j = |ghat_j|^2 and u_kj = vec[k][j-1] ghat_j; thread (part, kl) takes the grid values
+// a = 2 (k0 + kl) and b = a + 1 and accumulates, with r = 1/(t + mu) (one reciprocal of
+// (t + mu_a)(t + mu_b) per element for both), D += r, W += w r^2, P_k += u_k r over the
+// staged elements part, part + nparts, ...; parts are added in order (bitwise
+// reproducible).
+constexpr int XG_THREADS = 256;
+constexpr int XG_CHUNK = 256;
+constexpr int XG_NV = 4;                 // fixed vectors: |C| + 2 ghost rows <= 4 for every kind
+constexpr int XG_ACC = 2 + 2 * XG_NV;     // D, W, complex P_k
+
+template <bool CPLX>
+__global__ __launch_bounds__(XG_THREADS) void k_gcv_exact(Spec sp, const void* __restrict__ coeff, GcvOut o,
+                                                          XgcvParams xp, int n) {
+    constexpr int UW = CPLX ? 2 : 1;  // doubles per staged u
+    __shared__ double st_t[XG_CHUNK], st_w[XG_CHUNK];
+    __shared__ double st_u[XG_NV * UW][XG_CHUNK];
+    __shared__ double red[XG_THREADS][XG_ACC + 1];
+    __shared__ double Gs[1024];
+    __shared__ int kshared;
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const double* mus = o.mus + b * o.mu_stride;
+    const int K = o.K, N = n - 2, nv = xp.nv;
+    const int Kh = (K + 1) / 2;
+    const int Kb = Kh < XG_THREADS ? Kh : XG_THREADS;
+    const int nparts = XG_THREADS / Kb;
+    const int part = tid / Kb, kl = tid - part * Kb;
+    // t and ghat of element e (t = 1e150 where s = 0, as in the approximate scan)
+    auto load = [&](int64_t e, double& t, double2& g) {
+        double2 dd;
+        double ss;
+        spec_at(sp, b, e, dd, ss);
+        g = cload(coeff, b * sp.per_item + e, sp.cplx);
+        const double s2 = ss * ss;
+        t = 1e150;
+        if (s2 != 0.0) t = fma(dd.x, dd.x, dd.y * dd.y) / s2;
+    };
+    for (int k0 = 0; k0 < Kh; k0 += Kb) {
+        const int kk = k0 + kl;
+        const bool active = part < nparts && kk < Kh;
+        const int ka = 2 * kk, kb2 = ka + 1 < K ? ka + 1 : ka;
+        const double mua = active ? mus[ka] : 1.0, mub = active ? mus[kb2] : 1.0;
+        double Da = 0.0, Wa = 0.0, Db = 0.0, Wb = 0.0;
+        double2 Pa[XG_NV], Pb[XG_NV];
+#pragma unroll
+        for (int v = 0; v < XG_NV; ++v) Pa[v] = Pb[v] = make_double2(0.0, 0.0);
+        for (int c0 = 0; c0 < N; c0 += XG_CHUNK) {
+            const int len = N - c0 < XG_CHUNK ? N - c0 : XG_CHUNK;
+            __syncthreads();
+            for (int i = tid; i < len; i += XG_THREADS) {
+                const int j = c0 + i;  // core index; coefficient j + 1
+                double t;
+                double2 g;
+                load(j + 1, t, g);
+                const bool zero = t == 1e150;
+                st_t[i] = t;
+                st_w[i] = zero ? 0.0 : fma(g.x, g.x, g.y * g.y);
+                for (int v = 0; v < nv; ++v) {
+                    const double2 u = zero ? make_double2(0.0, 0.0) : cmul(xp.vec[static_cast<int64_t>(v) * N + j], g);
+                    st_u[v * UW][i] = u.x;
+                    if (CPLX) st_u[v * UW + 1][i] = u.y;
+                }
+            }
+            __syncthreads();
+            if (active) {
+                for (int i = part; i < len; i += nparts) {
+                    const double t = st_t[i], w = st_w[i];
+                    const double ua = t + mua, ub = t + mub;
+                    const double R = rcp_nr(ua * ub);
+                    const double ra = ub * R, rb = ua * R;
+                    Da += ra;
+                    Db += rb;
+                    Wa = fma(w, ra * ra, Wa);
+                    Wb = fma(w, rb * rb, Wb);
+#pragma unroll
+                    for (int v = 0; v < XG_NV; ++v) {
+                        if (v < nv) {
+                            const double ux = st_u[v * UW][i];
+                            Pa[v].x = fma(ux, ra, Pa[v].x);
+                            Pb[v].x = fma(ux, rb, Pb[v].x);
+                            if (CPLX) {
+                                const double uy = st_u[v * UW + UW - 1][i];
+                                Pa[v].y = fma(uy, ra, Pa[v].y);
+                                Pb[v].y = fma(uy, rb, Pb[v].y);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // two rounds through the reduction buffer: grid value a, then b
+        for (int round = 0; round < 2; ++round) {
+            __syncthreads();
+            if (part < nparts) {
+                double* rr = red[tid];
+                rr[0] = round ? Db : Da;
+                rr[1] = round ? Wb : Wa;
+                for (int v = 0; v < XG_NV; ++v) {
+                    const double2 P = round ? Pb[v] : Pa[v];
+                    rr[2 + 2 * v] = P.x;
+                    rr[3 + 2 * v] = P.y;
+                }
+            }
+            __syncthreads();
+            const int k = round ? ka + 1 : ka;
+            if (part == 0 && kk < Kh && k < K) {
+                const double mu = round ? mub : mua;
+                double acc[XG_ACC];
+                for (int a = 0; a < XG_ACC; ++a) acc[a] = red[kl][a];
+                for (int p = 1; p < nparts; ++p)
+                    for (int a = 0; a < XG_ACC; ++a) acc[a] += red[p * Kb + kl][a];
+                // boundary and replaced coefficients: v_c = ghat_c r_c
+                double2 vc[XG_MAXC];
+                double Dt = acc[0];
+                for (int c = 0; c < xp.nc; ++c) {
+                    double t;
+                    double2 g;
+                    load(xp.cidx[c], t, g);
+                    const double r = rcp_nr(t + mu);
+                    vc[c] = t == 1e150 ? make_double2(0.0, 0.0) : make_double2(g.x * r, g.y * r);
+                    if (c < 2) Dt += r;  // the two polynomial entries of the trace
+                }
+                double num = acc[1];
+                for (int c = 0; c < xp.nc; ++c) {
+                    const double2 Pc = make_double2(acc[2 + 2 * c], acc[3 + 2 * c]);
+                    num += 2.0 * (Pc.x * vc[c].x + Pc.y * vc[c].y);   // 2 Re(conj(P_c) v_c)
+                    for (int c2 = 0; c2 < xp.nc; ++c2)
+                        num += xp.gam[c][c2] * (vc[c].x * vc[c2].x + vc[c].y * vc[c2].y);
+                }
+                // boundary rows: y_0 = t00 v_0 + t0n v_{n-1} (+ a . v_mid), y_{n-1} likewise
+                double2 y0 = make_double2(xp.t00 * vc[0].x + xp.t0n * vc[1].x, xp.t00 * vc[0].y + xp.t0n * vc[1].y);
+                double2 yn = make_double2(xp.tn0 * vc[0].x + xp.tnn * vc[1].x, xp.tn0 * vc[0].y + xp.tnn * vc[1].y);
+                if (xp.rows) {
+                    y0.x += acc[2 + 2 * xp.nc];
+                    y0.y += acc[3 + 2 * xp.nc];
+                    yn.x += acc[4 + 2 * xp.nc];
+                    yn.y += acc[5 + 2 * xp.nc];
+                }
+                num += y0.x * y0.x + y0.y * y0.y + yn.x * yn.x + yn.y * yn.y;
+                const double g = num / (Dt * Dt);
+                Gs[k] = g;
+                if (o.G) o.G[b * K + k] = g;
+            }
+        }
+    }
+    __syncthreads();
+    gcv_argmin(Gs, K, &kshared);
+    if (tid == 0) {
+        const int kb = kshared;
+        o.kbest[b] = kb;
+        if (o.mubest) o.mubest[b] = kb >= 0 ? mus[kb] : __builtin_nan("");
+    }
+}
+
 static Spec make_spec(const ht_plan* plan, const void* d, const double* s, int64_t eig_batch, int layout) {
     Spec sp;
     sp.d = d;
@@ -598,4 +757,23 @@ extern "C" ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const v
     if (st != HT_OK) return st;
     hipLaunchKernelGGL(k_gcv_finalize, dim3(static_cast<unsigned>(batch)), dim3(GCV_THREADS), 0, stream, o, nw, part);
     return check_hip(hipGetLastError(), "ht_gcv_scan finalize launch");
+}
+
+extern "C" ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, const void* d, const double* s,
+                                       int64_t eig_batch, const double* mu_grid, int32_t K, int grid_per_item,
+                                       double* G, int32_t* k_best, double* mu_best, int64_t batch,
+                                       hipStream_t stream) {
+    if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: null plan");
+    if (plan->ndim != 1 || !plan->xg_mem) return fail(HT_ERR_UNSUPPORTED, "ht_gcv_scan_exact: 1D plans only");
+    if (K < 1 || K > 1024) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: K must be in [1, 1024]");
+    if (batch < 0 || batch > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: batch out of range");
+    if (batch == 0) return HT_OK;
+    if (!coeff || !d || !s || !mu_grid || !k_best) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: null argument");
+    ht_status st = check_spectrum(plan, eig_batch, HT_SPECTRUM_FULL, batch, "ht_gcv_scan_exact");
+    if (st != HT_OK) return st;
+    const Spec sp = make_spec(plan, d, s, eig_batch, HT_SPECTRUM_FULL);
+    GcvOut o{mu_grid, grid_per_item ? static_cast<int64_t>(K) : 0, K, G, k_best, mu_best};
+    hipLaunchKernelGGL(plan->cplx ? k_gcv_exact<true> : k_gcv_exact<false>, dim3(static_cast<unsigned>(batch)),
+                       dim3(XG_THREADS), 0, stream, sp, coeff, o, plan->xg, plan->ax[0].n);
+    return check_hip(hipGetLastError(), "ht_gcv_scan_exact launch");
 }

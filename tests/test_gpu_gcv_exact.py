@@ -1,0 +1,130 @@
+"""GPU parity of the exact GCV functional (ht_gcv_scan_exact, eq. gcv) against the oracle's
+dense evaluation ||T (sigma ghat)||^2 / (sum sigma)^2, through the C ABI, on the oracle's
+own coefficients and spectra (so that only the functional is compared), for every kind,
+both norms, lengths that span several chunks with a ragged tail, and the edge lengths.
+
+Tolerance: the structured form adds ||v_mid||^2, cross terms 2 Re conj(P_c) v_c, the Gram
+term and the two boundary rows, each of size at most about ||T||^2 ||v||^2 with
+v = sigma ghat, in float64 sums of n terms in a fixed order; when ||T v|| is much smaller
+than ||v|| (T_C and T_F are ill conditioned) the cancellation amplifies the rounding by
+||v||^2 / ||T v||^2.  Bound: 1e-12 (1 + ||v||^2 / ||T v||^2) relative, from the oracle's
+values."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import tikhonov as tk
+from oracle import transforms as tr
+from paper_0906_2704_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+CONFIGS = [(2, "paper", True, "C"), (2, "paper", False, "F"), (1, "paper", True, "AR"),
+           (2, "dst", True, "DST2"), (3, "dst", True, "DST3")]
+
+
+@pytest.fixture(scope="module")
+def ht():
+    from paper_0906_2704_amd import ht as _ht
+    _ht.lib()
+    return _ht
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def signals(kind, n, count, seed):
+    rng = np.random.default_rng(seed)
+    m = max(1, min(6, (n - 3) // 2))
+    h, c = synth.gaussian_psf(m, max(m / 3, 0.6), shift=0.4 if kind == "F" else 0.0)
+    Y = np.stack([synth.add_noise(rng, synth.observe_1d(synth.piecewise_poly(rng, n + 2 * m), h, c, n), 0.01)
+                  for _ in range(count)])
+    return Y, h, c
+
+
+def amplification(kind, ghat, d, s, mu):
+    T = tr.transform_matrix(kind, len(ghat)).astype(np.complex128)
+    sigma = s * s / (np.abs(d) ** 2 + mu * s * s)
+    v = sigma * ghat
+    return np.sum(np.abs(v) ** 2) / np.sum(np.abs(T @ v) ** 2)
+
+
+@pytest.mark.parametrize("degree,family,sym,kind", CONFIGS)
+@pytest.mark.parametrize("norm", ["I", "D2"])
+@pytest.mark.parametrize("n", [5, 8, 300, 1031])
+def test_exact_gcv_parity(ht, degree, family, sym, kind, norm, n):
+    if kind == "DST3" and n < 6:
+        pytest.skip("DST3 needs n >= 6")
+    print("case", kind, norm, n, flush=True)
+    Y, h, c = signals(kind, n, 3, n * 7 + degree)
+    plan = ht.Plan(n, degree, psf_symmetric=sym, family=family)
+    assert plan.kinds == [kind]
+    d = tr.blur_eigs(kind, n, h, c)
+    s = tr.smooth_eigs(kind, n, norm)
+    ghat = np.stack([tr.inverse(kind, y) for y in Y])
+    mus = synth.mu_grid(-6.0, 0.0, 64)
+    Gg, kb, mb = ht.ht_gcv_scan_exact(plan, to_dev(ghat), to_dev(d[None]), to_dev(s[None]), to_dev(mus))
+    Gg = Gg.cpu().numpy()
+    kb = kb.cpu().numpy()
+    for b in range(len(Y)):
+        Go = tk.gcv_exact_values(kind, ghat[b], d, s, mus)
+        amp = max(amplification(kind, ghat[b], d, s, mu) for mu in mus[::8])
+        err = np.max(np.abs(Gg[b] - Go) / Go)
+        print("  signal %d: max rel err %.2e (amplification %.1f)" % (b, err, amp))
+        assert err < 1e-12 * (1 + amp)
+        ko = int(np.argmin(Go))
+        assert kb[b] == ko or Go[kb[b]] <= Go[ko] * (1 + 2e-12 * (1 + amp))
+
+
+def test_exact_gcv_per_item_grids_and_contract(ht):
+    n = 64
+    Y, h, c = signals("C", n, 4, 1)
+    plan = ht.Plan(n, 2)
+    d = tr.blur_eigs("C", n, h, c)
+    s = tr.smooth_eigs("C", n, "I")
+    ghat = np.stack([tr.inverse("C", y) for y in Y])
+    grids = np.stack([synth.mu_grid(-7.0 + b, -1.0 + b, 33) for b in range(4)])
+    Gg, kb, mb = ht.ht_gcv_scan_exact(plan, to_dev(ghat), to_dev(d[None]), to_dev(s[None]), to_dev(grids))
+    for b in range(4):
+        Go = tk.gcv_exact_values("C", ghat[b], d, s, grids[b])
+        assert np.max(np.abs(Gg[b].cpu().numpy() - Go) / Go) < 1e-10
+        assert float(mb[b]) == grids[b][int(kb[b])]
+    p2 = ht.Plan((16, 16), 2)
+    with pytest.raises(ht.HTError, match="1D"):
+        ht.ht_gcv_scan_exact(p2, torch.zeros((1, 16, 16), dtype=torch.float64, device=DEV),
+                             torch.zeros(32, dtype=torch.float64, device=DEV),
+                             torch.zeros(32, dtype=torch.float64, device=DEV), to_dev(grids[0]))
+
+
+def test_exact_vs_approximate_choice_on_the_1d_workload(ht):
+    """The 1D workload (n = 256, Gaussian m = 8 sigma = 2, 1% noise, T_C) with L = I: the GPU
+    path picks mu by eq. gcv and by its approximation; the exact choices equal the
+    oracle's, and the restoration errors of both choices are reported."""
+    count = 64
+    G_host, F, h, c, _ = synth.config0_batch(count)
+    n = G_host.shape[1]
+    mus = synth.mu_grid(-6.0, 0.0, 64)
+    plan = ht.Plan(n, 2)
+    d, s = ht.ht_eigs(plan, to_dev(h), [len(h)], [c], "I")
+    g = to_dev(G_host)
+    ghat = ht.ht_transform_inv(plan, g)
+    _, ka, ma = ht.ht_gcv_scan(plan, ghat, d, s, to_dev(mus))
+    _, ke, me = ht.ht_gcv_scan_exact(plan, ghat, d, s, to_dev(mus))
+    fa = ht.ht_transform_fwd(plan, ht.ht_tikhonov_filter(plan, ghat, d, s, ma)).cpu().numpy()
+    fe = ht.ht_transform_fwd(plan, ht.ht_tikhonov_filter(plan, ghat, d, s, me)).cpu().numpy()
+    ka = ka.cpu().numpy()
+    ke = ke.cpu().numpy()
+    do = tr.blur_eigs("C", n, h, c)
+    so = np.ones(n)
+    for b in range(0, count, 8):
+        Go = tk.gcv_exact_values("C", tr.inverse("C", G_host[b]), do, so, mus)
+        ko = int(np.argmin(Go))
+        assert ke[b] == ko or Go[ke[b]] <= Go[ko] * (1 + 1e-9)
+    rre = lambda f: np.linalg.norm(f - F, axis=1) / np.linalg.norm(F, axis=1)
+    ra, re = rre(fa), rre(fe)
+    print("different choices %d / %d; mean RRE approximate %.5f exact %.5f; mean |k_a - k_e| %.2f"
+          % (int(np.sum(ka != ke)), count, ra.mean(), re.mean(), np.abs(ka - ke).mean()))
+    assert np.all(np.isfinite(re))
