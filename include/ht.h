@@ -22,8 +22,9 @@
  *     HT_OK; its array arguments may then be NULL.
  *   - Signals are real float64.  Coefficient vectors ("coeff"), filtered coefficients and
  *     eigenvalues d are float64 for the real kinds (AR, C, DST2, DST3) and interleaved
- *     complex128 (re, im) for the kind F.  Coefficients are ordered like the columns of
- *     T: [first polynomial column, the n-2 core columns, last polynomial column].
+ *     complex128 (re, im) for the kinds F and P.  Coefficients are ordered like the
+ *     columns of T: [first polynomial column, the n-2 core columns, last polynomial
+ *     column]; for the comparators P and R, the n core columns.
  *   - A batch of 1D signals is a contiguous [batch][n] array; a batch of images is
  *     [batch][n0][n1], row-major, coefficients in the same layout.
  *   - PSF convention: psf[idx] is the tap h_{idx - center}; the blur is the convolution
@@ -57,15 +58,29 @@ typedef enum {
  *                   sine columns are replaced by polynomial "bubbles" (symmetric PSF);
  *                   degree 1 is identical to the antireflective transform.            */
 /*  HT_FAMILY_PAPER_DST3: degrees 1 and 2 as HT_FAMILY_PAPER, degree 3 as HT_FAMILY_DST
- *                   (the paper defines no degree-3 transform of its own).            */
-typedef enum { HT_FAMILY_PAPER = 0, HT_FAMILY_DST = 1, HT_FAMILY_PAPER_DST3 = 2 } ht_family;
+ *                   (the paper defines no degree-3 transform of its own).
+ *  HT_FAMILY_PERIODIC / HT_FAMILY_REFLECTIVE: the comparators of Section 2.1 (degree 0):
+ *                   A_P = F^H diag(d) F (eq. permat, any PSF) and A_R = C^T diag(d) C
+ *                   (eq. refm, symmetric PSF), cores of order n with no boundary columns.
+ *                   Float64 and float32 cores; not in ragged batches or split precision. */
+typedef enum {
+    HT_FAMILY_PAPER = 0,
+    HT_FAMILY_DST = 1,
+    HT_FAMILY_PAPER_DST3 = 2,
+    HT_FAMILY_PERIODIC = 3,
+    HT_FAMILY_REFLECTIVE = 4
+} ht_family;
 
 /* Smoothing operator of eq. mintik: L = I, or the second difference with the same
  * boundary model (eq. L, L_C, L_F; in 2D the Laplacian L0 (x) I + I (x) L1).          */
 typedef enum { HT_NORM_IDENTITY = 0, HT_NORM_SECOND_DIFF = 1 } ht_norm;
 
 /* What a plan resolved to (per axis). */
-typedef enum { HT_KIND_AR = 1, HT_KIND_C = 2, HT_KIND_F = 3, HT_KIND_DST2 = 4, HT_KIND_DST3 = 5 } ht_kind;
+typedef enum {
+    HT_KIND_AR = 1, HT_KIND_C = 2, HT_KIND_F = 3, HT_KIND_DST2 = 4, HT_KIND_DST3 = 5,
+    HT_KIND_P = 6,  /* periodic: unitary DFT of order n (eq. permat)        */
+    HT_KIND_R = 7   /* reflective: orthonormal DCT-II of order n (eq. refm) */
+} ht_kind;
 
 typedef struct ht_plan ht_plan;
 
@@ -129,8 +144,11 @@ int ht_plan_precision(const ht_plan* plan);
  *   2D: psf = [h0 (psf_len[0]) | h1 (psf_len[1])], a separable PSF h0 (x) h1; outputs are
  *       the 1D factors d = [d0 (n0) | d1 (n1)], s = [s0 (n0) | s1 (n1)] with
  *       d_ij = d0_i d1_j and s_ij = s0_i + s1_j (for L = I: s0 = 1, s1 = 0).  batch = 1.
- *   psf_len, psf_center: host arrays [ndim].  Requires 2m+1 <= n-2 per axis, with
- *   m = max(center, len-1-center) (HT_ERR_PSF_TOO_WIDE otherwise).  For the real kinds
+ *   psf_len, psf_center: host arrays [ndim].  Requires 2m+1 <= n-2 per axis (2m+1 <= n
+ *   for the comparators, whose core has order n), with m = max(center, len-1-center)
+ *   (HT_ERR_PSF_TOO_WIDE otherwise).  The comparators have no polynomial columns: d is
+ *   z on the grid 2 pi k/n (P, conjugated for the convolution model) or pi k/n (R), and
+ *   s = 2 - 2 cos on the same grid.  For the real kinds
  *   the mask is used through Re z(t), i.e. its even part.                              */
 ht_status ht_eigs(const ht_plan* plan, const double* psf, const int64_t* psf_len,
                   const int64_t* psf_center, int norm, void* d, double* s, int64_t batch,
@@ -150,7 +168,7 @@ ht_status ht_eigs(const ht_plan* plan, const double* psf, const int64_t* psf_len
  *   d: device [batch][n0][n1] (complex128 for T_F plans, else float64); s: [batch][n0][n1]
  *   with s_ij = s0_i + s1_j for HT_NORM_SECOND_DIFF (0 on polynomial columns), 1 for
  *   HT_NORM_IDENTITY.  The HT_SPECTRUM_FULL layout of ht_tikhonov_filter / ht_gcv_scan.
- *   1 <= batch <= the plan's max_batch; 2m+1 <= n-2 per axis, m = max(center,
+ *   1 <= batch <= the plan's max_batch; 2m+1 <= n-2 (n for P, R) per axis, m = max(center,
  *   len-1-center) (HT_ERR_PSF_TOO_WIDE).  Uses the plan's 2D workspace: calls on one plan
  *   must be ordered on one stream, as for its transforms.                               */
 ht_status ht_eigs2d(const ht_plan* plan, const double* psf, int64_t psf_len0, int64_t psf_len1,

@@ -212,18 +212,26 @@ int resolve_kind(int degree, int sym, int family, ht_status* st) {
         *st = fail(HT_ERR_UNSUPPORTED, "HT_FAMILY_DST supports degrees 1..3");
         return 0;
     }
+    if (family == HT_FAMILY_PERIODIC || family == HT_FAMILY_REFLECTIVE) {
+        if (degree != 0) {
+            *st = fail(HT_ERR_UNSUPPORTED, "the periodic / reflective comparators have degree 0");
+            return 0;
+        }
+        if (family == HT_FAMILY_REFLECTIVE && !sym) {
+            *st = fail(HT_ERR_UNSUPPORTED, "the reflective comparator needs a symmetric PSF");
+            return 0;
+        }
+        return family == HT_FAMILY_PERIODIC ? HT_KIND_P : HT_KIND_R;
+    }
     *st = fail(HT_ERR_INVALID_ARG, "unknown family");
     return 0;
 }
 
 static ld to_ld(int64_t num, int64_t den) { return static_cast<ld>(num) / static_cast<ld>(den); }
 
-ht_status build_axis(int n, int kind, HostAxis& h) {
-    const int N = n - 2;
+// FFT length M >= 2N - 1 of a chirp-z core of order N, its split and LDS size.
+static ht_status size_core(int N, HostAxis& h) {
     Axis& a = h.ax;
-    a.n = n;
-    a.N = N;
-    a.kind = kind;
     int M = 512;
     while (M < 2 * N - 1) M <<= 1;
     h.M = M;
@@ -233,6 +241,47 @@ ht_status build_axis(int n, int kind, HostAxis& h) {
     while ((1 << a.logP) < P) ++a.logP;
     if (a.logP < MIN_LOGP || a.logP > MAX_LOGP || M > TWN)
         return fail(HT_ERR_INVALID_ARG, "internal: unsupported FFT size");
+    return HT_OK;
+}
+
+// The comparators of Section 2.1: the whole signal is the core (order n), A_P = F^H diag F
+// (the exponential core of T_F at order n) and A_R = C^T diag C (the cosine core of T_C at
+// order n); eigenvalue grid pi r / n.
+static ht_status build_comparator_axis(int n, int kind, HostAxis& h) {
+    Axis& a = h.ax;
+    a.n = n;
+    a.N = n;
+    a.kind = kind;
+    a.rank = 0;
+    ht_status st = size_core(n, h);
+    if (st != HT_OK) return st;
+    h.q.assign(n, 0.0);
+    a.q1 = 0.0;
+    for (int i = 0; i < 4; ++i) a.minv[i] = a.Gm[i] = 0.0;
+    const int core = kind == HT_KIND_P ? HT_KIND_F : HT_KIND_C;
+    make_chirp(core, false, n, h.M, h.ana);
+    make_chirp(core, true, n, h.M, h.syn);
+    a.den = n;
+    h.tcos.resize(2 * a.den);
+    h.tsin.resize(2 * a.den);
+    for (int r = 0; r < 2 * a.den; ++r) {
+        const cd w = cis_exact(r, 2LL * a.den);
+        h.tcos[r] = w.real();
+        h.tsin[r] = w.imag();
+    }
+    return HT_OK;
+}
+
+ht_status build_axis(int n, int kind, HostAxis& h) {
+    if (kind == HT_KIND_P || kind == HT_KIND_R) return build_comparator_axis(n, kind, h);
+    const int N = n - 2;
+    Axis& a = h.ax;
+    a.n = n;
+    a.N = N;
+    a.kind = kind;
+    ht_status st = size_core(N, h);
+    if (st != HT_OK) return st;
+    const int M = h.M;
     a.rank = kind == HT_KIND_DST2 ? 1 : kind == HT_KIND_DST3 ? 2 : 0;
 
     // polynomial column
@@ -600,7 +649,7 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
     p->ndim = ndim;
     p->device = device;
     p->tw = tw;
-    p->cplx = kind == HT_KIND_F ? 1 : 0;
+    p->cplx = (kind == HT_KIND_F || kind == HT_KIND_P) ? 1 : 0;
     p->max_batch = max_batch < 1 ? 1 : max_batch;
     st = upload_axes(hs, ndim, &p->arena, p->ax);
     if (st != HT_OK) {
@@ -608,7 +657,7 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
         return st;
     }
     for (int a = 0; a < ndim; ++a) p->ax[a].tw = tw;
-    if (ndim == 1) {
+    if (ndim == 1 && kind != HT_KIND_P && kind != HT_KIND_R) {  // unitary comparators: eq. gcv2 is exact
         st = build_exact_gcv(hs[0], p);
         if (st != HT_OK) {
             ht_plan_destroy(p);

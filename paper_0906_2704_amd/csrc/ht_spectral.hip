@@ -14,6 +14,8 @@ namespace ht {
 //   AR / DST:  num = i        (y = j pi / (n-1), core index j = i)          eq. jcf
 //   C:         num = i - 1    (x = (i-1) pi / (n-2))                         eq. Ac
 //   F:         num = -2(i-1)  (conj z(2 pi (i-1) / (n-2)) for the convolution model)
+//   P:         num = -2i      (conj z(2 pi i / n); no polynomial columns)            eq. permat
+//   R:         num = i        (x = i pi / n; no polynomial columns)                   eq. refm
 // evaluated by direct summation over the taps with every angle reduced exactly.
 __global__ void k_eigs(Axis ax, const double* __restrict__ psf, int64_t plen, int64_t pcenter,
                        int64_t psf_stride, int norm, double s_ident, void* d, double* s,
@@ -23,12 +25,15 @@ __global__ void k_eigs(Axis ax, const double* __restrict__ psf, int64_t plen, in
     if (i >= ax.n) return;
     const double* h = psf + b * psf_stride;
     const int n = ax.n;
-    const bool poly = (i == 0) || (i == n - 1) || (i >= 1 && i <= ax.rank);
+    const bool cmp = ax.kind == HT_KIND_P || ax.kind == HT_KIND_R;
+    const bool poly = !cmp && ((i == 0) || (i == n - 1) || (i >= 1 && i <= ax.rank));
     int64_t num;
     if (ax.kind == HT_KIND_C)
         num = i - 1;
     else if (ax.kind == HT_KIND_F)
         num = -2 * static_cast<int64_t>(i - 1);
+    else if (ax.kind == HT_KIND_P)
+        num = -2 * static_cast<int64_t>(i);
     else
         num = i;
     const int64_t period = 2 * static_cast<int64_t>(ax.den);
@@ -59,6 +64,8 @@ __global__ void k_eigs(Axis ax, const double* __restrict__ psf, int64_t plen, in
 
 // Frequency number of column i (angle pi * num / den), 0 on the polynomial columns.
 __device__ __forceinline__ int64_t freq_num(const Axis& ax, int i) {
+    if (ax.kind == HT_KIND_P) return -2 * static_cast<int64_t>(i);
+    if (ax.kind == HT_KIND_R) return i;
     const bool poly = (i == 0) || (i == ax.n - 1) || (i >= 1 && i <= ax.rank);
     if (poly) return 0;
     if (ax.kind == HT_KIND_C) return i - 1;
@@ -656,13 +663,13 @@ extern "C" ht_status ht_eigs(const ht_plan* plan, const double* psf, const int64
         const int64_t len = psf_len[a], c = psf_center[a];
         if (len < 1 || c < 0 || c >= len) return fail(HT_ERR_INVALID_ARG, "ht_eigs: bad PSF length or center");
         const int64_t m = c > len - 1 - c ? c : len - 1 - c;
-        if (2 * m + 1 > plan->ax[a].n - 2) return fail(HT_ERR_PSF_TOO_WIDE, "ht_eigs: PSF half-width m needs 2m+1 <= n-2");
+        if (2 * m + 1 > plan->ax[a].N) return fail(HT_ERR_PSF_TOO_WIDE, "ht_eigs: PSF half-width m needs 2m+1 <= n-2 (n for P, R)");
     }
     int64_t off_d = 0, off_psf = 0;
     for (int a = 0; a < plan->ndim; ++a) {
         const Axis& ax = plan->ax[a];
         const double s_ident = (plan->ndim == 2 && a == 1) ? 0.0 : 1.0;
-        const int cp = ax.kind == HT_KIND_F ? 1 : 0;
+        const int cp = plan->cplx;
         // 2D with one complex axis stores both factors as complex
         const int cp_out = plan->cplx;
         void* dd = cp_out ? static_cast<void*>(static_cast<double2*>(d) + off_d)
@@ -692,7 +699,7 @@ extern "C" ht_status ht_eigs2d(const ht_plan* plan, const double* psf, int64_t l
     for (int a = 0; a < 2; ++a) {
         if (lens[a] < 1 || cens[a] < 0 || cens[a] >= lens[a]) return fail(HT_ERR_INVALID_ARG, "ht_eigs2d: bad mask shape or center");
         const int64_t m = cens[a] > lens[a] - 1 - cens[a] ? cens[a] : lens[a] - 1 - cens[a];
-        if (2 * m + 1 > plan->ax[a].n - 2) return fail(HT_ERR_PSF_TOO_WIDE, "ht_eigs2d: PSF half-width m needs 2m+1 <= n-2 per axis");
+        if (2 * m + 1 > plan->ax[a].N) return fail(HT_ERR_PSF_TOO_WIDE, "ht_eigs2d: PSF half-width m needs 2m+1 <= n-2 (n for P, R) per axis");
     }
     const Axis& ax0 = plan->ax[0];
     const Axis& ax1 = plan->ax[1];
@@ -764,7 +771,10 @@ extern "C" ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, c
                                        double* G, int32_t* k_best, double* mu_best, int64_t batch,
                                        hipStream_t stream) {
     if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: null plan");
-    if (plan->ndim != 1 || !plan->xg_mem) return fail(HT_ERR_UNSUPPORTED, "ht_gcv_scan_exact: 1D plans only");
+    if (plan->ndim != 1) return fail(HT_ERR_UNSUPPORTED, "ht_gcv_scan_exact: 1D plans only");
+    if (!plan->xg_mem)  // periodic / reflective: T is unitary and eq. gcv2 is eq. gcv
+        return ht_gcv_scan(plan, coeff, d, s, eig_batch, HT_SPECTRUM_FULL, mu_grid, K, grid_per_item, G, k_best,
+                           mu_best, batch, stream);
     if (K < 1 || K > 1024) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: K must be in [1, 1024]");
     if (batch < 0 || batch > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: batch out of range");
     if (batch == 0) return HT_OK;

@@ -12,6 +12,8 @@
 //            y_1 / y_n from the extension of the core columns to the ghost grid points
 //            (zero for the sine core, mirror for the cosine core, periodic wrap for the
 //            exponential core) plus q_1 x_1 / q_1 x_n.
+// The comparators (periodic, reflective; Section 2.1) have no boundary columns: the whole
+// vector is the core of order n.
 #include <hip/hip_runtime.h>
 
 #include "chirp_core.h"
@@ -37,6 +39,9 @@ __device__ __forceinline__ int64_t vbase(const View& v, int64_t b) {
     return (b / v.per_img) * v.img_stride + (b % v.per_img) * v.sig_stride;
 }
 
+__device__ __forceinline__ bool is_comparator(int kind) { return kind == HT_KIND_P || kind == HT_KIND_R; }
+__device__ __forceinline__ bool is_fourier(int kind) { return kind == HT_KIND_F || kind == HT_KIND_P; }
+
 // The core's tables for the element type C (float64 or float32 copies).
 template <class C>
 __device__ __forceinline__ const ChirpT<C>& core_of(const Axis& ax, bool analysis);
@@ -61,12 +66,15 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View i
     const int64_t b = blockIdx.x;
     const int n = ax.n, N = ax.N;
     const int64_t ib = vbase(in, b), ob = vbase(out, b);
+    const bool cmp = is_comparator(ax.kind);
+    const int off = cmp ? 0 : 1;  // position of core entry 0 in the vectors
 
     // boundary coefficients (float64 closed form)
     const double2 y0 = vload(in, ib, 0), y1 = vload(in, ib, 1);
     const double2 yN = vload(in, ib, n - 2), yL = vload(in, ib, n - 1);
-    double2 x1, xn;
-    if (ax.kind == HT_KIND_C || ax.kind == HT_KIND_F) {
+    double2 x1 = make_double2(0.0, 0.0), xn = x1;
+    if (cmp) {
+    } else if (ax.kind == HT_KIND_C || ax.kind == HT_KIND_F) {
         const double2 r1 = ax.kind == HT_KIND_C ? csub(y0, y1) : csub(y0, yN);
         const double2 r2 = ax.kind == HT_KIND_C ? csub(yL, yN) : csub(yL, y1);
         x1 = make_double2(ax.minv[0] * r1.x + ax.minv[1] * r2.x, ax.minv[0] * r1.y + ax.minv[1] * r2.y);
@@ -78,15 +86,17 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View i
     }
     // interior correction r_j = y_{j+1} - q^_j x_1 - (J q^)_j x_n, then the core analysis
     auto in_fn = [&](int, int j) {
-        double2 r = vload(in, ib, j + 1);
-        const double qa = ax.q[j + 1], qb = ax.q[N - j];
-        r.x = r.x - qa * x1.x - qb * xn.x;
-        r.y = r.y - qa * x1.y - qb * xn.y;
+        double2 r = vload(in, ib, j + off);
+        if (!cmp) {
+            const double qa = ax.q[j + 1], qb = ax.q[N - j];
+            r.x = r.x - qa * x1.x - qb * xn.x;
+            r.y = r.y - qa * x1.y - qb * xn.y;
+        }
         return r;
     };
-    auto park = [&](int j, double2 y) { vstore(out, ob, j + 1, y); };
-    auto unpark = [&](int j) { return vload(out, ob, j + 1); };
-    const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ax.ana.mode;
+    auto park = [&](int j, double2 y) { vstore(out, ob, j + off, y); };
+    auto unpark = [&](int j) { return vload(out, ob, j + off); };
+    const int mode = (is_fourier(ax.kind) && out.cplx) ? MODE_CPLX : ax.ana.mode;
     double2 acc[SL];
     chirp_core<LOGP, S, SL>(acc, core_of<C>(ax, true), mode, N, lds, tw, in_fn, park, unpark);
     if (ax.rank > 0) {  // DST family: x_mid -= U (E^T K)^{-1} E^T x_mid
@@ -114,9 +124,9 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View i
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;
-        if (j < N) vstore(out, ob, j + 1, acc[k]);
+        if (j < N) vstore(out, ob, j + off, acc[k]);
     }
-    if (tid == 0) {
+    if (tid == 0 && !cmp) {
         vstore(out, ob, 0, x1);
         vstore(out, ob, n - 1, xn);
     }
@@ -133,21 +143,26 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View i
     const int64_t b = blockIdx.x;
     const int n = ax.n, N = ax.N;
     const int64_t ib = vbase(in, b), ob = vbase(out, b);
+    const bool cmp = is_comparator(ax.kind);
+    const int off = cmp ? 0 : 1;  // position of core entry 0 in the vectors
 
-    const double2 x1 = vload(in, ib, 0), xn = vload(in, ib, n - 1);
-    const double2 beta0 = ax.rank > 0 ? vload(in, ib, 1) : make_double2(0.0, 0.0);
-    const double2 beta1 = ax.rank > 1 ? vload(in, ib, 2) : make_double2(0.0, 0.0);
+    const double2 zero = make_double2(0.0, 0.0);
+    const double2 x1 = cmp ? zero : vload(in, ib, 0), xn = cmp ? zero : vload(in, ib, n - 1);
+    const double2 beta0 = ax.rank > 0 ? vload(in, ib, 1) : zero;
+    const double2 beta1 = ax.rank > 1 ? vload(in, ib, 2) : zero;
     // the replaced (bubble) columns are added explicitly, not through the sine core
-    auto in_fn = [&](int, int j) { return j >= ax.rank ? vload(in, ib, j + 1) : make_double2(0.0, 0.0); };
-    auto park = [&](int j, double2 y) { vstore(out, ob, j + 1, y); };
-    auto unpark = [&](int j) { return vload(out, ob, j + 1); };
-    const int mode = (ax.kind == HT_KIND_F && out.cplx) ? MODE_CPLX : ax.syn.mode;
+    auto in_fn = [&](int, int j) { return j >= ax.rank ? vload(in, ib, j + off) : zero; };
+    auto park = [&](int j, double2 y) { vstore(out, ob, j + off, y); };
+    auto unpark = [&](int j) { return vload(out, ob, j + off); };
+    const int mode = (is_fourier(ax.kind) && out.cplx) ? MODE_CPLX : ax.syn.mode;
     double2 u[SL];
     chirp_core<LOGP, S, SL>(u, core_of<C>(ax, false), mode, N, lds, tw, in_fn, park, unpark);
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;
-        if (j < N) {
+        if (j < N && cmp) {
+            vstore(out, ob, j, u[k]);
+        } else if (j < N) {
             const double qa = ax.q[j + 1], qb = ax.q[N - j];
             double2 y = make_double2(u[k].x + qa * x1.x + qb * xn.x, u[k].y + qa * x1.y + qb * xn.y);
             if (ax.rank > 0) {
@@ -160,7 +175,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View i
                     y.y += b1 * beta1.y;
                 }
             }
-            vstore(out, ob, j + 1, y);
+            vstore(out, ob, j + off, y);
             // boundary rows: extension of the core columns to the two ghost grid points
             if (ax.kind == HT_KIND_C || ax.kind == HT_KIND_F) {
                 const bool first_src = ax.kind == HT_KIND_C ? (j == 0) : (j == N - 1);
@@ -170,7 +185,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View i
             }
         }
     }
-    if (tid == 0 && !(ax.kind == HT_KIND_C || ax.kind == HT_KIND_F)) {
+    if (tid == 0 && !cmp && !(ax.kind == HT_KIND_C || ax.kind == HT_KIND_F)) {
         vstore(out, ob, 0, cscale(x1, ax.q1));
         vstore(out, ob, n - 1, cscale(xn, ax.q1));
     }
