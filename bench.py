@@ -66,17 +66,20 @@ class Uniform1D:
 
     stages = ["eigs", "transform_inv", "gcv_scan", "tikhonov_filter", "transform_fwd"]
 
-    def __init__(self, torch, ht, synth, batch, n=256, degree=2, gcv="approx"):
+    def __init__(self, torch, ht, synth, batch, n=256, degree=2, gcv="approx", family="paper"):
         self.torch, self.ht, self.synth = torch, ht, synth
-        self.batch, self.n, self.degree, self.gcv = batch, n, degree, gcv
-        self.name = "1d_uniform_n%d_d%d_x%d%s" % (n, degree, batch, "_exact_gcv" if gcv == "exact" else "")
+        if family in ("periodic", "reflective"):
+            degree = 0
+        self.batch, self.n, self.degree, self.gcv, self.family = batch, n, degree, gcv, family
+        bc = "" if family == "paper" else "_" + family
+        self.name = "1d_uniform_n%d_d%d_x%d%s%s" % (n, degree, batch, bc, "_exact_gcv" if gcv == "exact" else "")
 
     def setup(self):
         torch, ht, synth = self.torch, self.ht, self.synth
         G, F, h, c, mus = synth.config0_batch(self.batch)
         self.G_host, self.h, self.c, self.mus_host = G, h, c, mus
         dev = "cuda"
-        self.plan = ht.Plan(self.n, self.degree, psf_symmetric=True)
+        self.plan = ht.Plan(self.n, self.degree, psf_symmetric=True, family=self.family)
         self.kind = self.plan.kinds[0]
         self.g = torch.tensor(G, device=dev)
         self.psf = torch.tensor(h, device=dev)
@@ -115,8 +118,10 @@ class Uniform1D:
         B, n, K = self.batch, self.n, len(self.mus_host)
         cb = 16 if self.plan.is_complex else 8
         # the exact functional adds one fused multiply-add per (element, mu, fixed vector):
-        # 4 vectors for T_C (two boundary columns, two ghost rows)
-        per_pair = GCV_FLOPS_PER_PAIR + (2 * 4 if self.gcv == "exact" else 0)
+        # 4 vectors for T_C (two boundary columns, two ghost rows); none for the unitary
+        # comparators, where it is the same scan
+        extra = 4 if self.kind == "C" else 0
+        per_pair = GCV_FLOPS_PER_PAIR + (2 * extra if self.gcv == "exact" else 0)
         return {
             "eigs": ("hbm", (len(self.h) * 8 + n * (cb + 8))),
             "transform_inv": ("hbm", B * n * (8 + cb)),
@@ -823,6 +828,8 @@ def main():
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x3"], help="mixed: core arithmetic")
     ap.add_argument("--gcv", default="approx", choices=["approx", "exact"],
                     help="uniform: the eq. mugcv scan or the exact eq. gcv functional")
+    ap.add_argument("--bc", default="paper", choices=["paper", "periodic", "reflective"],
+                    help="uniform: T_C (degree 2) or a comparator boundary condition")
     ap.add_argument("--train", type=int, default=200000, help="learned: training problems")
     ap.add_argument("--epochs", type=int, default=25, help="learned: training epochs")
     ap.add_argument("--learned-path", default="two-pass", choices=["two-pass", "fused"],
@@ -862,7 +869,7 @@ def main():
     elif args.workload == "ragged":
         wl = Ragged1D(torch, ht, synth, args.batch or 4096, graph=not args.no_graph, autotune=not args.no_autotune)
     else:
-        wl = Uniform1D(torch, ht, synth, args.batch or 65536, gcv=args.gcv)
+        wl = Uniform1D(torch, ht, synth, args.batch or 65536, gcv=args.gcv, family=args.bc)
     print("setup %s" % wl.name, file=sys.stderr, flush=True)
     wl.setup()
     if args.copy_calibration_mib > 0:
