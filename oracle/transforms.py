@@ -18,6 +18,13 @@ reduced exactly as an integer multiple of pi before the trigonometric call:
              boundary conditions; this construction is the reading adopted for degree 3)
 * ``"P"``, ``"R"``  periodic F^(n) and reflective C^(n) bases of order n (eqs. permat,
              refm), used as comparators and to pin the GCV formula.
+* ``"F3"``   degree 3 for any PSF (not in the paper; the reading adopted here): T_F with
+             its conjugate pair of frequency +-1 (columns 3 and n-1, 1-based) replaced by
+             two real columns, sqrt(2) cos x / sqrt(N) (the pair's real part) and the
+             unit-norm samples of the cubic x (x - pi)(x - 2 pi) on the extended grid, so
+             that the columns with eigenvalue z(0) span all cubics.  The cosine column
+             carries Re z(x_1) (the part of the mask even about its centre, as for the real
+             kinds), the cubic z(0).
 
 A kind's matrix T has the eigenvectors of the blurring matrix A = T diag(d) T^{-1} as
 columns; ``blur_eigs`` returns d and ``smooth_eigs`` the spectrum s of the smoothing
@@ -43,13 +50,13 @@ LD = np.longdouble
 CLD = np.clongdouble
 PI = 4 * np.arctan(LD(1))
 
-KINDS = ("AR", "C", "F", "DST2", "DST3", "P", "R")
-COMPLEX_KINDS = ("F", "P")
+KINDS = ("AR", "C", "F", "DST2", "DST3", "P", "R", "F3")
+COMPLEX_KINDS = ("F", "P", "F3")
 
 
 def degree_of(kind):
     """Degree of the polynomials the model preserves with eigenvalue z(0)."""
-    return {"AR": 1, "C": 2, "F": 2, "DST2": 2, "DST3": 3, "P": 0, "R": 0}[kind]
+    return {"AR": 1, "C": 2, "F": 2, "DST2": 2, "DST3": 3, "P": 0, "R": 0, "F3": 3}[kind]
 
 
 def is_complex(kind):
@@ -127,11 +134,28 @@ def dst_bubbles(n, degree):
 # dense transform matrices
 # ----------------------------------------------------------------------------------------
 
+def cubic_f3(n):
+    """Unit-norm samples of x (x - pi)(x - 2 pi) at the T_F grid x_r = (r-2) 2 pi/(n-2),
+    r = 1..n (exact rationals in units of pi)."""
+    N = n - 2
+    vals = []
+    for r in range(1, n + 1):
+        t = Fraction(2 * (r - 2), N)  # x / pi
+        v = t * (t - 1) * (t - 2)
+        vals.append(LD(v.numerator) / LD(v.denominator))
+    return _unit(np.array(vals, dtype=LD))
+
+
 @lru_cache(maxsize=16)
 def transform_matrix(kind, n):
-    """Dense n x n matrix of the kind's transform, long double (complex for F, P)."""
+    """Dense n x n matrix of the kind's transform, long double (complex for F, P, F3)."""
     if kind not in KINDS:
         raise ValueError(kind)
+    if kind == "F3":
+        T = transform_matrix("F", n).copy()
+        T[:, 2] = np.sqrt(LD(2)) * T[:, 2].real   # (e^{ix} + e^{-ix}) / sqrt(2 N)
+        T[:, n - 2] = cubic_f3(n)
+        return T
     if kind in ("P", "R"):
         return _comparator_matrix(kind, n)
     if n < 5:
@@ -209,6 +233,7 @@ def eigen_grid(kind, n):
     DSTd as AR, with columns 2..d also carrying z(0) (the replaced columns)
     P    x_i = 2 (i-1) pi / n                                               (eq. permat)
     R    x_i = (i-1) pi / n                                                 (eq. refm)
+    F3   as F, with column n-1 (the cubic) also carrying z(0)
     """
     i = np.arange(1, n + 1, dtype=np.int64)
     poly = np.zeros(n, dtype=bool)
@@ -223,6 +248,8 @@ def eigen_grid(kind, n):
         num, den = i - 2, n - 2
     else:
         num, den = 2 * (i - 2), n - 2
+        if kind == "F3":
+            poly[n - 2] = True
     num = np.where(poly, 0, num)
     return poly, num, den
 
@@ -264,9 +291,11 @@ def blur_eigs(kind, n, h, center):
     if kind not in COMPLEX_KINDS and not psf_is_symmetric(h, center):
         raise ValueError("kind %s needs a symmetric PSF" % kind)
     poly, num, den = eigen_grid(kind, n)
-    if kind in ("F", "P"):
+    if kind in ("F", "P", "F3"):
         num = -num  # R4: exponential column e^{ikx} carries z(-kx) under convolution
     z = symbol(h, center, num, den)
+    if kind == "F3":
+        z[2] = z[2].real  # the cosine column: Re z(x_1)
     z[poly] = np.sum(np.asarray(h, dtype=np.float64).astype(LD))  # R7: z(0) = sum h_j
     if kind in COMPLEX_KINDS:
         return z.astype(np.complex128)
