@@ -70,6 +70,8 @@ class Uniform1D:
         self.torch, self.ht, self.synth = torch, ht, synth
         if family in ("periodic", "reflective"):
             degree = 0
+        if family == "f3":   # degree 3 for any PSF: T_F with a cosine and a cubic column
+            degree = 3
         self.batch, self.n, self.degree, self.gcv, self.family = batch, n, degree, gcv, family
         bc = "" if family == "paper" else "_" + family
         self.name = "1d_uniform_n%d_d%d_x%d%s%s" % (n, degree, batch, bc, "_exact_gcv" if gcv == "exact" else "")
@@ -79,7 +81,10 @@ class Uniform1D:
         G, F, h, c, mus = synth.config0_batch(self.batch)
         self.G_host, self.h, self.c, self.mus_host = G, h, c, mus
         dev = "cuda"
-        self.plan = ht.Plan(self.n, self.degree, psf_symmetric=True, family=self.family)
+        if self.family == "f3":
+            self.plan = ht.Plan(self.n, 3, psf_symmetric=False, family="paper+dst3")
+        else:
+            self.plan = ht.Plan(self.n, self.degree, psf_symmetric=True, family=self.family)
         self.kind = self.plan.kinds[0]
         self.g = torch.tensor(G, device=dev)
         self.psf = torch.tensor(h, device=dev)
@@ -828,8 +833,9 @@ def main():
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x3"], help="mixed: core arithmetic")
     ap.add_argument("--gcv", default="approx", choices=["approx", "exact"],
                     help="uniform: the eq. mugcv scan or the exact eq. gcv functional")
-    ap.add_argument("--bc", default="paper", choices=["paper", "periodic", "reflective"],
-                    help="uniform: T_C (degree 2) or a comparator boundary condition")
+    ap.add_argument("--bc", default="paper", choices=["paper", "periodic", "reflective", "f3"],
+                    help="uniform: T_C (degree 2), a comparator boundary condition, or degree 3 "
+                         "for any PSF")
     ap.add_argument("--train", type=int, default=200000, help="learned: training problems")
     ap.add_argument("--epochs", type=int, default=25, help="learned: training epochs")
     ap.add_argument("--learned-path", default="two-pass", choices=["two-pass", "fused"],

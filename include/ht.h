@@ -58,7 +58,8 @@ typedef enum {
  *                   sine columns are replaced by polynomial "bubbles" (symmetric PSF);
  *                   degree 1 is identical to the antireflective transform.            */
 /*  HT_FAMILY_PAPER_DST3: degrees 1 and 2 as HT_FAMILY_PAPER, degree 3 as HT_FAMILY_DST
- *                   (the paper defines no degree-3 transform of its own).
+ *                   for a symmetric PSF and as HT_KIND_F3 otherwise (the paper defines
+ *                   no degree-3 transform of its own).
  *  HT_FAMILY_PERIODIC / HT_FAMILY_REFLECTIVE: the comparators of Section 2.1 (degree 0):
  *                   A_P = F^H diag(d) F (eq. permat, any PSF) and A_R = C^T diag(d) C
  *                   (eq. refm, symmetric PSF), cores of order n with no boundary columns.
@@ -79,7 +80,13 @@ typedef enum { HT_NORM_IDENTITY = 0, HT_NORM_SECOND_DIFF = 1 } ht_norm;
 typedef enum {
     HT_KIND_AR = 1, HT_KIND_C = 2, HT_KIND_F = 3, HT_KIND_DST2 = 4, HT_KIND_DST3 = 5,
     HT_KIND_P = 6,  /* periodic: unitary DFT of order n (eq. permat)        */
-    HT_KIND_R = 7   /* reflective: orthonormal DCT-II of order n (eq. refm) */
+    HT_KIND_R = 7,  /* reflective: orthonormal DCT-II of order n (eq. refm) */
+    HT_KIND_F3 = 8  /* degree 3, any PSF: T_F with its frequency +-1 pair replaced by the
+                       real columns sqrt(2/N) cos x (eigenvalue Re z(x_1)) and the unit-norm
+                       cubic x (x - pi)(x - 2 pi) (eigenvalue z(0)); complex coefficients,
+                       real on those two columns for real signals; inverse = the T_F
+                       inverse plus a rank-2 float64 correction.  Not in ragged batches,
+                       split precision, ht_eigs2d or ht_gcv_scan_exact.                */
 } ht_kind;
 
 typedef struct ht_plan ht_plan;

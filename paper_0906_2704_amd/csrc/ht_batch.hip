@@ -768,7 +768,7 @@ extern "C" ht_status ht_batch_create(int64_t count, const int64_t* n, const int*
         ht_status st;
         kind[b] = resolve_kind(degree[b], psf_symmetric[b], family, &st);
         if (st != HT_OK) return st;
-        if (kind[b] == HT_KIND_F || kind[b] == HT_KIND_P || kind[b] == HT_KIND_R)
+        if (kind[b] == HT_KIND_F || kind[b] == HT_KIND_P || kind[b] == HT_KIND_R || kind[b] == HT_KIND_F3)
             return fail(HT_ERR_UNSUPPORTED,
                         "ht_batch_create: ragged batches take the boundary transforms of real kinds (AR, C, DST)");
         const int64_t len = psf_len[b], c = psf_center[b];

@@ -1070,7 +1070,8 @@ extern "C" ht_status ht_plan_set_precision(ht_plan* p, int precision) {
     if (precision != HT_PRECISION_F64) {
         if (precision != HT_PRECISION_F32)
             for (int a = 0; a < p->ndim; ++a)
-                if (p->ax[a].kind == HT_KIND_F || p->ax[a].kind == HT_KIND_P || p->ax[a].kind == HT_KIND_R)
+                if (p->ax[a].kind == HT_KIND_F || p->ax[a].kind == HT_KIND_P || p->ax[a].kind == HT_KIND_R ||
+                    p->ax[a].kind == HT_KIND_F3)
                     return fail(HT_ERR_UNSUPPORTED,
                                 "ht_plan_set_precision: the split-precision core needs a real boundary transform "
                                 "(not T_F or a comparator)");

@@ -57,6 +57,13 @@ struct Axis {
     const double* tcos;   // [2 den] cos(pi r / den)
     const double* tsin;   // [2 den] sin(pi r / den)
     const double2* tw;    // the device's FFT twiddle table
+    // degree 3 for any PSF (kind F3): the T_F inverse corrected by
+    //   a = Vi (x[2], x[n-2]),  x[2] = a0, x[n-2] = a1, x[j] -= f3v[j] a1 elsewhere,
+    // with f3v = T_F^{-1} (cubic column) and Vi the inverse of rows {2, n-2} of
+    // [ (e_2 + e_{n-2})/sqrt 2 | f3v ]; the forward adds f3b[0] x[2] + f3b[1] x[n-2].
+    const double2* f3v;   // [n]
+    const double* f3b;    // [2][n]: cosine column, cubic column (all n rows)
+    double2 f3vi[4];      // Vi, row-major
 };
 
 // Strided view of a batch of 1D signals: signal b lives at

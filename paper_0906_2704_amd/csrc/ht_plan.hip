@@ -194,7 +194,10 @@ static std::vector<double> host_core(const HostChirp& hc, const std::vector<doub
 
 int resolve_kind(int degree, int sym, int family, ht_status* st) {
     *st = HT_OK;
-    if (family == HT_FAMILY_PAPER_DST3 && degree == 3) family = HT_FAMILY_DST;
+    if (family == HT_FAMILY_PAPER_DST3 && degree == 3) {
+        if (!sym) return HT_KIND_F3;
+        family = HT_FAMILY_DST;
+    }
     if (family == HT_FAMILY_PAPER || family == HT_FAMILY_PAPER_DST3) {
         if (degree == 1) {
             if (!sym) *st = fail(HT_ERR_UNSUPPORTED, "degree 1 (antireflective) needs a symmetric PSF");
@@ -272,8 +275,12 @@ static ht_status build_comparator_axis(int n, int kind, HostAxis& h) {
     return HT_OK;
 }
 
-ht_status build_axis(int n, int kind, HostAxis& h) {
-    if (kind == HT_KIND_P || kind == HT_KIND_R) return build_comparator_axis(n, kind, h);
+static ht_status build_f3_tables(HostAxis& h);
+
+ht_status build_axis(int n, int kind_in, HostAxis& h) {
+    if (kind_in == HT_KIND_P || kind_in == HT_KIND_R) return build_comparator_axis(n, kind_in, h);
+    // F3 is T_F plus a rank-2 modification: every T_F table, then its own
+    const int kind = kind_in == HT_KIND_F3 ? HT_KIND_F : kind_in;
     const int N = n - 2;
     Axis& a = h.ax;
     a.n = n;
@@ -370,6 +377,61 @@ ht_status build_axis(int n, int kind, HostAxis& h) {
         h.tcos[r] = w.real();
         h.tsin[r] = w.imag();
     }
+    if (kind_in == HT_KIND_F3) {
+        a.kind = HT_KIND_F3;
+        return build_f3_tables(h);
+    }
+    return HT_OK;
+}
+
+// T_F^{-1} y for a real vector y on the host (the kernel's steps: the 2x2 boundary
+// solve, the interior correction, the DFT analysis core).
+static std::vector<cd> host_inverse_f(const HostAxis& h, const std::vector<double>& y) {
+    const Axis& a = h.ax;
+    const int n = a.n, N = a.N;
+    const double r1 = y[0] - y[n - 2], r2 = y[n - 1] - y[1];
+    const double x1 = a.minv[0] * r1 + a.minv[1] * r2, xn = a.minv[2] * r1 + a.minv[3] * r2;
+    std::vector<double> r(N);
+    for (int j = 0; j < N; ++j) r[j] = y[j + 1] - h.q[j + 1] * x1 - h.q[N - j] * xn;
+    const std::vector<cd> core = host_core_c(h.ana, r, h.M);
+    std::vector<cd> x(n);
+    x[0] = cd(x1, 0.0);
+    x[n - 1] = cd(xn, 0.0);
+    for (int j = 0; j < N; ++j) x[j + 1] = core[j];
+    return x;
+}
+
+// Tables of the degree-3 transform for any PSF (columns 2 and n-2 of T_F replaced by the
+// cosine column and the cubic x (x - pi)(x - 2 pi) on the extended grid of T_F).
+static ht_status build_f3_tables(HostAxis& h) {
+    Axis& a = h.ax;
+    const int n = a.n, N = a.N;
+    if (N < 3) return fail(HT_ERR_UNSUPPORTED, "degree 3 for a nonsymmetric PSF needs n >= 5");
+    h.f3b.assign(2 * static_cast<size_t>(n), 0.0);
+    std::vector<ld> cub(n);
+    ld nrm = 0.0L;
+    for (int r = 0; r < n; ++r) {
+        // x_r / pi = 2 (r - 1) / N for 0-based r (the grid point of row r + 1)
+        const ld t = to_ld(2LL * (r - 1), N);
+        cub[r] = t * (t - 1.0L) * (t - 2.0L);
+        nrm += cub[r] * cub[r];
+        const cd w = cis_exact(static_cast<int64_t>(r - 1), N, sqrtl(2.0L / N));  // sqrt(2/N) e^{i x_r}
+        h.f3b[r] = w.real();
+    }
+    nrm = sqrtl(nrm);
+    std::vector<double> cubic(n);
+    for (int r = 0; r < n; ++r) {
+        cubic[r] = static_cast<double>(cub[r] / nrm);
+        h.f3b[n + r] = cubic[r];
+    }
+    h.f3v = host_inverse_f(h, cubic);
+    // V_E = [[1/sqrt2, v_2], [1/sqrt2, v_{n-2}]]
+    const cd s2(1.0 / std::sqrt(2.0), 0.0);
+    const cd v2 = h.f3v[2], vm = h.f3v[n - 2];
+    const cd det = s2 * vm - v2 * s2;
+    if (std::abs(det) < 1e-300) return fail(HT_ERR_SINGULAR, "degree-3 correction is singular");
+    const cd vi[4] = {vm / det, -v2 / det, -s2 / det, s2 / det};
+    for (int k = 0; k < 4; ++k) a.f3vi[k] = make_double2(vi[k].real(), vi[k].imag());
     return HT_OK;
 }
 
@@ -464,11 +526,13 @@ ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* a
         bytes += (nbytes + 255) & ~static_cast<size_t>(255);
         return off;
     };
-    struct Offs { size_t q, bub, U, tcos, tsin, apre, apost, aB, spre, spost, sB; };
+    struct Offs { size_t q, bub, U, tcos, tsin, apre, apost, aB, spre, spost, sB, f3v, f3b; };
     std::vector<Offs> o(nax);
     for (int64_t a = 0; a < nax; ++a) {
         const HostAxis& h = hs[a];
         const size_t N = h.ax.N;
+        o[a].f3v = reserve(sizeof(double2) * (h.f3v.size() + 1));
+        o[a].f3b = reserve(sizeof(double) * (h.f3b.size() + 1));
         o[a].q = reserve(sizeof(double) * h.q.size());
         o[a].bub = reserve(sizeof(double) * (h.bub.size() + 1));
         o[a].U = reserve(sizeof(double) * (h.U.size() + 1));
@@ -507,6 +571,8 @@ ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* a
     for (int64_t a = 0; a < nax; ++a) {
         const HostAxis& h = hs[a];
         put(o[a].q, h.q.data(), sizeof(double) * h.q.size());
+        putc(o[a].f3v, h.f3v);
+        put(o[a].f3b, h.f3b.data(), sizeof(double) * h.f3b.size());
         put(o[a].bub, h.bub.data(), sizeof(double) * h.bub.size());
         put(o[a].U, h.U.data(), sizeof(double) * h.U.size());
         put(o[a].tcos, h.tcos.data(), sizeof(double) * h.tcos.size());
@@ -528,6 +594,8 @@ ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* a
     for (int64_t a = 0; a < nax; ++a) {
         Axis ax = hs[a].ax;
         ax.q = reinterpret_cast<const double*>(dev + o[a].q);
+        ax.f3v = reinterpret_cast<const double2*>(dev + o[a].f3v);
+        ax.f3b = reinterpret_cast<const double*>(dev + o[a].f3b);
         ax.bub = reinterpret_cast<const double*>(dev + o[a].bub);
         ax.U = reinterpret_cast<const double*>(dev + o[a].U);
         ax.tcos = reinterpret_cast<const double*>(dev + o[a].tcos);
@@ -649,7 +717,7 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
     p->ndim = ndim;
     p->device = device;
     p->tw = tw;
-    p->cplx = (kind == HT_KIND_F || kind == HT_KIND_P) ? 1 : 0;
+    p->cplx = (kind == HT_KIND_F || kind == HT_KIND_P || kind == HT_KIND_F3) ? 1 : 0;
     p->max_batch = max_batch < 1 ? 1 : max_batch;
     st = upload_axes(hs, ndim, &p->arena, p->ax);
     if (st != HT_OK) {
@@ -657,7 +725,7 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
         return st;
     }
     for (int a = 0; a < ndim; ++a) p->ax[a].tw = tw;
-    if (ndim == 1 && kind != HT_KIND_P && kind != HT_KIND_R) {  // unitary comparators: eq. gcv2 is exact
+    if (ndim == 1 && kind != HT_KIND_P && kind != HT_KIND_R && kind != HT_KIND_F3) {  // P, R: eq. gcv2 is exact
         st = build_exact_gcv(hs[0], p);
         if (st != HT_OK) {
             ht_plan_destroy(p);

@@ -16,6 +16,7 @@ namespace ht {
 //   F:         num = -2(i-1)  (conj z(2 pi (i-1) / (n-2)) for the convolution model)
 //   P:         num = -2i      (conj z(2 pi i / n); no polynomial columns)            eq. permat
 //   R:         num = i        (x = i pi / n; no polynomial columns)                   eq. refm
+//   F3:        as F, with the cubic column n-2 polynomial and Re z on the cosine column 2
 // evaluated by direct summation over the taps with every angle reduced exactly.
 __global__ void k_eigs(Axis ax, const double* __restrict__ psf, int64_t plen, int64_t pcenter,
                        int64_t psf_stride, int norm, double s_ident, void* d, double* s,
@@ -26,11 +27,12 @@ __global__ void k_eigs(Axis ax, const double* __restrict__ psf, int64_t plen, in
     const double* h = psf + b * psf_stride;
     const int n = ax.n;
     const bool cmp = ax.kind == HT_KIND_P || ax.kind == HT_KIND_R;
-    const bool poly = !cmp && ((i == 0) || (i == n - 1) || (i >= 1 && i <= ax.rank));
+    const bool f3 = ax.kind == HT_KIND_F3;
+    const bool poly = !cmp && ((i == 0) || (i == n - 1) || (i >= 1 && i <= ax.rank) || (f3 && i == n - 2));
     int64_t num;
     if (ax.kind == HT_KIND_C)
         num = i - 1;
-    else if (ax.kind == HT_KIND_F)
+    else if (ax.kind == HT_KIND_F || f3)
         num = -2 * static_cast<int64_t>(i - 1);
     else if (ax.kind == HT_KIND_P)
         num = -2 * static_cast<int64_t>(i);
@@ -48,6 +50,7 @@ __global__ void k_eigs(Axis ax, const double* __restrict__ psf, int64_t plen, in
             dr = fma(h[k], ax.tcos[r], dr);
             di = fma(h[k], ax.tsin[r], di);
         }
+        if (f3 && i == 2) di = 0.0;  // the cosine column: Re z(x_1)
         int64_t r = num % period;
         if (r < 0) r += period;
         sv = norm == HT_NORM_IDENTITY ? s_ident : 2.0 - 2.0 * ax.tcos[r];
@@ -691,6 +694,8 @@ extern "C" ht_status ht_eigs2d(const ht_plan* plan, const double* psf, int64_t l
                                hipStream_t stream) {
     if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_eigs2d: null plan");
     if (plan->ndim != 2) return fail(HT_ERR_INVALID_ARG, "ht_eigs2d: needs a 2D plan");
+    if (plan->ax[0].kind == HT_KIND_F3 || plan->ax[1].kind == HT_KIND_F3)
+        return fail(HT_ERR_UNSUPPORTED, "ht_eigs2d: not defined for the degree-3 Fourier kind (use separable factors)");
     if (norm != HT_NORM_IDENTITY && norm != HT_NORM_SECOND_DIFF) return fail(HT_ERR_INVALID_ARG, "ht_eigs2d: bad norm");
     if (batch < 0 || batch > plan->max_batch) return fail(HT_ERR_INVALID_ARG, "ht_eigs2d: batch must be in [0, max_batch]");
     if (batch == 0) return HT_OK;
@@ -772,6 +777,7 @@ extern "C" ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, c
                                        hipStream_t stream) {
     if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: null plan");
     if (plan->ndim != 1) return fail(HT_ERR_UNSUPPORTED, "ht_gcv_scan_exact: 1D plans only");
+    if (plan->ax[0].kind == HT_KIND_F3) return fail(HT_ERR_UNSUPPORTED, "ht_gcv_scan_exact: not for the degree-3 Fourier kind");
     if (!plan->xg_mem)  // periodic / reflective: T is unitary and eq. gcv2 is eq. gcv
         return ht_gcv_scan(plan, coeff, d, s, eig_batch, HT_SPECTRUM_FULL, mu_grid, K, grid_per_item, G, k_best,
                            mu_best, batch, stream);

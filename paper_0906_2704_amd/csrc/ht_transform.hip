@@ -40,7 +40,9 @@ __device__ __forceinline__ int64_t vbase(const View& v, int64_t b) {
 }
 
 __device__ __forceinline__ bool is_comparator(int kind) { return kind == HT_KIND_P || kind == HT_KIND_R; }
-__device__ __forceinline__ bool is_fourier(int kind) { return kind == HT_KIND_F || kind == HT_KIND_P; }
+__device__ __forceinline__ bool is_fourier(int kind) { return kind == HT_KIND_F || kind == HT_KIND_P || kind == HT_KIND_F3; }
+// the kind whose boundary columns and core a kind uses (F3 is T_F plus a rank-2 change)
+__device__ __forceinline__ int base_kind(int kind) { return kind == HT_KIND_F3 ? HT_KIND_F : kind; }
 
 // The core's tables for the element type C (float64 or float32 copies).
 template <class C>
@@ -68,15 +70,16 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View i
     const int64_t ib = vbase(in, b), ob = vbase(out, b);
     const bool cmp = is_comparator(ax.kind);
     const int off = cmp ? 0 : 1;  // position of core entry 0 in the vectors
+    const int kb = base_kind(ax.kind);
 
     // boundary coefficients (float64 closed form)
     const double2 y0 = vload(in, ib, 0), y1 = vload(in, ib, 1);
     const double2 yN = vload(in, ib, n - 2), yL = vload(in, ib, n - 1);
     double2 x1 = make_double2(0.0, 0.0), xn = x1;
     if (cmp) {
-    } else if (ax.kind == HT_KIND_C || ax.kind == HT_KIND_F) {
-        const double2 r1 = ax.kind == HT_KIND_C ? csub(y0, y1) : csub(y0, yN);
-        const double2 r2 = ax.kind == HT_KIND_C ? csub(yL, yN) : csub(yL, y1);
+    } else if (kb == HT_KIND_C || kb == HT_KIND_F) {
+        const double2 r1 = kb == HT_KIND_C ? csub(y0, y1) : csub(y0, yN);
+        const double2 r2 = kb == HT_KIND_C ? csub(yL, yN) : csub(yL, y1);
         x1 = make_double2(ax.minv[0] * r1.x + ax.minv[1] * r2.x, ax.minv[0] * r1.y + ax.minv[1] * r2.y);
         xn = make_double2(ax.minv[2] * r1.x + ax.minv[3] * r2.x, ax.minv[2] * r1.y + ax.minv[3] * r2.y);
     } else {
@@ -121,6 +124,25 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View i
             }
         }
     }
+    if (ax.kind == HT_KIND_F3) {  // rank-2 correction of the T_F inverse
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int j = tid + k * BLOCK;
+            if (j == 1) corr[0] = acc[k];
+            if (j == N - 1) corr[1] = acc[k];
+        }
+        __syncthreads();
+        const double2 e0 = corr[0], e1 = corr[1];
+        const double2 a0 = cadd(cmul(ax.f3vi[0], e0), cmul(ax.f3vi[1], e1));
+        const double2 a1 = cadd(cmul(ax.f3vi[2], e0), cmul(ax.f3vi[3], e1));
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int j = tid + k * BLOCK;
+            if (j < N) acc[k] = j == 1 ? a0 : (j == N - 1 ? a1 : csub(acc[k], cmul(ax.f3v[j + 1], a1)));
+        }
+        x1 = csub(x1, cmul(ax.f3v[0], a1));
+        xn = csub(xn, cmul(ax.f3v[n - 1], a1));
+    }
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;
@@ -144,14 +166,21 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View i
     const int n = ax.n, N = ax.N;
     const int64_t ib = vbase(in, b), ob = vbase(out, b);
     const bool cmp = is_comparator(ax.kind);
+    const bool f3 = ax.kind == HT_KIND_F3;
     const int off = cmp ? 0 : 1;  // position of core entry 0 in the vectors
+    const int kb = base_kind(ax.kind);
 
     const double2 zero = make_double2(0.0, 0.0);
     const double2 x1 = cmp ? zero : vload(in, ib, 0), xn = cmp ? zero : vload(in, ib, n - 1);
     const double2 beta0 = ax.rank > 0 ? vload(in, ib, 1) : zero;
     const double2 beta1 = ax.rank > 1 ? vload(in, ib, 2) : zero;
-    // the replaced (bubble) columns are added explicitly, not through the sine core
-    auto in_fn = [&](int, int j) { return j >= ax.rank ? vload(in, ib, j + off) : zero; };
+    // F3: the coefficients of the cosine and cubic columns (positions 2 and n-2)
+    const double2 g0 = f3 ? vload(in, ib, 2) : zero, g1 = f3 ? vload(in, ib, n - 2) : zero;
+    // the replaced (bubble, cosine, cubic) columns are added explicitly, not through the core
+    auto in_fn = [&](int, int j) {
+        const bool replaced = j < ax.rank || (f3 && (j == 1 || j == N - 1));
+        return replaced ? zero : vload(in, ib, j + off);
+    };
     auto park = [&](int j, double2 y) { vstore(out, ob, j + off, y); };
     auto unpark = [&](int j) { return vload(out, ob, j + off); };
     const int mode = (is_fourier(ax.kind) && out.cplx) ? MODE_CPLX : ax.syn.mode;
@@ -175,17 +204,30 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View i
                     y.y += b1 * beta1.y;
                 }
             }
+            if (f3) {
+                const double c0 = ax.f3b[j + 1], c1 = ax.f3b[n + j + 1];
+                y.x += c0 * g0.x + c1 * g1.x;
+                y.y += c0 * g0.y + c1 * g1.y;
+            }
             vstore(out, ob, j + off, y);
             // boundary rows: extension of the core columns to the two ghost grid points
-            if (ax.kind == HT_KIND_C || ax.kind == HT_KIND_F) {
-                const bool first_src = ax.kind == HT_KIND_C ? (j == 0) : (j == N - 1);
-                const bool last_src = ax.kind == HT_KIND_C ? (j == N - 1) : (j == 0);
-                if (first_src) vstore(out, ob, 0, make_double2(ax.q1 * x1.x + u[k].x, ax.q1 * x1.y + u[k].y));
-                if (last_src) vstore(out, ob, n - 1, make_double2(ax.q1 * xn.x + u[k].x, ax.q1 * xn.y + u[k].y));
+            if (kb == HT_KIND_C || kb == HT_KIND_F) {
+                const bool first_src = kb == HT_KIND_C ? (j == 0) : (j == N - 1);
+                const bool last_src = kb == HT_KIND_C ? (j == N - 1) : (j == 0);
+                double2 b0v = make_double2(ax.q1 * x1.x + u[k].x, ax.q1 * x1.y + u[k].y);
+                double2 bnv = make_double2(ax.q1 * xn.x + u[k].x, ax.q1 * xn.y + u[k].y);
+                if (f3) {
+                    b0v.x += ax.f3b[0] * g0.x + ax.f3b[n] * g1.x;
+                    b0v.y += ax.f3b[0] * g0.y + ax.f3b[n] * g1.y;
+                    bnv.x += ax.f3b[n - 1] * g0.x + ax.f3b[2 * n - 1] * g1.x;
+                    bnv.y += ax.f3b[n - 1] * g0.y + ax.f3b[2 * n - 1] * g1.y;
+                }
+                if (first_src) vstore(out, ob, 0, b0v);
+                if (last_src) vstore(out, ob, n - 1, bnv);
             }
         }
     }
-    if (tid == 0 && !cmp && !(ax.kind == HT_KIND_C || ax.kind == HT_KIND_F)) {
+    if (tid == 0 && !cmp && !(kb == HT_KIND_C || kb == HT_KIND_F)) {
         vstore(out, ob, 0, cscale(x1, ax.q1));
         vstore(out, ob, n - 1, cscale(xn, ax.q1));
     }

@@ -18,6 +18,8 @@ struct HostChirp {
 struct HostAxis {
     Axis ax{};
     std::vector<double> q, bub, U, tcos, tsin;
+    std::vector<cd> f3v;       // kind F3 only
+    std::vector<double> f3b;   // kind F3 only
     HostChirp ana, syn;
     int M = 0;
 };

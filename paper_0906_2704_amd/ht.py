@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libht.so")
 
 HT_FAMILY_PAPER, HT_FAMILY_DST = 0, 1
 HT_NORM_IDENTITY, HT_NORM_SECOND_DIFF = 0, 1
-KIND_NAMES = {1: "AR", 2: "C", 3: "F", 4: "DST2", 5: "DST3", 6: "P", 7: "R"}
+KIND_NAMES = {1: "AR", 2: "C", 3: "F", 4: "DST2", 5: "DST3", 6: "P", 7: "R", 8: "F3"}
 NORMS = {"I": HT_NORM_IDENTITY, "D2": HT_NORM_SECOND_DIFF}
 FAMILIES = {"paper": HT_FAMILY_PAPER, "dst": HT_FAMILY_DST, "paper+dst3": 2, "periodic": 3, "reflective": 4}
 PRECISIONS = {"f64": 0, "bf16x3": 1, "f16x3": 2, "f32": 3}

@@ -1,0 +1,155 @@
+"""GPU parity of the degree-3 transform for any PSF (kind F3: T_F with its frequency +-1
+pair replaced by a cosine column and a cubic; the T_F inverse plus a rank-2 float64
+correction), through the C ABI, against the oracle's dense transforms: transforms,
+eigenvalues, GCV and restorations in 1D (lengths spanning the FFT size classes, the edge
+lengths 5 and 6) and 2D, the float32 core, and the exact restoration of cubics."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import tikhonov as tk
+from oracle import transforms as tr
+from oracle import twod
+from paper_0906_2704_amd import synth
+
+from parity import assert_gcv_close, rel_normwise
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ht():
+    from paper_0906_2704_amd import ht as _ht
+    _ht.lib()
+    return _ht
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def plan_f3(ht, n, **kw):
+    p = ht.Plan(n, 3, psf_symmetric=False, family="paper+dst3", **kw)
+    assert p.kinds == ["F3"] * p.ndim and p.is_complex
+    return p
+
+
+def problem(n, count, seed):
+    rng = np.random.default_rng(seed)
+    m = max(1, min(6, (n - 3) // 2))
+    h, c = synth.gaussian_psf(m, max(m / 3, 0.6), shift=0.6)
+    Y = np.stack([synth.add_noise(rng, synth.observe_1d(synth.piecewise_poly(rng, n + 2 * m), h, c, n), 0.01)
+                  for _ in range(count)])
+    return Y, h, c
+
+
+@pytest.mark.parametrize("n", [5, 6, 37, 300, 1031])
+def test_f3_transforms_eigs_restoration(ht, n):
+    print("case F3", n, flush=True)
+    plan = plan_f3(ht, n)
+    Y, h, c = problem(n, 3, n + 5)
+    X = np.stack([tr.inverse("F3", y) for y in Y])
+    Xg = ht.ht_transform_inv(plan, to_dev(Y)).cpu().numpy()
+    assert rel_normwise(Xg, X) < TOL
+    # real signals: real coefficients on the cosine and cubic columns
+    assert np.abs(Xg[:, [2, n - 2]].imag).max() < 1e-13 * np.abs(Xg).max()
+    Z = rng_coeffs(n, 2)
+    Zr = np.stack([tr.forward("F3", z) for z in Z])
+    Zg = ht.ht_transform_fwd(plan, to_dev(Z)).cpu().numpy()
+    assert rel_normwise(Zg, Zr.real) < TOL
+    mus = synth.mu_grid(-6.0, 0.0, 48)
+    for norm in ("I", "D2"):
+        d, s = ht.ht_eigs(plan, to_dev(h), [len(h)], [c], norm)
+        do = tr.blur_eigs("F3", n, h, c)
+        so = tr.smooth_eigs("F3", n, norm)
+        assert np.abs(d.cpu().numpy()[0] - do).max() < 1e-13
+        assert np.abs(s.cpu().numpy()[0] - so).max() < 1e-14
+        ghat = ht.ht_transform_inv(plan, to_dev(Y))
+        Gv, kb, mb = ht.ht_gcv_scan(plan, ghat, d, s, to_dev(mus))
+        f = ht.ht_transform_fwd(plan, ht.ht_tikhonov_filter(plan, ghat, d, s, mb)).cpu().numpy()
+        for b in range(len(Y)):
+            Gw, kw, muw = tk.gcv_scan(X[b], do, so, mus)
+            assert_gcv_close(Gv[b].cpu().numpy(), Gw, X[b], do, so, mus, "F3 %d" % b)
+            k = int(kb[b])
+            # k* exact, or an equally good grid point where G is flat (n = 5 with L = D2 leaves
+            # one entry with s != 0, and G does not depend on mu at all)
+            assert k == kw or Gw[k] <= Gw[kw] * (1 + 1e-12), (k, kw)
+            fw = tr.forward("F3", tk.tikhonov_filter(X[b], do, so, float(mus[k]))).real
+            assert rel_normwise(f[b], fw) < TOL
+
+
+def rng_coeffs(n, count):
+    """Coefficients of real signals (the image of real vectors under T^{-1})."""
+    rng = np.random.default_rng(n)
+    return np.stack([tr.inverse("F3", rng.standard_normal(n)) for _ in range(count)])
+
+
+@pytest.mark.parametrize("n", [64, 4097])
+def test_f3_cubics_restored_exactly_and_round_trip(ht, n):
+    """Noise-free cubics pass the filter unchanged with L = D2 (any mu, any PSF); long
+    signals take the 8192-point core and the round trip T (T^{-1} y) = y."""
+    plan = plan_f3(ht, n)
+    rng = np.random.default_rng(2)
+    h, c = synth.gaussian_psf(5, 1.5, shift=0.8)
+    x = np.linspace(-1.0, 1.0, n)
+    P = np.stack([np.polyval(rng.standard_normal(4), x) for _ in range(3)])
+    d, s = ht.ht_eigs(plan, to_dev(h), [len(h)], [c], "D2")
+    ghat = ht.ht_transform_inv(plan, to_dev(P))
+    for mu in (1e-6, 1e-2, 10.0):
+        f = ht.ht_transform_fwd(plan, ht.ht_tikhonov_filter(plan, ghat, d, s,
+                                                             torch.full((3,), mu, dtype=torch.float64,
+                                                                        device=DEV))).cpu().numpy()
+        assert np.abs(f - P).max() < 1e-10 * np.abs(P).max()
+    Y, _, _ = problem(n, 2, 9)
+    back = ht.ht_transform_fwd(plan, ht.ht_transform_inv(plan, to_dev(Y))).cpu().numpy()
+    assert rel_normwise(back, Y) < 1e-11
+
+
+def test_f3_2d_and_float32(ht):
+    n0, n1 = 40, 73
+    plan = plan_f3(ht, (n0, n1), max_batch=2)
+    rng = np.random.default_rng(5)
+    h0, c0 = synth.gaussian_psf(3, 1.2, shift=0.5)
+    h1, c1 = synth.gaussian_psf(4, 1.4, shift=-0.7)
+    Fx = synth.piecewise_poly_image(rng, (n0 + 6, n1 + 8))
+    G = synth.add_noise(rng, synth.observe_2d(Fx, h0, c0, h1, c1, (n0, n1)), 0.005)
+    gh = twod.inverse2d("F3", "F3", G)
+    ghat = ht.ht_transform_inv(plan, to_dev(G[None]))
+    assert rel_normwise(ghat.cpu().numpy()[0], gh) < TOL
+    d, s = ht.ht_eigs(plan, to_dev(np.concatenate([h0, h1])), [len(h0), len(h1)], [c0, c1], "D2")
+    D = twod.eigs2d_separable("F3", "F3", n0, n1, h0, c0, h1, c1)
+    s2 = twod.smooth2d("F3", "F3", n0, n1, "D2")
+    mus = synth.mu_grid(-6.0, 0.0, 32)
+    Gv, kb, mb = ht.ht_gcv_scan(plan, ghat, d, s, to_dev(mus))
+    Gw, kw, muw = tk.gcv_scan(gh.ravel(), D.ravel(), s2.ravel(), mus)
+    assert_gcv_close(Gv[0].cpu().numpy(), Gw, gh.ravel(), D.ravel(), s2.ravel(), mus, "2d F3")
+    assert int(kb[0]) == kw
+    f = ht.ht_transform_fwd(plan, ht.ht_tikhonov_filter(plan, ghat, d, s, mb)).cpu().numpy()[0]
+    fw = twod.forward2d("F3", "F3", tk.tikhonov_filter(gh, D, s2, muw)).real
+    assert rel_normwise(f, fw) < TOL
+    # float32 chirp core, float64 boundary and rank-2 terms
+    p1 = plan_f3(ht, 300)
+    p1.set_precision("f32")
+    Y, _, _ = problem(300, 2, 4)
+    X = np.stack([tr.inverse("F3", y) for y in Y])
+    assert rel_normwise(ht.ht_transform_inv(p1, to_dev(Y)).cpu().numpy(), X) < 1e-5
+
+
+def test_f3_contract(ht):
+    p2 = plan_f3(ht, (16, 16))
+    H, c0, c1 = synth.motion_psf(3, 30)
+    with pytest.raises(ht.HTError, match="UNSUPPORTED"):
+        ht.ht_eigs2d(p2, to_dev(H), (c0, c1), "I")
+    p1 = plan_f3(ht, 32)
+    with pytest.raises(ht.HTError, match="UNSUPPORTED"):
+        ht.ht_gcv_scan_exact(p1, torch.zeros((1, 32), dtype=torch.complex128, device=DEV),
+                             torch.ones((1, 32), dtype=torch.complex128, device=DEV),
+                             torch.ones((1, 32), dtype=torch.float64, device=DEV),
+                             torch.ones(4, dtype=torch.float64, device=DEV))
+    with pytest.raises(ht.HTError, match="UNSUPPORTED"):
+        p1.set_precision("bf16x3")
+    # degree 3 with a symmetric PSF stays the DST family
+    assert ht.Plan(32, 3, psf_symmetric=True, family="paper+dst3").kinds == ["DST3"]
