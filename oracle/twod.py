@@ -98,6 +98,22 @@ def eigs2d_general(kind0, kind1, n0, n1, H, c0, c1):
     return D
 
 
+def gcv2d_exact_values(kind0, kind1, ghat, d, s, mus):
+    """Eq. gcv for an image: ||T^(2) (sigma ghat)||^2 / (sum sigma)^2 per grid value, the
+    residual norm of eq. gcnum with T^(2) = T_{n0} (x) T_{n1} applied exactly (long-double
+    products), on the scale of eq. gcv2 (the factors mu^2 cancel; R21 in 2D)."""
+    ghat = np.asarray(ghat)
+    d = np.asarray(d)
+    s2 = np.asarray(s, dtype=np.float64) ** 2
+    d2 = np.abs(d) ** 2
+    out = np.empty(len(mus), dtype=np.float64)
+    for k, mu in enumerate(mus):
+        sigma = s2 / (d2 + mu * s2)
+        Y = forward2d(kind0, kind1, sigma * ghat)
+        out[k] = np.sum(np.abs(Y) ** 2) / np.sum(sigma) ** 2
+    return out
+
+
 def smooth2d(kind0, kind1, n0, n1, norm):
     if norm == "I":
         return np.ones((n0, n1))
