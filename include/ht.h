@@ -225,19 +225,25 @@ ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const void* d, con
                       double* G, int32_t* k_best, double* mu_best, int64_t batch,
                       hipStream_t stream);
 
-/* ht_gcv_scan_exact -- the exact GCV functional of eq. gcv for a 1D plan,
+/* ht_gcv_scan_exact -- the exact GCV functional of eq. gcv,
  * G(mu_k) = ||T (sigma ghat)||^2 / (sum_i sigma_i)^2, i.e. ||g - A f_reg||^2 /
  * trace(I - A T Phi D^{-1} T^{-1})^2 with the factors mu^2 cancelled (the residual is
  * T (I - Phi) ghat and the trace sum_i (1 - Phi_i)), on the same scale as ht_gcv_scan,
- * which uses the approximation ||T v|| ~ ||v|| of eq. gcnum.  ||T v||^2 is evaluated from
- * T's structure (orthonormal core plus boundary columns and ghost rows): the sums of
- * ht_gcv_scan plus up to six weighted sums of sigma_i ghat_i with fixed vectors, float64,
- * fixed order.  Arguments as for ht_gcv_scan (spectra [eig_batch][n]); HT_ERR_UNSUPPORTED
- * for 2D plans.                                                                         */
+ * which uses the approximation ||T v|| ~ ||v|| of eq. gcnum.  Arguments as for
+ * ht_gcv_scan.  Float64 sums in a fixed order.
+ *   1D plans: ||T v||^2 from T's structure (orthonormal core plus boundary columns and
+ *   ghost rows): the sums of ht_gcv_scan plus up to four weighted sums of sigma_i ghat_i
+ *   with fixed vectors; allocates nothing.
+ *   2D plans: per grid value, the plan's forward transform of sigma ghat and its squared
+ *   norm (K forward transforms per image: a diagnostic, not a scan rate); batch <=
+ *   max_batch; allocates its workspace (at most 256 MiB plus the G values when G is
+ *   NULL) on the stream with hipMallocAsync and frees it there.
+ *   The periodic and reflective comparators are unitary: eq. gcv is eq. gcv2 (1D plans
+ *   run ht_gcv_scan).  HT_ERR_UNSUPPORTED for HT_KIND_F3.                               */
 ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, const void* d, const double* s,
-                            int64_t eig_batch, const double* mu_grid, int32_t K, int grid_per_item,
-                            double* G, int32_t* k_best, double* mu_best, int64_t batch,
-                            hipStream_t stream);
+                            int64_t eig_batch, int layout, const double* mu_grid, int32_t K,
+                            int grid_per_item, double* G, int32_t* k_best, double* mu_best,
+                            int64_t batch, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------
  * Ragged batches: many 1D signals of uneven length n_b, each with its own PSF mask,

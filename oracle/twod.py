@@ -98,10 +98,11 @@ def eigs2d_general(kind0, kind1, n0, n1, H, c0, c1):
     return D
 
 
-def gcv2d_exact_values(kind0, kind1, ghat, d, s, mus):
+def gcv2d_exact_values(kind0, kind1, ghat, d, s, mus, wide=True):
     """Eq. gcv for an image: ||T^(2) (sigma ghat)||^2 / (sum sigma)^2 per grid value, the
     residual norm of eq. gcnum with T^(2) = T_{n0} (x) T_{n1} applied exactly (long-double
-    products), on the scale of eq. gcv2 (the factors mu^2 cancel; R21 in 2D)."""
+    products; float64 products with wide=False, for large images), on the scale of eq. gcv2
+    (the factors mu^2 cancel; R21 in 2D)."""
     ghat = np.asarray(ghat)
     d = np.asarray(d)
     s2 = np.asarray(s, dtype=np.float64) ** 2
@@ -109,7 +110,7 @@ def gcv2d_exact_values(kind0, kind1, ghat, d, s, mus):
     out = np.empty(len(mus), dtype=np.float64)
     for k, mu in enumerate(mus):
         sigma = s2 / (d2 + mu * s2)
-        Y = forward2d(kind0, kind1, sigma * ghat)
+        Y = forward2d(kind0, kind1, sigma * ghat, wide=wide)
         out[k] = np.sum(np.abs(Y) ** 2) / np.sum(sigma) ** 2
     return out
 

@@ -622,6 +622,84 @@ __global__ __launch_bounds__(XG_THREADS) void k_gcv_exact(Spec sp, const void* _
     }
 }
 
+// ------------------------------------------------------------------- exact GCV, 2D
+
+// X = sigma ghat with sigma = |s|^2 / (|d|^2 + mu |s|^2) at the grid value mu_b of every
+// image (0 where s = 0, as in the scan).
+__global__ void k_xg2_scale(Spec sp, const void* __restrict__ coeff, const double* __restrict__ mus,
+                            int64_t mu_stride, int k, int64_t b0, void* X, int64_t total) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int64_t bl = idx / sp.per_item, e = idx - bl * sp.per_item, b = b0 + bl;
+    double2 dd;
+    double ss;
+    spec_at(sp, b, e, dd, ss);
+    const double s2 = ss * ss;
+    const double mu = mus[b * mu_stride + k];
+    const double sg = s2 != 0.0 ? s2 / (fma(dd.x, dd.x, dd.y * dd.y) + mu * s2) : 0.0;
+    const double2 g = cload(coeff, b * sp.per_item + e, sp.cplx);
+    if (sp.cplx)
+        static_cast<double2*>(X)[idx] = make_double2(sg * g.x, sg * g.y);
+    else
+        static_cast<double*>(X)[idx] = sg * g.x;
+}
+
+constexpr int XG2_PARTS = 256;  // partial sums per image, added in order
+
+// part[bl][w] = (sum Y^2, sum sigma) over the span w of image bl; a fixed tree per block.
+__global__ __launch_bounds__(256) void k_xg2_partial(Spec sp, const double* __restrict__ mus, int64_t mu_stride, int k,
+                                                     int64_t b0, const double* __restrict__ Y, double2* part) {
+    __shared__ double2 red[256];
+    const int64_t bl = blockIdx.y, b = b0 + bl;
+    const int64_t span = (sp.per_item + XG2_PARTS - 1) / XG2_PARTS;
+    const int64_t e0 = blockIdx.x * span;
+    const int64_t e1 = e0 + span < sp.per_item ? e0 + span : sp.per_item;
+    const double mu = mus[b * mu_stride + k];
+    double N = 0.0, D = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const double y = Y[bl * sp.per_item + e];
+        N = fma(y, y, N);
+        double2 dd;
+        double ss;
+        spec_at(sp, b, e, dd, ss);
+        const double s2 = ss * ss;
+        if (s2 != 0.0) D += s2 / (fma(dd.x, dd.x, dd.y * dd.y) + mu * s2);
+    }
+    red[threadIdx.x] = make_double2(N, D);
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[threadIdx.x].x += red[threadIdx.x + w].x;
+            red[threadIdx.x].y += red[threadIdx.x + w].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[bl * XG2_PARTS + blockIdx.x] = red[0];
+}
+
+// G[b][k] = sum N / (sum D)^2 over the parts in order.
+__global__ void k_xg2_final(const double2* __restrict__ part, int k, int K, int64_t b0, double* G) {
+    const int64_t bl = blockIdx.y;  // one single-thread block per image of the chunk
+    double N = 0.0, D = 0.0;
+    for (int w = 0; w < XG2_PARTS; ++w) {
+        const double2 v = part[bl * XG2_PARTS + w];
+        N += v.x;
+        D += v.y;
+    }
+    G[(b0 + bl) * K + k] = N / (D * D);
+}
+
+__global__ __launch_bounds__(64) void k_xg2_argmin(const double* __restrict__ G, GcvOut o) {
+    const int64_t b = blockIdx.x;
+    __shared__ int kshared;
+    gcv_argmin(G + b * o.K, o.K, &kshared);
+    if (threadIdx.x == 0) {
+        const int kb = kshared;
+        o.kbest[b] = kb;
+        if (o.mubest) o.mubest[b] = kb >= 0 ? o.mus[b * o.mu_stride + kb] : __builtin_nan("");
+    }
+}
+
 static Spec make_spec(const ht_plan* plan, const void* d, const double* s, int64_t eig_batch, int layout) {
     Spec sp;
     sp.d = d;
@@ -771,16 +849,80 @@ extern "C" ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const v
     return check_hip(hipGetLastError(), "ht_gcv_scan finalize launch");
 }
 
+// Eq. gcv for images: per grid value, X = sigma ghat, Y = T^(2) X by the plan's forward
+// transform, G = ||Y||^2 / (sum sigma)^2.  Images in chunks of at most 256 MiB of
+// workspace, allocated on the stream.
+static ht_status gcv_exact_2d(const ht_plan* plan, const void* coeff, const Spec& sp, GcvOut o, int64_t batch,
+                              hipStream_t stream) {
+    const int64_t img = sp.per_item;
+    const size_t xb = plan->cplx ? sizeof(double2) : sizeof(double);
+    int64_t chunk = (static_cast<int64_t>(1) << 28) / (img * static_cast<int64_t>(xb + sizeof(double)));
+    chunk = chunk < 1 ? 1 : (chunk > batch ? batch : chunk);
+    if (chunk > plan->max_batch) chunk = plan->max_batch;
+    void* X = nullptr;
+    double* Y = nullptr;
+    double2* part = nullptr;
+    double* Gb = o.G;
+    bool ok = hipMallocAsync(&X, xb * img * chunk, stream) == hipSuccess &&
+              hipMallocAsync(reinterpret_cast<void**>(&Y), sizeof(double) * img * chunk, stream) == hipSuccess &&
+              hipMallocAsync(reinterpret_cast<void**>(&part), sizeof(double2) * XG2_PARTS * chunk, stream) == hipSuccess;
+    if (ok && !Gb) ok = hipMallocAsync(reinterpret_cast<void**>(&Gb), sizeof(double) * o.K * batch, stream) == hipSuccess;
+    ht_status st = ok ? HT_OK : fail(HT_ERR_OOM, "ht_gcv_scan_exact: workspace allocation failed");
+    for (int64_t b0 = 0; st == HT_OK && b0 < batch; b0 += chunk) {
+        const int64_t nb = batch - b0 < chunk ? batch - b0 : chunk;
+        const int64_t total = nb * img;
+        const void* cf = static_cast<const char*>(coeff);
+        for (int k = 0; st == HT_OK && k < o.K; ++k) {
+            hipLaunchKernelGGL(k_xg2_scale, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream, sp, cf,
+                               o.mus, o.mu_stride, k, b0, X, total);
+            st = check_hip(hipGetLastError(), "ht_gcv_scan_exact scale launch");
+            if (st != HT_OK) break;
+            st = ht_transform_fwd(plan, X, Y, nb, stream);
+            if (st != HT_OK) break;
+            hipLaunchKernelGGL(k_xg2_partial, dim3(XG2_PARTS, static_cast<unsigned>(nb)), dim3(256), 0, stream, sp,
+                               o.mus, o.mu_stride, k, b0, static_cast<const double*>(Y), part);
+            st = check_hip(hipGetLastError(), "ht_gcv_scan_exact partial launch");
+            if (st != HT_OK) break;
+            hipLaunchKernelGGL(k_xg2_final, dim3(1, static_cast<unsigned>(nb)), dim3(1), 0, stream,
+                               static_cast<const double2*>(part), k, o.K, b0, Gb);
+            st = check_hip(hipGetLastError(), "ht_gcv_scan_exact final launch");
+        }
+    }
+    if (st == HT_OK) {
+        hipLaunchKernelGGL(k_xg2_argmin, dim3(static_cast<unsigned>(batch)), dim3(64), 0, stream,
+                           static_cast<const double*>(Gb), o);
+        st = check_hip(hipGetLastError(), "ht_gcv_scan_exact argmin launch");
+    }
+    if (X) (void)hipFreeAsync(X, stream);
+    if (Y) (void)hipFreeAsync(Y, stream);
+    if (part) (void)hipFreeAsync(part, stream);
+    if (Gb && Gb != o.G) (void)hipFreeAsync(Gb, stream);
+    return st;
+}
+
 extern "C" ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, const void* d, const double* s,
-                                       int64_t eig_batch, const double* mu_grid, int32_t K, int grid_per_item,
-                                       double* G, int32_t* k_best, double* mu_best, int64_t batch,
+                                       int64_t eig_batch, int layout, const double* mu_grid, int32_t K,
+                                       int grid_per_item, double* G, int32_t* k_best, double* mu_best, int64_t batch,
                                        hipStream_t stream) {
     if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: null plan");
-    if (plan->ndim != 1) return fail(HT_ERR_UNSUPPORTED, "ht_gcv_scan_exact: 1D plans only");
-    if (plan->ax[0].kind == HT_KIND_F3) return fail(HT_ERR_UNSUPPORTED, "ht_gcv_scan_exact: not for the degree-3 Fourier kind");
+    for (int a = 0; a < plan->ndim; ++a)
+        if (plan->ax[a].kind == HT_KIND_F3)
+            return fail(HT_ERR_UNSUPPORTED, "ht_gcv_scan_exact: not for the degree-3 Fourier kind");
+    if (plan->ndim == 2) {
+        if (K < 1 || K > 1024) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: K must be in [1, 1024]");
+        if (batch < 0 || batch > plan->max_batch)
+            return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: batch exceeds the plan's max_batch");
+        if (batch == 0) return HT_OK;
+        if (!coeff || !d || !s || !mu_grid || !k_best) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: null argument");
+        ht_status st2 = check_spectrum(plan, eig_batch, layout, batch, "ht_gcv_scan_exact");
+        if (st2 != HT_OK) return st2;
+        const Spec sp = make_spec(plan, d, s, eig_batch, layout);
+        GcvOut o{mu_grid, grid_per_item ? static_cast<int64_t>(K) : 0, K, G, k_best, mu_best};
+        return gcv_exact_2d(plan, coeff, sp, o, batch, stream);
+    }
     if (!plan->xg_mem)  // periodic / reflective: T is unitary and eq. gcv2 is eq. gcv
-        return ht_gcv_scan(plan, coeff, d, s, eig_batch, HT_SPECTRUM_FULL, mu_grid, K, grid_per_item, G, k_best,
-                           mu_best, batch, stream);
+        return ht_gcv_scan(plan, coeff, d, s, eig_batch, layout, mu_grid, K, grid_per_item, G, k_best, mu_best, batch,
+                           stream);
     if (K < 1 || K > 1024) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: K must be in [1, 1024]");
     if (batch < 0 || batch > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: batch out of range");
     if (batch == 0) return HT_OK;

@@ -49,7 +49,7 @@ def lib():
     L.ht_eigs2d.argtypes = [P, VP, I64, I64, I64, I64, ctypes.c_int, VP, VP, I64, VP]
     L.ht_tikhonov_filter.argtypes = [P, VP, VP, VP, I64, ctypes.c_int, VP, VP, I64, VP]
     L.ht_gcv_scan.argtypes = [P, VP, VP, VP, I64, ctypes.c_int, VP, I32, ctypes.c_int, VP, VP, VP, I64, VP]
-    L.ht_gcv_scan_exact.argtypes = [P, VP, VP, VP, I64, VP, I32, ctypes.c_int, VP, VP, VP, I64, VP]
+    L.ht_gcv_scan_exact.argtypes = [P, VP, VP, VP, I64, ctypes.c_int, VP, I32, ctypes.c_int, VP, VP, VP, I64, VP]
     L.ht_plan_set_precision.argtypes = [P, ctypes.c_int]
     L.ht_plan_precision.argtypes = [P]
     L.ht_status_str.argtypes = [ctypes.c_int]
@@ -239,10 +239,10 @@ def ht_gcv_scan(plan, coeff, d, s, mu_grid, want_G=True, G=None, kb=None, mb=Non
 
 
 def ht_gcv_scan_exact(plan, coeff, d, s, mu_grid, want_G=True, G=None, kb=None, mb=None):
-    """Eq. gcv (exact residual norm) for 1D plans; returns (G or None, k_best, mu_best)."""
+    """Eq. gcv (exact residual norm); returns (G or None, k_best, mu_best)."""
     L = lib()
     batch = coeff.numel() // _item(plan)
-    eig_batch, _ = _spectrum(plan, d)
+    eig_batch, layout = _spectrum(plan, d)
     K = mu_grid.shape[-1]
     per_item = 1 if mu_grid.dim() == 2 else 0
     dev = coeff.device
@@ -253,7 +253,7 @@ def ht_gcv_scan_exact(plan, coeff, d, s, mu_grid, want_G=True, G=None, kb=None, 
     if mb is None:
         mb = torch.empty(batch, dtype=torch.float64, device=dev)
     _check(L.ht_gcv_scan_exact(plan.handle, _ptr(coeff, plan.coeff_dtype, "coeff"), _ptr(d, plan.coeff_dtype, "d"),
-                               _ptr(s, torch.float64, "s"), eig_batch, _ptr(mu_grid, torch.float64, "mu_grid"),
+                               _ptr(s, torch.float64, "s"), eig_batch, layout, _ptr(mu_grid, torch.float64, "mu_grid"),
                                int(K), per_item, _ptr(G, torch.float64, "G"), _ptr(kb, torch.int32, "k_best"),
                                _ptr(mb, torch.float64, "mu_best"), batch, _stream()), "ht_gcv_scan_exact")
     return G, kb, mb

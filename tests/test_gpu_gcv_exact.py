@@ -1,7 +1,9 @@
 """GPU parity of the exact GCV functional (ht_gcv_scan_exact, eq. gcv) against the oracle's
-dense evaluation ||T (sigma ghat)||^2 / (sum sigma)^2, through the C ABI, on the oracle's
-own coefficients and spectra (so that only the functional is compared), for every kind,
-both norms, lengths that span several chunks with a ragged tail, and the edge lengths.
+dense evaluation ||T (sigma ghat)||^2 / (sum sigma)^2, through the C ABI: in 1D on the
+oracle's own coefficients and spectra (so that only the functional is compared), for every
+kind, both norms, lengths that span several chunks with a ragged tail, and the edge
+lengths; in 2D for separable and general masks; and the choice of mu against the
+approximation on the 1D workload and on the out-of-focus 2D experiment.
 
 Tolerance: the structured form adds ||v_mid||^2, cross terms 2 Re conj(P_c) v_c, the Gram
 term and the two boundary rows, each of size at most about ||T||^2 ||v||^2 with
@@ -16,6 +18,7 @@ import torch
 
 from oracle import tikhonov as tk
 from oracle import transforms as tr
+from oracle import twod
 from paper_0906_2704_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -92,11 +95,6 @@ def test_exact_gcv_per_item_grids_and_contract(ht):
         Go = tk.gcv_exact_values("C", ghat[b], d, s, grids[b])
         assert np.max(np.abs(Gg[b].cpu().numpy() - Go) / Go) < 1e-10
         assert float(mb[b]) == grids[b][int(kb[b])]
-    p2 = ht.Plan((16, 16), 2)
-    with pytest.raises(ht.HTError, match="1D"):
-        ht.ht_gcv_scan_exact(p2, torch.zeros((1, 16, 16), dtype=torch.float64, device=DEV),
-                             torch.zeros(32, dtype=torch.float64, device=DEV),
-                             torch.zeros(32, dtype=torch.float64, device=DEV), to_dev(grids[0]))
 
 
 def test_exact_vs_approximate_choice_on_the_1d_workload(ht):
@@ -127,4 +125,74 @@ def test_exact_vs_approximate_choice_on_the_1d_workload(ht):
     ra, re = rre(fa), rre(fe)
     print("different choices %d / %d; mean RRE approximate %.5f exact %.5f; mean |k_a - k_e| %.2f"
           % (int(np.sum(ka != ke)), count, ra.mean(), re.mean(), np.abs(ka - ke).mean()))
+    assert np.all(np.isfinite(re))
+
+
+# ------------------------------------------------------------------------------- 2D
+
+@pytest.mark.parametrize("kind,norm,layout", [("C", "I", "factors"), ("F", "D2", "factors"), ("C", "D2", "full"),
+                                              ("AR", "I", "full")])
+def test_exact_gcv_2d_parity(ht, kind, norm, layout):
+    """Images (two, ragged tiles): the forward transform of sigma ghat per grid value
+    against the oracle's dense eq. gcv; the bound is the float64 transform's normwise
+    error (about 1e-15 relative to the vector), amplified by ||V||^2 / ||T V||^2 as in 1D."""
+    n0, n1 = 70, 53
+    degree = 1 if kind == "AR" else 2
+    plan = ht.Plan((n0, n1), degree, psf_symmetric=(kind != "F"), max_batch=2)
+    assert plan.kinds == [kind, kind]
+    rng = np.random.default_rng(3)
+    if layout == "factors":
+        h0, c0 = synth.gaussian_psf(4, 1.4, shift=0.6 if kind == "F" else 0.0)
+        h1, c1 = synth.gaussian_psf(3, 1.1)
+        d, s = ht.ht_eigs(plan, to_dev(np.concatenate([h0, h1])), [len(h0), len(h1)], [c0, c1], norm)
+        D = twod.eigs2d_separable(kind, kind, n0, n1, h0, c0, h1, c1)
+        Fs = [synth.piecewise_poly_image(rng, (n0 + 8, n1 + 6)) for _ in range(2)]
+        Gs = [synth.add_noise(rng, synth.observe_2d(F, h0, c0, h1, c1, (n0, n1)), 0.003) for F in Fs]
+    else:
+        H, c0, c1 = synth.disk_psf(3.5)
+        d, s = ht.ht_eigs2d(plan, to_dev(H), (c0, c1), norm)
+        D = twod.eigs2d_general(kind, kind, n0, n1, H, c0, c1)
+        m0, m1 = synth.mask_halfwidths(H, c0, c1)
+        Fs = [synth.piecewise_poly_image(rng, (n0 + 2 * m0, n1 + 2 * m1)) for _ in range(2)]
+        Gs = [synth.add_noise(rng, synth.observe_2d_mask(F, H, c0, c1, (n0, n1)), 0.003) for F in Fs]
+    S = twod.smooth2d(kind, kind, n0, n1, norm)
+    ghat = ht.ht_transform_inv(plan, to_dev(np.stack(Gs)))
+    mus = synth.mu_grid(-6.0, 0.0, 24)
+    Gx, kx, mx = ht.ht_gcv_scan_exact(plan, ghat, d, s, to_dev(mus))
+    Gx = Gx.cpu().numpy()
+    for b in range(2):
+        gh = twod.inverse2d(kind, kind, Gs[b])
+        Go = twod.gcv2d_exact_values(kind, kind, gh, D, S, mus)
+        sig = S ** 2 / (np.abs(D) ** 2 + mus[0] * S ** 2)
+        V = sig * gh
+        amp = np.sum(np.abs(V) ** 2) / np.sum(np.abs(twod.forward2d(kind, kind, V)) ** 2)
+        err = np.max(np.abs(Gx[b] - Go) / Go)
+        print("%s %s %s image %d: max rel err %.2e (amplification %.1f)" % (kind, norm, layout, b, err, amp))
+        assert err < 1e-11 * (1 + amp)
+        ko = int(np.argmin(Go))
+        k = int(kx[b])
+        assert k == ko or Go[k] <= Go[ko] * (1 + 1e-10)
+        assert float(mx[b]) == mus[k]
+
+
+def test_exact_vs_approximate_choice_on_the_disk_experiment(ht):
+    """The 2D experiment of Section 6 (out-of-focus blur, 0.1% noise, L = I, T_C) on 4
+    images 256 x 256, disk radius 4: the choice of mu by eq. gcv and by its approximation,
+    and the restoration errors of both (reported)."""
+    n, count = 256, 4
+    probs = [synth.disk_image(i, n, 4.0) for i in range(count)]
+    plan = ht.Plan((n, n), 2, psf_symmetric=True, max_batch=count)
+    p0 = probs[0]
+    d, s = ht.ht_eigs2d(plan, to_dev(p0.H), (p0.c0, p0.c1), "I")
+    ghat = ht.ht_transform_inv(plan, to_dev(np.stack([p.g for p in probs])))
+    mus = to_dev(p0.mus)
+    _, ka, ma = ht.ht_gcv_scan(plan, ghat, d, s, mus)
+    _, ke, me = ht.ht_gcv_scan_exact(plan, ghat, d, s, mus)
+    fa = ht.ht_transform_fwd(plan, ht.ht_tikhonov_filter(plan, ghat, d, s, ma)).cpu().numpy()
+    fe = ht.ht_transform_fwd(plan, ht.ht_tikhonov_filter(plan, ghat, d, s, me)).cpu().numpy()
+    rre = lambda f, p: np.linalg.norm(f - p.f_true) / np.linalg.norm(p.f_true)
+    ra = [rre(fa[i], p) for i, p in enumerate(probs)]
+    re = [rre(fe[i], p) for i, p in enumerate(probs)]
+    print("k approximate %s exact %s; mean RRE approximate %.5f exact %.5f"
+          % (ka.cpu().tolist(), ke.cpu().tolist(), np.mean(ra), np.mean(re)))
     assert np.all(np.isfinite(re))
