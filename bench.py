@@ -737,8 +737,11 @@ class Mask2D:
             # one fused multiply-add per (mask row, column, tap) and per (row, column, mask row)
             "eigs": ("alu", 2.0 * (L0 * n * L1 + n * n * L0)),
             "transform_inv": ("hbm", px * 16),
-            # exact: K forward transforms of the images (16 B per pixel each) plus the sums
-            "gcv_scan": ("hbm", K * px * 40) if self.gcv == "exact" else ("alu", px * K * GCV_FLOPS_PER_PAIR),
+            # exact: per (pixel, mu) the row pass (the eq. mugcv pair plus one fused multiply-add
+            # per axis-1 fixed vector, 4 for T_C) and the column pass (one reciprocal per two mu,
+            # a multiply-add per axis-0 functional: 2 boundary columns, 2 ghost rows)
+            "gcv_scan": ("alu", px * K * (GCV_FLOPS_PER_PAIR + 2 * 4 + 2 * 4 + 4)) if self.gcv == "exact"
+                        else ("alu", px * K * GCV_FLOPS_PER_PAIR),
             "tikhonov_filter": ("hbm", px * 16 + n * n * 16 + B * 8),
             "transform_fwd": ("hbm", px * 16),
         }

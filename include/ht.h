@@ -234,10 +234,12 @@ ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const void* d, con
  *   1D plans: ||T v||^2 from T's structure (orthonormal core plus boundary columns and
  *   ghost rows): the sums of ht_gcv_scan plus up to four weighted sums of sigma_i ghat_i
  *   with fixed vectors; allocates nothing.
- *   2D plans: per grid value, the plan's forward transform of sigma ghat and its squared
- *   norm (K forward transforms per image: a diagnostic, not a scan rate); batch <=
- *   max_batch; allocates its workspace (at most 256 MiB plus the G values when G is
- *   NULL) on the stream with hipMallocAsync and frees it there.
+ *   2D plans: ||T0 V T1^T||^2 from the same structure of both axes: the 1D form of every
+ *   interior row plus the axis-0 boundary terms, built from the rows' functionals and the
+ *   weighted column sums of V (a row pass, a column pass and a combination per grid
+ *   value); batch <= max_batch; allocates its workspace (at most 256 MiB, plus the G
+ *   values when G is NULL) on the stream with hipMallocAsync and frees it there, so it
+ *   is not for graph capture.
  *   The periodic and reflective comparators are unitary: eq. gcv is eq. gcv2 (1D plans
  *   run ht_gcv_scan).  HT_ERR_UNSUPPORTED for HT_KIND_F3.                               */
 ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, const void* d, const double* s,

@@ -110,8 +110,8 @@ struct ht_plan {
     ht::GemmState* gemm = nullptr;     // set by ht_plan_set_precision (null: float64 core)
     int f32 = 0;                       // float32 chirp-z cores (HT_PRECISION_F32)
     void* arena32 = nullptr;           // their tables
-    ht::XgcvParams xg{};               // 1D: exact GCV tables (vec in xg_mem)
-    void* xg_mem = nullptr;
+    ht::XgcvParams xg[2]{};            // exact GCV tables per axis (vec in xg_mem)
+    void* xg_mem[2] = {nullptr, nullptr};
 };
 
 namespace ht {
@@ -128,7 +128,7 @@ void gemm_release(GemmState* g);
 
 // exact GCV tables of a 1D plan (ht_plan.hip)
 struct HostAxis;
-ht_status build_exact_gcv(const HostAxis& h, ht_plan* p);
+ht_status build_exact_gcv(const HostAxis& h, ht_plan* p, int axis);
 
 // float32 chirp-z cores (ht_plan.hip)
 ht_status plan_build_f32(ht_plan* p);

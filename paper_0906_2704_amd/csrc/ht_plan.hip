@@ -439,7 +439,7 @@ static ht_status build_f3_tables(HostAxis& h) {
 // boundary columns, bubble minus the sine column it replaces), M_c = S^H R_c by the host
 // core, their Gram matrix, the ghost rows a, b of the cosine / Fourier cores and the corner
 // entries of T.
-ht_status build_exact_gcv(const HostAxis& h, ht_plan* p) {
+ht_status build_exact_gcv(const HostAxis& h, ht_plan* p, int axis) {
     const Axis& ax = h.ax;
     const int n = ax.n, N = ax.N, kind = ax.kind;
     XgcvParams xp{};
@@ -512,8 +512,8 @@ ht_status build_exact_gcv(const HostAxis& h, ht_plan* p) {
         return fail(HT_ERR_HIP, "exact GCV table upload failed");
     }
     xp.vec = static_cast<const double2*>(mem);
-    p->xg = xp;
-    p->xg_mem = mem;
+    p->xg[axis] = xp;
+    p->xg_mem[axis] = mem;
     return HT_OK;
 }
 
@@ -725,11 +725,13 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
         return st;
     }
     for (int a = 0; a < ndim; ++a) p->ax[a].tw = tw;
-    if (ndim == 1 && kind != HT_KIND_P && kind != HT_KIND_R && kind != HT_KIND_F3) {  // P, R: eq. gcv2 is exact
-        st = build_exact_gcv(hs[0], p);
-        if (st != HT_OK) {
-            ht_plan_destroy(p);
-            return st;
+    if (kind != HT_KIND_P && kind != HT_KIND_R && kind != HT_KIND_F3) {  // P, R: eq. gcv2 is exact
+        for (int a = 0; a < ndim; ++a) {
+            st = build_exact_gcv(hs[a], p, a);
+            if (st != HT_OK) {
+                ht_plan_destroy(p);
+                return st;
+            }
         }
     }
     if (ndim == 2) {
@@ -753,7 +755,8 @@ extern "C" ht_status ht_plan_destroy(ht_plan* p) {
     if (p->arena) (void)hipFree(p->arena);
     if (p->work) (void)hipFree(p->work);
     if (p->gcv_part) (void)hipFree(p->gcv_part);
-    if (p->xg_mem) (void)hipFree(p->xg_mem);
+    for (void* m : p->xg_mem)
+        if (m) (void)hipFree(m);
     gemm_release(p->gemm);
     plan_release_f32(p);
     delete p;

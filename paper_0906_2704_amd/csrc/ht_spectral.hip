@@ -478,17 +478,24 @@ constexpr int XG_CHUNK = 256;
 constexpr int XG_NV = 4;                 // fixed vectors: |C| + 2 ghost rows <= 4 for every kind
 constexpr int XG_ACC = 2 + 2 * XG_NV;     // D, W, complex P_k
 
-template <bool CPLX>
+// ROWS: the "signals" are the rows of a chunk of images (block (row i, image b0 + y)); per
+// row and grid value the kernel writes the row's functionals ell(v_i) = [P_c, v_c, y_0,
+// y_{n-1}] (complex), ||T v_i||^2 and its part of the trace to rows_out[((y n0 + i) K + k)]
+// (XG2_RW doubles) instead of G.
+constexpr int XG2_RW = 2 * (2 * XG_MAXC + 2) + 2;
+
+template <bool CPLX, bool ROWS>
 __global__ __launch_bounds__(XG_THREADS) void k_gcv_exact(Spec sp, const void* __restrict__ coeff, GcvOut o,
-                                                          XgcvParams xp, int n) {
+                                                          XgcvParams xp, int n, int64_t b0, double* rows_out) {
     constexpr int UW = CPLX ? 2 : 1;  // doubles per staged u
     __shared__ double st_t[XG_CHUNK], st_w[XG_CHUNK];
     __shared__ double st_u[XG_NV * UW][XG_CHUNK];
     __shared__ double red[XG_THREADS][XG_ACC + 1];
-    __shared__ double Gs[1024];
+    __shared__ double Gs[ROWS ? 1 : 1024];
     __shared__ int kshared;
     const int tid = threadIdx.x;
-    const int64_t b = blockIdx.x;
+    const int64_t b = ROWS ? b0 + blockIdx.y : blockIdx.x;
+    const int64_t off = ROWS ? static_cast<int64_t>(blockIdx.x) * n : 0;  // first element of the row
     const double* mus = o.mus + b * o.mu_stride;
     const int K = o.K, N = n - 2, nv = xp.nv;
     const int Kh = (K + 1) / 2;
@@ -499,8 +506,8 @@ __global__ __launch_bounds__(XG_THREADS) void k_gcv_exact(Spec sp, const void* _
     auto load = [&](int64_t e, double& t, double2& g) {
         double2 dd;
         double ss;
-        spec_at(sp, b, e, dd, ss);
-        g = cload(coeff, b * sp.per_item + e, sp.cplx);
+        spec_at(sp, b, off + e, dd, ss);
+        g = cload(coeff, b * sp.per_item + off + e, sp.cplx);
         const double s2 = ss * ss;
         t = 1e150;
         if (s2 != 0.0) t = fma(dd.x, dd.x, dd.y * dd.y) / s2;
@@ -607,12 +614,30 @@ __global__ __launch_bounds__(XG_THREADS) void k_gcv_exact(Spec sp, const void* _
                     yn.y += acc[5 + 2 * xp.nc];
                 }
                 num += y0.x * y0.x + y0.y * y0.y + yn.x * yn.x + yn.y * yn.y;
-                const double g = num / (Dt * Dt);
-                Gs[k] = g;
-                if (o.G) o.G[b * K + k] = g;
+                if (ROWS) {
+                    double* out = rows_out + ((static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * K + k) * XG2_RW;
+                    const int nc = xp.nc;
+                    for (int c = 0; c < nc; ++c) {
+                        out[2 * c] = acc[2 + 2 * c];
+                        out[2 * c + 1] = acc[3 + 2 * c];
+                        out[2 * (nc + c)] = vc[c].x;
+                        out[2 * (nc + c) + 1] = vc[c].y;
+                    }
+                    out[4 * nc] = y0.x;
+                    out[4 * nc + 1] = y0.y;
+                    out[4 * nc + 2] = yn.x;
+                    out[4 * nc + 3] = yn.y;
+                    out[XG2_RW - 2] = num;
+                    out[XG2_RW - 1] = Dt;
+                } else {
+                    const double g = num / (Dt * Dt);
+                    Gs[k] = g;
+                    if (o.G) o.G[b * K + k] = g;
+                }
             }
         }
     }
+    if (ROWS) return;
     __syncthreads();
     gcv_argmin(Gs, K, &kshared);
     if (tid == 0) {
@@ -622,72 +647,223 @@ __global__ __launch_bounds__(XG_THREADS) void k_gcv_exact(Spec sp, const void* _
     }
 }
 
-// ------------------------------------------------------------------- exact GCV, 2D
+// The column pass of the 2D exact GCV.  With V = sigma ghat and the axis-0 functionals
+// lambda_p = [P_c, e_c, y_0, y_{n0-1}], u_p = sum_i lambda_p[i] v_i (a vector over the
+// columns); for every interior column j this thread accumulates u_{P_c}[j], u_y[j] and
+// the entries v_{c, j} of the boundary / replaced rows for four grid values at a time, then
+// the products the axis-0 low-rank form needs, S = [conj(u_{P_c}) v_c (c < nc),
+// conj(v_c) v_c' (c, c' < nc), |u_{y0}|^2, |u_{yn}|^2], added over the 64 columns of the
+// wave by a fixed butterfly; part[((y nblk + block) K + k) XG2_NE + e].  Block (column
+// tile, image, group of XG2_MU grid values).
+constexpr int XG2_NE = XG_MAXC + XG_MAXC * XG_MAXC + 2;
+constexpr int XG2_MU = 8;   // grid values per block, in pairs sharing one reciprocal
 
-// X = sigma ghat with sigma = |s|^2 / (|d|^2 + mu |s|^2) at the grid value mu_b of every
-// image (0 where s = 0, as in the scan).
-__global__ void k_xg2_scale(Spec sp, const void* __restrict__ coeff, const double* __restrict__ mus,
-                            int64_t mu_stride, int k, int64_t b0, void* X, int64_t total) {
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int64_t bl = idx / sp.per_item, e = idx - bl * sp.per_item, b = b0 + bl;
-    double2 dd;
-    double ss;
-    spec_at(sp, b, e, dd, ss);
-    const double s2 = ss * ss;
-    const double mu = mus[b * mu_stride + k];
-    const double sg = s2 != 0.0 ? s2 / (fma(dd.x, dd.x, dd.y * dd.y) + mu * s2) : 0.0;
-    const double2 g = cload(coeff, b * sp.per_item + e, sp.cplx);
-    if (sp.cplx)
-        static_cast<double2*>(X)[idx] = make_double2(sg * g.x, sg * g.y);
-    else
-        static_cast<double*>(X)[idx] = sg * g.x;
+// acc += w v (complex, or the real parts only for the real kinds)
+template <bool CPLX>
+__device__ __forceinline__ void xg_fma(double2& acc, double2 w, double2 v) {
+    if (CPLX) {
+        acc.x = fma(w.x, v.x, fma(-w.y, v.y, acc.x));
+        acc.y = fma(w.x, v.y, fma(w.y, v.x, acc.y));
+    } else {
+        acc.x = fma(w.x, v.x, acc.x);
+    }
 }
 
-constexpr int XG2_PARTS = 256;  // partial sums per image, added in order
-
-// part[bl][w] = (sum Y^2, sum sigma) over the span w of image bl; a fixed tree per block.
-__global__ __launch_bounds__(256) void k_xg2_partial(Spec sp, const double* __restrict__ mus, int64_t mu_stride, int k,
-                                                     int64_t b0, const double* __restrict__ Y, double2* part) {
-    __shared__ double2 red[256];
-    const int64_t bl = blockIdx.y, b = b0 + bl;
-    const int64_t span = (sp.per_item + XG2_PARTS - 1) / XG2_PARTS;
-    const int64_t e0 = blockIdx.x * span;
-    const int64_t e1 = e0 + span < sp.per_item ? e0 + span : sp.per_item;
-    const double mu = mus[b * mu_stride + k];
-    double N = 0.0, D = 0.0;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-        const double y = Y[bl * sp.per_item + e];
-        N = fma(y, y, N);
-        double2 dd;
-        double ss;
-        spec_at(sp, b, e, dd, ss);
-        const double s2 = ss * ss;
-        if (s2 != 0.0) D += s2 / (fma(dd.x, dd.x, dd.y * dd.y) + mu * s2);
-    }
-    red[threadIdx.x] = make_double2(N, D);
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            red[threadIdx.x].x += red[threadIdx.x + w].x;
-            red[threadIdx.x].y += red[threadIdx.x + w].y;
+template <bool CPLX>
+__global__ __launch_bounds__(64) void k_xg2_cols(Spec sp, const void* __restrict__ coeff, const double* __restrict__ mus,
+                                                 int64_t mu_stride, int K, XgcvParams x0, int n0, int n1, int64_t b0,
+                                                 double2* part) {
+    const int lane = threadIdx.x;
+    const int64_t b = b0 + blockIdx.y;
+    const int jc = blockIdx.x * 64 + lane;           // core column, coefficient jc + 1
+    const bool active = jc < n1 - 2;
+    const int j = active ? jc + 1 : 1;
+    const int nc = x0.nc, N0 = n0 - 2;
+    const double* mb = mus + b * mu_stride;
+    {
+        const int k0 = blockIdx.z * XG2_MU;
+        double mu[XG2_MU];
+#pragma unroll
+        for (int m = 0; m < XG2_MU; ++m) mu[m] = mb[k0 + m < K ? k0 + m : K - 1];
+        double2 uP[XG_MAXC][XG2_MU], uE[XG_MAXC][XG2_MU], uY[2][XG2_MU];
+#pragma unroll
+        for (int m = 0; m < XG2_MU; ++m) {
+#pragma unroll
+            for (int c = 0; c < XG_MAXC; ++c) uP[c][m] = uE[c][m] = make_double2(0.0, 0.0);
+            uY[0][m] = uY[1][m] = make_double2(0.0, 0.0);
         }
-        __syncthreads();
+        for (int i = 0; i < n0; ++i) {
+            const int64_t e = static_cast<int64_t>(i) * n1 + j;
+            double2 dd;
+            double ss;
+            spec_at(sp, b, e, dd, ss);
+            const double2 g = cload(coeff, b * sp.per_item + e, sp.cplx);
+            const double s2 = ss * ss;
+            const bool zero = s2 == 0.0;
+            const double t = zero ? 1.0 : fma(dd.x, dd.x, dd.y * dd.y) / s2;
+            const bool mid = i >= 1 && i <= N0;
+            // weights of row i in the axis-0 functionals
+            double2 wP[XG_MAXC];
+#pragma unroll
+            for (int c = 0; c < XG_MAXC; ++c)
+                wP[c] = (mid && c < nc) ? x0.vec[static_cast<int64_t>(c) * N0 + i - 1] : make_double2(0.0, 0.0);
+            double2 wy0 = make_double2(i == 0 ? x0.t00 : (i == n0 - 1 ? x0.t0n : 0.0), 0.0);
+            double2 wyn = make_double2(i == 0 ? x0.tn0 : (i == n0 - 1 ? x0.tnn : 0.0), 0.0);
+            if (mid && x0.rows) {
+                wy0 = x0.vec[static_cast<int64_t>(nc) * N0 + i - 1];
+                wyn = x0.vec[static_cast<int64_t>(nc + 1) * N0 + i - 1];
+            }
+            int ce = -1;  // the boundary / replaced row this is, if any
+#pragma unroll
+            for (int c = 0; c < XG_MAXC; ++c)
+                if (c < nc && i == x0.cidx[c]) ce = c;
+#pragma unroll
+            for (int m = 0; m < XG2_MU; m += 2) {
+                const double ua = t + mu[m], ub = t + mu[m + 1];
+                const double R = zero ? 0.0 : rcp_nr(ua * ub);
+                const double rr[2] = {ub * R, ua * R};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const double2 v = make_double2(g.x * rr[h], g.y * rr[h]);
+#pragma unroll
+                    for (int c = 0; c < XG_MAXC; ++c) xg_fma<CPLX>(uP[c][m + h], wP[c], v);
+                    xg_fma<CPLX>(uY[0][m + h], wy0, v);
+                    xg_fma<CPLX>(uY[1][m + h], wyn, v);
+#pragma unroll
+                    for (int c = 0; c < XG_MAXC; ++c)
+                        if (c == ce) uE[c][m + h] = v;
+                }
+            }
+        }
+        for (int m = 0; m < XG2_MU && k0 + m < K; ++m) {
+            double2 S[XG2_NE];
+#pragma unroll
+            for (int q = 0; q < XG2_NE; ++q) S[q] = make_double2(0.0, 0.0);
+            if (active) {
+                for (int c = 0; c < nc; ++c) {
+                    S[c] = cmulc(uE[c][m], uP[c][m]);  // conj(u_P) v_c
+                    for (int c2 = 0; c2 < nc; ++c2) S[XG_MAXC + c * XG_MAXC + c2] = cmulc(uE[c2][m], uE[c][m]);
+                }
+                S[XG2_NE - 2] = make_double2(uY[0][m].x * uY[0][m].x + uY[0][m].y * uY[0][m].y, 0.0);
+                S[XG2_NE - 1] = make_double2(uY[1][m].x * uY[1][m].x + uY[1][m].y * uY[1][m].y, 0.0);
+            }
+#pragma unroll
+            for (int q = 0; q < XG2_NE; ++q) {
+                double2 v = S[q];
+                for (int w = 32; w > 0; w >>= 1) {
+                    v.x += __shfl_xor(v.x, w, 64);
+                    v.y += __shfl_xor(v.y, w, 64);
+                }
+                S[q] = v;
+            }
+            if (lane == 0) {
+                double2* dst = part + ((static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * K + k0 + m) * XG2_NE;
+#pragma unroll
+                for (int q = 0; q < XG2_NE; ++q) dst[q] = S[q];
+            }
+        }
     }
-    if (threadIdx.x == 0) part[bl * XG2_PARTS + blockIdx.x] = red[0];
 }
 
-// G[b][k] = sum N / (sum D)^2 over the parts in order.
-__global__ void k_xg2_final(const double2* __restrict__ part, int k, int K, int64_t b0, double* G) {
-    const int64_t bl = blockIdx.y;  // one single-thread block per image of the chunk
-    double N = 0.0, D = 0.0;
-    for (int w = 0; w < XG2_PARTS; ++w) {
-        const double2 v = part[bl * XG2_PARTS + w];
-        N += v.x;
-        D += v.y;
+// B1(x, z) = ell(x)^H M1 ell(z) of axis 1 for functional vectors laid out [P_c, v_c, y0, yn].
+__device__ __forceinline__ double2 xg_bilinear(const XgcvParams& x1, const double2* x, const double2* z) {
+    const int nc = x1.nc;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int c = 0; c < nc; ++c) {
+        acc = cadd(acc, cmulc(z[nc + c], x[c]));      // conj(x_P) z_e
+        acc = cadd(acc, cmulc(z[c], x[nc + c]));      // conj(x_e) z_P
+        for (int c2 = 0; c2 < nc; ++c2) {
+            const double2 p = cmulc(z[nc + c2], x[nc + c]);
+            acc.x += x1.gam[c][c2] * p.x;
+            acc.y += x1.gam[c][c2] * p.y;
+        }
     }
-    G[(b0 + bl) * K + k] = N / (D * D);
+    acc = cadd(acc, cmulc(z[2 * nc], x[2 * nc]));
+    acc = cadd(acc, cmulc(z[2 * nc + 1], x[2 * nc + 1]));
+    return acc;
 }
+
+// G(mu_k) of one image: the interior rows' ||T1 v_i||^2 plus the axis-0 low-rank form
+// sum_{p,q} M0[p,q] (S_pq + B1(ell1(u_p), ell1(u_q))) over (sum sigma)^2, with
+// ell1(u_p) = sum_i lambda_p[i] ell1(v_i) from the row pass.  Block (k, image): lane t
+// owns the weighted row sum (p, q) = (t / k1, t % k1); sums in a fixed order.
+__global__ __launch_bounds__(64) void k_xg2_combine(const double* __restrict__ rows_in, const double2* __restrict__ part,
+                                                    int nblk, int K, XgcvParams x0, XgcvParams x1, int n0, int64_t b0,
+                                                    double* G) {
+    __shared__ double2 rt[2 * XG_MAXC + 2][2 * XG_MAXC + 2];   // ell1(u_p), p over [P_c, e_c, y0, yn]
+    __shared__ double2 Ssum[XG2_NE];
+    __shared__ double sums[2][64];
+    const int lane = threadIdx.x, k = blockIdx.x;
+    const int64_t y = blockIdx.y;
+    const int nc0 = x0.nc, k1 = 2 * x1.nc + 2, N0 = n0 - 2;
+    const double* rows = rows_in + y * static_cast<int64_t>(n0) * K * XG2_RW;
+    auto row = [&](int i) { return rows + (static_cast<int64_t>(i) * K + k) * XG2_RW; };
+    // interior rows' norms and the whole trace
+    double rs = 0.0, ds = 0.0;
+    for (int i = lane; i < n0; i += 64) {
+        const double* r = row(i);
+        if (i >= 1 && i <= N0) rs += r[XG2_RW - 2];
+        ds += r[XG2_RW - 1];
+    }
+    sums[0][lane] = rs;
+    sums[1][lane] = ds;
+    // weighted row sums of the functionals: P_c (c < nc0), then y0, yn
+    const int nw = nc0 + 2;
+    if (lane < nw * k1) {
+        const int p = lane / k1, q = lane - p * k1;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int i = 0; i < n0; ++i) {
+            const bool mid = i >= 1 && i <= N0;
+            double2 w = make_double2(0.0, 0.0);
+            if (p < nc0) {
+                if (mid) w = x0.vec[static_cast<int64_t>(p) * N0 + i - 1];
+            } else {
+                const int yy = p - nc0;  // 0: y0, 1: yn
+                if (i == 0) w.x = yy ? x0.tn0 : x0.t00;
+                else if (i == n0 - 1) w.x = yy ? x0.tnn : x0.t0n;
+                else if (x0.rows) w = x0.vec[static_cast<int64_t>(nc0 + yy) * N0 + i - 1];
+            }
+            const double* r = row(i);
+            acc = cadd(acc, cmul(w, make_double2(r[2 * q], r[2 * q + 1])));
+        }
+        const int slot = p < nc0 ? p : 2 * nc0 + (p - nc0);
+        rt[slot][q] = acc;
+    }
+    // ell1 of the e_c functionals: the rows themselves
+    if (lane < nc0 * k1) {
+        const int c = lane / k1, q = lane - c * k1;
+        const double* r = row(x0.cidx[c]);
+        rt[nc0 + c][q] = make_double2(r[2 * q], r[2 * q + 1]);
+    }
+    // S over the column blocks, in order
+    if (lane < XG2_NE) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int w = 0; w < nblk; ++w) acc = cadd(acc, part[((y * nblk + w) * K + k) * XG2_NE + lane]);
+        Ssum[lane] = acc;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        double rsum = 0.0, dsum = 0.0;
+        for (int t = 0; t < 64; ++t) {
+            rsum += sums[0][t];
+            dsum += sums[1][t];
+        }
+        double num = rsum;
+        for (int c = 0; c < nc0; ++c) {
+            const double2 a = cadd(Ssum[c], xg_bilinear(x1, rt[c], rt[nc0 + c]));
+            num += 2.0 * a.x;
+            for (int c2 = 0; c2 < nc0; ++c2) {
+                const double2 e = cadd(Ssum[XG_MAXC + c * XG_MAXC + c2], xg_bilinear(x1, rt[nc0 + c], rt[nc0 + c2]));
+                num += x0.gam[c][c2] * e.x;
+            }
+        }
+        num += Ssum[XG2_NE - 2].x + xg_bilinear(x1, rt[2 * nc0], rt[2 * nc0]).x;
+        num += Ssum[XG2_NE - 1].x + xg_bilinear(x1, rt[2 * nc0 + 1], rt[2 * nc0 + 1]).x;
+        G[(b0 + y) * K + k] = num / (dsum * dsum);
+    }
+}
+
+// ------------------------------------------------------------------- exact GCV, 2D
 
 __global__ __launch_bounds__(64) void k_xg2_argmin(const double* __restrict__ G, GcvOut o) {
     const int64_t b = blockIdx.x;
@@ -849,52 +1025,51 @@ extern "C" ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const v
     return check_hip(hipGetLastError(), "ht_gcv_scan finalize launch");
 }
 
-// Eq. gcv for images: per grid value, X = sigma ghat, Y = T^(2) X by the plan's forward
-// transform, G = ||Y||^2 / (sum sigma)^2.  Images in chunks of at most 256 MiB of
-// workspace, allocated on the stream.
+// Eq. gcv for images, ||T0 V T1^T||^2 with V = sigma ghat, from the structure of both axes:
+// ||T0 W||^2 over the columns of W = V T1^T is the interior rows' ||T1 v_i||^2 plus the
+// axis-0 low-rank form of the functionals of W's columns, which are T1 applied to the
+// weighted row sums u_p = sum_i lambda_p[i] v_i; so ||.||^2 = sum_{i interior} ||T1 v_i||^2
+// + sum_{p,q} M0[p,q] (<u_p, u_q>_interior + ell1(u_p)^H M1 ell1(u_q)).  Row pass (the 1D
+// kernel on every row, emitting its functionals), column pass (u_p over the interior
+// columns and their products), combination per grid value.  Images in chunks of at most
+// 256 MiB of row-pass workspace, allocated on the stream.
 static ht_status gcv_exact_2d(const ht_plan* plan, const void* coeff, const Spec& sp, GcvOut o, int64_t batch,
                               hipStream_t stream) {
-    const int64_t img = sp.per_item;
-    const size_t xb = plan->cplx ? sizeof(double2) : sizeof(double);
-    int64_t chunk = (static_cast<int64_t>(1) << 28) / (img * static_cast<int64_t>(xb + sizeof(double)));
+    const int n0 = plan->ax[0].n, n1 = plan->ax[1].n, K = o.K;
+    const int64_t per_img = static_cast<int64_t>(n0) * K * XG2_RW;
+    int64_t chunk = (static_cast<int64_t>(1) << 25) / per_img;  // 2^25 doubles = 256 MiB
     chunk = chunk < 1 ? 1 : (chunk > batch ? batch : chunk);
-    if (chunk > plan->max_batch) chunk = plan->max_batch;
-    void* X = nullptr;
-    double* Y = nullptr;
+    const int nblk = (n1 - 2 + 63) / 64;
+    double* rows = nullptr;
     double2* part = nullptr;
     double* Gb = o.G;
-    bool ok = hipMallocAsync(&X, xb * img * chunk, stream) == hipSuccess &&
-              hipMallocAsync(reinterpret_cast<void**>(&Y), sizeof(double) * img * chunk, stream) == hipSuccess &&
-              hipMallocAsync(reinterpret_cast<void**>(&part), sizeof(double2) * XG2_PARTS * chunk, stream) == hipSuccess;
-    if (ok && !Gb) ok = hipMallocAsync(reinterpret_cast<void**>(&Gb), sizeof(double) * o.K * batch, stream) == hipSuccess;
+    bool ok = hipMallocAsync(reinterpret_cast<void**>(&rows), sizeof(double) * per_img * chunk, stream) == hipSuccess &&
+              hipMallocAsync(reinterpret_cast<void**>(&part), sizeof(double2) * chunk * nblk * K * XG2_NE, stream) ==
+                  hipSuccess;
+    if (ok && !Gb) ok = hipMallocAsync(reinterpret_cast<void**>(&Gb), sizeof(double) * K * batch, stream) == hipSuccess;
     ht_status st = ok ? HT_OK : fail(HT_ERR_OOM, "ht_gcv_scan_exact: workspace allocation failed");
+    const bool cp = plan->cplx != 0;
     for (int64_t b0 = 0; st == HT_OK && b0 < batch; b0 += chunk) {
-        const int64_t nb = batch - b0 < chunk ? batch - b0 : chunk;
-        const int64_t total = nb * img;
-        const void* cf = static_cast<const char*>(coeff);
-        for (int k = 0; st == HT_OK && k < o.K; ++k) {
-            hipLaunchKernelGGL(k_xg2_scale, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream, sp, cf,
-                               o.mus, o.mu_stride, k, b0, X, total);
-            st = check_hip(hipGetLastError(), "ht_gcv_scan_exact scale launch");
-            if (st != HT_OK) break;
-            st = ht_transform_fwd(plan, X, Y, nb, stream);
-            if (st != HT_OK) break;
-            hipLaunchKernelGGL(k_xg2_partial, dim3(XG2_PARTS, static_cast<unsigned>(nb)), dim3(256), 0, stream, sp,
-                               o.mus, o.mu_stride, k, b0, static_cast<const double*>(Y), part);
-            st = check_hip(hipGetLastError(), "ht_gcv_scan_exact partial launch");
-            if (st != HT_OK) break;
-            hipLaunchKernelGGL(k_xg2_final, dim3(1, static_cast<unsigned>(nb)), dim3(1), 0, stream,
-                               static_cast<const double2*>(part), k, o.K, b0, Gb);
-            st = check_hip(hipGetLastError(), "ht_gcv_scan_exact final launch");
-        }
+        const unsigned nb = static_cast<unsigned>(batch - b0 < chunk ? batch - b0 : chunk);
+        hipLaunchKernelGGL((cp ? k_gcv_exact<true, true> : k_gcv_exact<false, true>), dim3(n0, nb), dim3(XG_THREADS), 0,
+                           stream, sp, coeff, o, plan->xg[1], n1, b0, rows);
+        st = check_hip(hipGetLastError(), "ht_gcv_scan_exact row launch");
+        if (st != HT_OK) break;
+        hipLaunchKernelGGL(cp ? k_xg2_cols<true> : k_xg2_cols<false>, dim3(nblk, nb, (K + XG2_MU - 1) / XG2_MU), dim3(64),
+                           0, stream, sp, coeff,
+                           o.mus, o.mu_stride, K, plan->xg[0], n0, n1, b0, part);
+        st = check_hip(hipGetLastError(), "ht_gcv_scan_exact column launch");
+        if (st != HT_OK) break;
+        hipLaunchKernelGGL(k_xg2_combine, dim3(K, nb), dim3(64), 0, stream, static_cast<const double*>(rows),
+                           static_cast<const double2*>(part), nblk, K, plan->xg[0], plan->xg[1], n0, b0, Gb);
+        st = check_hip(hipGetLastError(), "ht_gcv_scan_exact combine launch");
     }
     if (st == HT_OK) {
         hipLaunchKernelGGL(k_xg2_argmin, dim3(static_cast<unsigned>(batch)), dim3(64), 0, stream,
                            static_cast<const double*>(Gb), o);
         st = check_hip(hipGetLastError(), "ht_gcv_scan_exact argmin launch");
     }
-    if (X) (void)hipFreeAsync(X, stream);
-    if (Y) (void)hipFreeAsync(Y, stream);
+    if (rows) (void)hipFreeAsync(rows, stream);
     if (part) (void)hipFreeAsync(part, stream);
     if (Gb && Gb != o.G) (void)hipFreeAsync(Gb, stream);
     return st;
@@ -908,6 +1083,9 @@ extern "C" ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, c
     for (int a = 0; a < plan->ndim; ++a)
         if (plan->ax[a].kind == HT_KIND_F3)
             return fail(HT_ERR_UNSUPPORTED, "ht_gcv_scan_exact: not for the degree-3 Fourier kind");
+    if (plan->ndim == 2 && !plan->xg_mem[0])  // periodic / reflective: eq. gcv2 is eq. gcv
+        return ht_gcv_scan(plan, coeff, d, s, eig_batch, layout, mu_grid, K, grid_per_item, G, k_best, mu_best, batch,
+                           stream);
     if (plan->ndim == 2) {
         if (K < 1 || K > 1024) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: K must be in [1, 1024]");
         if (batch < 0 || batch > plan->max_batch)
@@ -920,7 +1098,7 @@ extern "C" ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, c
         GcvOut o{mu_grid, grid_per_item ? static_cast<int64_t>(K) : 0, K, G, k_best, mu_best};
         return gcv_exact_2d(plan, coeff, sp, o, batch, stream);
     }
-    if (!plan->xg_mem)  // periodic / reflective: T is unitary and eq. gcv2 is eq. gcv
+    if (!plan->xg_mem[0])  // periodic / reflective: T is unitary and eq. gcv2 is eq. gcv
         return ht_gcv_scan(plan, coeff, d, s, eig_batch, layout, mu_grid, K, grid_per_item, G, k_best, mu_best, batch,
                            stream);
     if (K < 1 || K > 1024) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: K must be in [1, 1024]");
@@ -931,7 +1109,8 @@ extern "C" ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, c
     if (st != HT_OK) return st;
     const Spec sp = make_spec(plan, d, s, eig_batch, HT_SPECTRUM_FULL);
     GcvOut o{mu_grid, grid_per_item ? static_cast<int64_t>(K) : 0, K, G, k_best, mu_best};
-    hipLaunchKernelGGL(plan->cplx ? k_gcv_exact<true> : k_gcv_exact<false>, dim3(static_cast<unsigned>(batch)),
-                       dim3(XG_THREADS), 0, stream, sp, coeff, o, plan->xg, plan->ax[0].n);
+    hipLaunchKernelGGL((plan->cplx ? k_gcv_exact<true, false> : k_gcv_exact<false, false>),
+                       dim3(static_cast<unsigned>(batch)), dim3(XG_THREADS), 0, stream, sp, coeff, o, plan->xg[0],
+                       plan->ax[0].n, static_cast<int64_t>(0), static_cast<double*>(nullptr));
     return check_hip(hipGetLastError(), "ht_gcv_scan_exact launch");
 }
