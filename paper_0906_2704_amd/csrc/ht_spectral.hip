@@ -443,20 +443,36 @@ __global__ __launch_bounds__(GCV_THREADS) void k_gcv_partial(Spec sp, const void
     gcv_accumulate(sp, coeff, b, e0, e1, mus, o.K, part + (b * gridDim.x + w) * o.K, stage, red);
 }
 
+// Sum of the partial (N, D) of every grid value over the parts: block (group of 8 grid
+// values, item); 32 lanes per grid value each add the parts w = lane, lane + 32, ... in
+// order, then a fixed butterfly over the 32 lanes; the total replaces part w = 0 (read by
+// this block only).
+constexpr int GCV_RK = GCV_THREADS / 32;
+
+__global__ __launch_bounds__(GCV_THREADS) void k_gcv_reduce(int K, int64_t nparts, double2* part) {
+    const int64_t b = blockIdx.y;
+    const int g = threadIdx.x / 32, lane = threadIdx.x & 31;
+    const int k = blockIdx.x * GCV_RK + g;
+    const int kk = k < K ? k : K - 1;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t w = lane; w < nparts; w += 32) {
+        const double2 v = part[(b * nparts + w) * K + kk];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    for (int off = 16; off > 0; off >>= 1) {
+        acc.x += __shfl_xor(acc.x, off, 32);
+        acc.y += __shfl_xor(acc.y, off, 32);
+    }
+    if (lane == 0 && k < K) part[(b * nparts) * K + k] = acc;
+}
+
 __global__ __launch_bounds__(GCV_THREADS) void k_gcv_finalize(GcvOut o, int64_t nparts, const double2* __restrict__ part) {
     __shared__ double2 sums[1024];
     __shared__ double Gs[1024];
     __shared__ int kshared;
     const int64_t b = blockIdx.x;
-    for (int k = threadIdx.x; k < o.K; k += GCV_THREADS) {
-        double2 acc = make_double2(0.0, 0.0);
-        for (int64_t w = 0; w < nparts; ++w) {
-            const double2 v = part[(b * nparts + w) * o.K + k];
-            acc.x += v.x;
-            acc.y += v.y;
-        }
-        sums[k] = acc;
-    }
+    for (int k = threadIdx.x; k < o.K; k += GCV_THREADS) sums[k] = part[(b * nparts) * o.K + k];
     __syncthreads();
     const double* mus = o.mus + b * o.mu_stride;
     gcv_finish(sums, o.K, mus, o.G ? o.G + b * o.K : nullptr, o.kbest + b,
@@ -1020,6 +1036,10 @@ extern "C" ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const v
     hipLaunchKernelGGL(k_gcv_partial, dim3(static_cast<unsigned>(nw), static_cast<unsigned>(batch)), dim3(GCV_THREADS), 0,
                        stream, sp, coeff, o, span, part);
     ht_status st = check_hip(hipGetLastError(), "ht_gcv_scan partial launch");
+    if (st != HT_OK) return st;
+    hipLaunchKernelGGL(k_gcv_reduce, dim3(static_cast<unsigned>((K + GCV_RK - 1) / GCV_RK), static_cast<unsigned>(batch)),
+                       dim3(GCV_THREADS), 0, stream, static_cast<int>(K), nw, part);
+    st = check_hip(hipGetLastError(), "ht_gcv_scan reduce launch");
     if (st != HT_OK) return st;
     hipLaunchKernelGGL(k_gcv_finalize, dim3(static_cast<unsigned>(batch)), dim3(GCV_THREADS), 0, stream, o, nw, part);
     return check_hip(hipGetLastError(), "ht_gcv_scan finalize launch");
