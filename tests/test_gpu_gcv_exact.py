@@ -196,3 +196,26 @@ def test_exact_vs_approximate_choice_on_the_disk_experiment(ht):
     print("k approximate %s exact %s; mean RRE approximate %.5f exact %.5f"
           % (ka.cpu().tolist(), ke.cpu().tolist(), np.mean(ra), np.mean(re)))
     assert np.all(np.isfinite(re))
+
+
+def test_exact_gcv_2d_odd_grid_per_image_and_small_image(ht):
+    """Odd K below the column pass's group of 8, one grid per image, and an image of the
+    smallest size (5 x 6) with T_F (complex)."""
+    for (n0, n1), kind, sym in (((40, 37), "C", True), ((5, 6), "F", False)):
+        plan = ht.Plan((n0, n1), 2, psf_symmetric=sym, max_batch=2)
+        rng = np.random.default_rng(n0)
+        h0, c0 = (np.array([0.2, 0.6, 0.2]), 1) if sym else (np.array([0.5, 0.3, 0.2]), 1)
+        h1, c1 = (np.array([0.25, 0.5, 0.25]), 1) if sym else (np.array([0.6, 0.4]), 0)
+        d, s = ht.ht_eigs(plan, to_dev(np.concatenate([h0, h1])), [len(h0), len(h1)], [c0, c1], "D2")
+        D = twod.eigs2d_separable(kind, kind, n0, n1, h0, c0, h1, c1)
+        S = twod.smooth2d(kind, kind, n0, n1, "D2")
+        G = rng.standard_normal((2, n0, n1))
+        ghat = ht.ht_transform_inv(plan, to_dev(G))
+        grids = np.stack([synth.mu_grid(-5.0 + b, -1.0 + b, 7) for b in range(2)])
+        Gx, kx, mx = ht.ht_gcv_scan_exact(plan, ghat, d, s, to_dev(grids))
+        for b in range(2):
+            Go = twod.gcv2d_exact_values(kind, kind, twod.inverse2d(kind, kind, G[b]), D, S, grids[b])
+            err = np.max(np.abs(Gx[b].cpu().numpy() - Go) / Go)
+            print("%s %dx%d image %d: max rel err %.2e" % (kind, n0, n1, b, err))
+            assert err < 1e-9
+            assert float(mx[b]) == grids[b][int(kx[b])]
