@@ -14,15 +14,16 @@
  *   - All array arguments are DEVICE pointers owned by the caller, except where a
  *     parameter is documented as a host array.  The library never frees caller memory.
  *   - Calls are asynchronous on the given HIP stream (0 = legacy default stream) and
- *     allocate nothing: a plan owns every table and workspace it needs.
+ *     allocate nothing: a plan owns every table and workspace it needs (one exception:
+ *     ht_gcv_scan_exact on a 2D plan, documented there).
  *   - Arguments are validated on the host before anything is launched; on error nothing
  *     is launched and a status other than HT_OK is returned.  ht_last_error() returns a
  *     thread-local message describing the most recent failure.  No exception crosses the
  *     ABI.  With batch = 0 a call validates its sizes, launches nothing and returns
  *     HT_OK; its array arguments may then be NULL.
  *   - Signals are real float64.  Coefficient vectors ("coeff"), filtered coefficients and
- *     eigenvalues d are float64 for the real kinds (AR, C, DST2, DST3) and interleaved
- *     complex128 (re, im) for the kinds F and P.  Coefficients are ordered like the
+ *     eigenvalues d are float64 for the real kinds (AR, C, DST2, DST3, R) and interleaved
+ *     complex128 (re, im) for the kinds F, P and F3.  Coefficients are ordered like the
  *     columns of T: [first polynomial column, the n-2 core columns, last polynomial
  *     column]; for the comparators P and R, the n core columns.
  *   - A batch of 1D signals is a contiguous [batch][n] array; a batch of images is
@@ -44,7 +45,7 @@ typedef enum {
     HT_OK = 0,
     HT_ERR_INVALID_ARG = 1,   /* null pointer, size out of range, bad enum value          */
     HT_ERR_UNSUPPORTED = 2,   /* e.g. a nonsymmetric PSF with a degree that needs symmetry */
-    HT_ERR_PSF_TOO_WIDE = 3,  /* 2m+1 > n-2 (eq. jcf requires 2m+1 <= n-2)                 */
+    HT_ERR_PSF_TOO_WIDE = 3,  /* 2m+1 > n-2 (eq. jcf requires 2m+1 <= n-2; n for P, R)     */
     HT_ERR_SINGULAR = 4,      /* a boundary capacitance matrix is singular                 */
     HT_ERR_NONFINITE = 5,     /* non-finite data detected                                  */
     HT_ERR_HIP = 6,           /* a HIP runtime call failed                                 */
@@ -108,7 +109,7 @@ ht_status ht_plan_create(int ndim, const int64_t* n /* host [ndim] */, int degre
 ht_status ht_plan_destroy(ht_plan* plan);
 /* Kind of axis `axis` (0 or 1), or -1 on a bad argument. */
 int ht_plan_kind(const ht_plan* plan, int axis);
-/* 1 if coefficients / eigenvalues are complex128 (kind F on any axis), else 0. */
+/* 1 if coefficients / eigenvalues are complex128 (kinds F, P, F3), else 0. */
 int ht_plan_is_complex(const ht_plan* plan);
 
 /* Arithmetic of the core transform inside ht_transform_inv / ht_transform_fwd.
