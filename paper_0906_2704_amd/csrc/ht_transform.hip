@@ -39,6 +39,16 @@ __device__ __forceinline__ int64_t vbase(const View& v, int64_t b) {
     return (b / v.per_img) * v.img_stride + (b % v.per_img) * v.sig_stride;
 }
 
+// Workgroups are handed to the 8 XCDs round-robin in launch order; give each XCD a
+// contiguous range of vectors instead, so that the column passes of a 2D transform (one
+// column per workgroup, elements n1 apart) share their cache lines within one XCD's L2.
+// A bijection on [0, gridDim.x): the first 8 floor(g / 8) ids are permuted, the tail kept.
+__device__ __forceinline__ int64_t xcd_vector(unsigned w, unsigned g) {
+    const unsigned per = g / 8;
+    if (w >= 8 * per) return w;
+    return static_cast<int64_t>(w % 8) * per + w / 8;
+}
+
 __device__ __forceinline__ bool is_comparator(int kind) { return kind == HT_KIND_P || kind == HT_KIND_R; }
 __device__ __forceinline__ bool is_fourier(int kind) { return kind == HT_KIND_F || kind == HT_KIND_P || kind == HT_KIND_F3; }
 // the kind whose boundary columns and core a kind uses (F3 is T_F plus a rank-2 change)
@@ -65,7 +75,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_inverse(Axis ax, View i
     __shared__ C lds[P];
     __shared__ double2 corr[2];
     const int tid = threadIdx.x;
-    const int64_t b = blockIdx.x;
+    const int64_t b = xcd_vector(blockIdx.x, gridDim.x);
     const int n = ax.n, N = ax.N;
     const int64_t ib = vbase(in, b), ob = vbase(out, b);
     const bool cmp = is_comparator(ax.kind);
@@ -162,7 +172,7 @@ __global__ __launch_bounds__(fft_block_for(LOGP)) void k_forward(Axis ax, View i
     constexpr int BLOCK = fft_block_for(LOGP);
     __shared__ C lds[P];
     const int tid = threadIdx.x;
-    const int64_t b = blockIdx.x;
+    const int64_t b = xcd_vector(blockIdx.x, gridDim.x);
     const int n = ax.n, N = ax.N;
     const int64_t ib = vbase(in, b), ob = vbase(out, b);
     const bool cmp = is_comparator(ax.kind);
