@@ -303,19 +303,26 @@ __global__ __launch_bounds__(256) void k_prep_cols(Axis ax, PrepCols p) {
         if (p.mode == COL_INV) return row[j];
         return fma(row[0], p.c1[j], fma(row[p.n1 - 1], p.cj1[j], row[1 + j]));
     };
+    // blockIdx.z: a range of the contraction (the bfloat16 parts need no per-row scale, so
+    // their rows are split over several blocks); the first range writes the per-column data
+    const bool first = blockIdx.z == 0;
     if (ty == 0) {
         double x1 = 0.0, xn = 0.0;
         if (ok) {
             if (p.mode == COL_INV) {
                 boundary_solve(ax, col(0), col(1), col(n - 2), col(n - 1), x1, xn);
-                p.bout[z * p.img + j] = x1 + cross_at(p.cross, z * p.cross.zc_img, j);
-                p.bout[z * p.img + (n - 1) * p.ld + j] = xn + cross_at(p.cross, z * p.cross.zc_img + n - 1, j);
+                if (first) {
+                    p.bout[z * p.img + j] = x1 + cross_at(p.cross, z * p.cross.zc_img, j);
+                    p.bout[z * p.img + (n - 1) * p.ld + j] = xn + cross_at(p.cross, z * p.cross.zc_img + n - 1, j);
+                }
             } else {
                 x1 = col(0);
                 xn = col(n - 1);
             }
-            p.xbuf[z * p.xb_img + j] = x1;
-            p.xbuf[z * p.xb_img + p.xb_last + j] = xn;
+            if (first) {
+                p.xbuf[z * p.xb_img + j] = x1;
+                p.xbuf[z * p.xb_img + p.xb_last + j] = xn;
+            }
         }
         sx1[tx] = x1;
         sxn[tx] = xn;
@@ -338,11 +345,14 @@ __global__ __launch_bounds__(256) void k_prep_cols(Axis ax, PrepCols p) {
         mx = fmax(fmax(smax[0][tx], smax[1][tx]), fmax(smax[2][tx], smax[3][tx]));
         s = row_scale_exp<PREC>(mx, &e);
     }
-    if (ty == 0 && ok) p.scale[z * p.rows_per_img + j] = static_cast<float>(ldexp(1.0, -e));
+    if (ty == 0 && ok && first) p.scale[z * p.rows_per_img + j] = static_cast<float>(ldexp(1.0, -e));
     const int jj = tid >> 2, ks = (tid & 3) * 16;
     const int jw = blockIdx.x * 64 + jj;
     const int64_t orow = z * p.rows_per_img + jw;
-    for (int k0 = 0; k0 < p.Kp; k0 += 64) {
+    const int nchunk = p.Kp / 64, per = (nchunk + gridDim.z - 1) / gridDim.z;
+    const int kbeg = blockIdx.z * per * 64;
+    const int kend = (blockIdx.z + 1) * per * 64 < p.Kp ? (blockIdx.z + 1) * per * 64 : p.Kp;
+    for (int k0 = kbeg; k0 < kend; k0 += 64) {
 #pragma unroll 4
         for (int t = 0; t < 16; ++t) {
             const int kl = ty + 4 * t, k = k0 + kl;
@@ -797,7 +807,9 @@ static ht_status run_prep_rows(const Axis& ax, const PrepRows& pr, int64_t count
 
 template <int PREC>
 static ht_status run_prep_cols(const Axis& ax, const PrepCols& pc, int64_t batch, hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>((pc.ncols + 63) / 64), static_cast<unsigned>(batch));
+    // float16 parts carry a per-row scale from the whole row: one block per column tile
+    const unsigned ksplit = PREC == HT_PRECISION_F16X3 ? 1u : static_cast<unsigned>(std::min(8, pc.Kp / 64));
+    const dim3 grid(static_cast<unsigned>((pc.ncols + 63) / 64), static_cast<unsigned>(batch), ksplit);
     hipLaunchKernelGGL((k_prep_cols<PREC>), grid, dim3(256), 0, s, ax, pc);
     return check_hip(hipGetLastError(), "operand preparation launch");
 }
