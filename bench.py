@@ -879,7 +879,7 @@ def main():
                     help="run one device copy of this size (MiB) before timing, for HBM counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: there is no multi-GPU path "
               "(independent signals would be sharded by cost with no exchange).", file=sys.stderr)
         sys.exit(2)
 

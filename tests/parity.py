@@ -1,4 +1,4 @@
-"""Tolerances shared by the GPU parity tests (derived in DESIGN.md, "Tolerances").
+"""Tolerances shared by the GPU parity tests.
 
 Float64 vectors (coefficients, restorations, eigenvalues) are compared normwise:
 max_i |a_i - b_i| / max_i |b_i| <= 1e-12.
