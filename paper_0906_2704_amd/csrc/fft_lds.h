@@ -136,8 +136,17 @@ __host__ __device__ constexpr int fft_block_for(int logp) { return (1 << logp) /
 
 // One Stockham pass of radix R with Ns = product of the radices of earlier passes (Ns = 1:
 // no twiddles).  LAST: the outputs stay in the thread's own slots.
-template <int R, int DIR, int BLOCK, int SLOTS, bool LAST, class C>
+//
+// FIRST (the Ns = 1 pass, radix 8): thread t writes its eight outputs to the contiguous
+// elements 8t .. 8t+7, so in a plain layout the lanes of one store instruction are 128
+// bytes apart and meet in the same LDS banks.  This pass stores element e at
+// e ^ ((e >> 3) & 7) instead -- a permutation inside each aligned group of eight elements
+// that puts the eight lanes of a 128-byte row in eight different 16-byte bank groups --
+// and its read-back applies the same permutation (BLOCK is a multiple of 64, so every
+// read element tid + s * BLOCK has (e >> 3) & 7 = (tid >> 3) & 7).
+template <int R, int DIR, int BLOCK, int SLOTS, bool LAST, class C, bool FIRST = false>
 __device__ __forceinline__ void stockham_pass(C (&v)[SLOTS], C* lds, const C* __restrict__ tw, int Ns) {
+    static_assert(!FIRST || (R == 8 && !LAST && BLOCK % 64 == 0), "permuted first pass: radix 8, 64-aligned");
     constexpr int NB = SLOTS / R;  // butterflies per thread
     const int tid = threadIdx.x;
 #pragma unroll
@@ -176,6 +185,10 @@ __device__ __forceinline__ void stockham_pass(C (&v)[SLOTS], C* lds, const C* __
         if (LAST) {
 #pragma unroll
             for (int r = 0; r < R; ++r) v[c + r * NB] = u[r];
+        } else if constexpr (FIRST) {
+            const int sw = t & 7;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[t * R + (r ^ sw)] = u[r];
         } else {
             const int base = (t - k) * R + k;
 #pragma unroll
@@ -184,8 +197,9 @@ __device__ __forceinline__ void stockham_pass(C (&v)[SLOTS], C* lds, const C* __
     }
     if (!LAST) {
         __syncthreads();
+        const int rd = FIRST ? tid ^ ((tid >> 3) & 7) : tid;
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) v[s] = lds[tid + s * BLOCK];
+        for (int s = 0; s < SLOTS; ++s) v[s] = lds[rd + s * BLOCK];
         __syncthreads();
     }
 }
@@ -202,9 +216,11 @@ __device__ __forceinline__ void fft_slots(C (&v)[SL], C* lds, const C* __restric
     constexpr int NR8 = LOGP / 3;
     constexpr int REM = LOGP % 3;
     constexpr int NMID = REM ? NR8 : NR8 - 1;  // radix-8 passes that go through LDS
-    int Ns = 1;
+    static_assert(NMID >= 1, "the first pass goes through LDS");
+    stockham_pass<8, DIR, BL, SL, false, C, true>(v, lds, tw, 1);
+    int Ns = 8;
 #pragma unroll 1
-    for (int p = 0; p < NMID; ++p) {
+    for (int p = 1; p < NMID; ++p) {
         stockham_pass<8, DIR, BL, SL, false>(v, lds, tw, Ns);
         Ns *= 8;
     }

@@ -192,8 +192,19 @@ __device__ __forceinline__ void mlp_layer(const float* in, int K, const uint16_t
     __syncthreads();
 }
 
+// The 1024-, 2048- and 4096-point classes with 8 points per thread are held to 128
+// registers per lane (four waves per SIMD): two to eight workgroups then share a CU and
+// cover each other's barrier and memory waits, which pays for the spills this costs
+// (measured: 20 % less time in the 2048- and 4096-point classes; the 512-point class of
+// single-wave workgroups is slower so, and the 8192-point classes are bound by their LDS
+// to one workgroup per CU).
+template <int LOGP, int S, int SL>
+constexpr int restore_waves_per_eu() { return LOGP >= 10 && LOGP <= 12 && SL == 8 ? 4 : 1; }
+
 template <int LOGP, int S, int SL, int MODE>
-__global__ __launch_bounds__((1 << LOGP) / SL) void k_restore(RaggedArgs a, int cls, int start, int count) {
+__global__ __launch_bounds__((1 << LOGP) / SL)
+__attribute__((amdgpu_waves_per_eu(restore_waves_per_eu<LOGP, S, SL>())))
+void k_restore(RaggedArgs a, int cls, int start, int count) {
     constexpr int P = 1 << LOGP;
     constexpr int BLOCK = P / SL;
     // cross-part GCV reduction buffer: only 64-thread groups can need more than one pass
