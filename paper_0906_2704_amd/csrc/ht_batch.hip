@@ -218,14 +218,22 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
     __shared__ float s_pred;
     const int tid = threadIdx.x;
     double* scratch = a.scratch + static_cast<int64_t>(blockIdx.x) * MAX_N;
+    // Classes of 4096 points and more take their next queue entry while the current signal
+    // runs (the atomic's latency then hides behind the signal's own loads); their long
+    // queues per workgroup make the one reserved entry irrelevant to the load balance,
+    // which it does disturb for the short queues of the small classes.
+    constexpr bool PREFETCH = LOGP >= 12;
+    int nxt = 0;
+    if (PREFETCH && tid == 0) nxt = atomicAdd(&a.counters[cls], 1);
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(&a.counters[cls], 1);
+        if (tid == 0) s_item = PREFETCH ? nxt : atomicAdd(&a.counters[cls], 1);
         __syncthreads();
         // uniform across the workgroup: keeps the signal's descriptor and table pointers in
         // scalar registers
         const int qi = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (qi >= count) break;
+        if (PREFETCH && tid == 0) nxt = atomicAdd(&a.counters[cls], 1);
         const RSig sg = uniform_load(a.sigs + start + qi);
         const Axis ax = uniform_load(a.axes + sg.axis);
         // read per signal so that no twiddle address is hoisted out of the queue loop
