@@ -306,10 +306,16 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
 
         __builtin_amdgcn_sched_barrier(0);
         // ---- eigenvalues on the signal's grid: cos(pi r / den), r <= den, staged in LDS
+        // (the learned pass reads d from the feature pass and needs only cos(pi num / den)
+        // at its own frequency for s: it reads those straight from the table, coalesced,
+        // and skips the staging)
+        const bool staged = !(MODE == MODE_LEARNED && a.spec);
         double* ctab = reinterpret_cast<double*>(lds);
-        __syncthreads();
-        for (int r = tid; r <= den; r += BLOCK) ctab[r] = ax.tcos[r];
-        __syncthreads();
+        if (staged) {
+            __syncthreads();
+            for (int r = tid; r <= den; r += BLOCK) ctab[r] = ax.tcos[r];
+            __syncthreads();
+        }
         double z0 = 0.0;
         for (int t = 0; t < sg.psf_len; ++t) z0 += h[t];
         const bool ident = a.norm == HT_NORM_IDENTITY;
@@ -350,7 +356,8 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
                 }
                 dj[k] = acc;
                 const int rn = num % per;
-                sj[k] = ident ? 1.0 : 2.0 - 2.0 * ctab[rn <= den ? rn : per - rn];
+                const int rc = rn <= den ? rn : per - rn;
+                sj[k] = ident ? 1.0 : 2.0 - 2.0 * (staged ? ctab[rc] : ax.tcos[rc]);
             }
         }
         __syncthreads();
