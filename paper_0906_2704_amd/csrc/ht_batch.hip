@@ -323,6 +323,14 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
         const int per = 2 * den;
         const int pc = sg.psf_center, pl = sg.psf_len;
         const bool centred = 2 * pc + 1 == pl;
+        // Mirror pairs (centred masks): the frequency of index mj = (C: N - j, sine: N - 1 - j)
+        // is pi - theta_j, where cos(t (pi - theta)) = (-1)^t cos(t theta); summing the even
+        // and the odd taps apart gives d_j = E + O and d_mj = E - O in one pass over the
+        // taps.  The lower index of a pair computes both and leaves d_mj in LDS behind the
+        // staged table (den + 1 + N <= 2P doubles) for the owner of mj.
+        const bool pair = staged && centred;
+        double* dmir = ctab + den + 1;
+        auto mirror = [&](int j) { return kind == HT_KIND_C ? N - j : N - 1 - j; };
         double dj[SL], sj[SL];
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
@@ -331,21 +339,34 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             sj[k] = s_poly;
             if (j < N && j >= rank) {
                 const int num = kind == HT_KIND_C ? j : j + 1;  // frequency pi * num / den
-                double acc;
+                const int mj = mirror(j);
+                const bool lead = pair && mj > j && mj < N && mj >= rank;
+                const bool follow = pair && mj < j && mj >= rank;
+                double acc = 0.0;
                 if (MODE == MODE_LEARNED && a.spec) {
                     acc = a.spec[sg.off + 1 + j];  // left by the feature pass
+                } else if (follow) {
+                    // d_j arrives from the owner of mj below
                 } else if (centred) {
-                    // Re z = h_0 + sum_{t>0} (h_t + h_{-t}) cos(t theta)
-                    acc = h[pc];
-                    int r = 0;
-                    for (int t = 1; t <= pc; ++t) {
+                    // Re z = h_0 + sum_{t>0} (h_t + h_{-t}) cos(t theta), even and odd t apart
+                    double ev = h[pc], od = 0.0;
+                    int r = 0, t = 1;
+                    for (; t + 1 <= pc; t += 2) {
                         r += num;
                         if (r >= per) r -= per;
-                        const double cv = ctab[r <= den ? r : per - r];
-                        acc = fma(h[pc + t] + h[pc - t], cv, acc);
+                        od = fma(h[pc + t] + h[pc - t], ctab[r <= den ? r : per - r], od);
+                        r += num;
+                        if (r >= per) r -= per;
+                        ev = fma(h[pc + t + 1] + h[pc - t - 1], ctab[r <= den ? r : per - r], ev);
                     }
+                    if (t <= pc) {
+                        r += num;
+                        if (r >= per) r -= per;
+                        od = fma(h[pc + t] + h[pc - t], ctab[r <= den ? r : per - r], od);
+                    }
+                    acc = ev + od;
+                    if (lead) dmir[mj] = ev - od;
                 } else {
-                    acc = 0.0;
                     int r = static_cast<int>((static_cast<int64_t>(per) * pl - static_cast<int64_t>(pc) * num) % per);
                     for (int t = 0; t < pl; ++t) {
                         const double cv = ctab[r <= den ? r : per - r];
@@ -361,6 +382,17 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             }
         }
         __syncthreads();
+        if (pair) {  // uniform: the mirrored halves, then LDS is free for the next phase
+#pragma unroll
+            for (int k = 0; k < SL; ++k) {
+                const int j = tid + k * BLOCK;
+                if (j < N && j >= rank) {
+                    const int mj = mirror(j);
+                    if (mj < j && mj >= rank) dj[k] = dmir[j];
+                }
+            }
+            __syncthreads();
+        }
 
         __shared__ float s_feat[NFEAT];
         if constexpr (MODE == MODE_FEATURES || MODE == MODE_FUSED) {
