@@ -397,26 +397,37 @@ def _dense_inverse(kind, n):
         CLD if is_complex(kind) else LD)
 
 
-def row_of_T(kind, n, i):
-    """Row i (0-based) of T, computed on its own in O(n) (for sampled checks at large n)."""
-    if n <= 2048:
+def row_of_T(kind, n, i, rowwise=None):
+    """Row i (0-based) of T.  With rowwise (the default for n > 2048) the row is computed
+    on its own from the entry formulas in O(n) (for sampled checks at sizes where the dense
+    matrix is too large); otherwise it is read from transform_matrix."""
+    if rowwise is None:
+        rowwise = n > 2048
+    if not rowwise:
         return transform_matrix(kind, n)[i]
+    if kind in ("P", "R"):
+        k = np.arange(n, dtype=np.int64)
+        if kind == "P":  # column k of F^H: exp(+2 pi i (row) k / n) / sqrt(n)
+            c, s = cos_sin_pi(2 * i * k, n)
+            return (c + 1j * s) / np.sqrt(LD(n))
+        c, _ = cos_sin_pi(k * (2 * i + 1), 2 * n)  # column k of C^T: row k of C
+        return c * np.where(k == 0, np.sqrt(LD(1) / LD(n)), np.sqrt(LD(2) / LD(n)))
     N = n - 2
+    j = np.arange(1, N + 1, dtype=np.int64)  # core column j (1-based), matrix column j
     if kind in ("AR", "DST2", "DST3"):
         row = np.zeros(n, dtype=LD)
         p = ar_p(n)
         row[0], row[n - 1] = p[i], p[n - 1 - i]
         if 0 < i < n - 1:
-            j = np.arange(1, N + 1, dtype=np.int64)
-            _, s = cos_sin_pi(i * j, n - 1)
+            _, s = cos_sin_pi(i * j, n - 1)  # Q_{ij}, rows of Q sit on rows 2..n-1 of T
             row[1:n - 1] = np.sqrt(LD(2) / LD(n - 1)) * s
             if kind != "AR":
                 for c, bub in enumerate(dst_bubbles(n, degree_of(kind))):
                     row[1 + c] = bub[i - 1]
         return row
-    q = quad_q(kind, n)
-    j = np.arange(1, N + 1, dtype=np.int64)
-    r = i + 1
+    kq = "C" if kind == "C" else "F"
+    q = quad_q(kq, n)
+    r = i + 1  # 1-based row: the grid point x_{r-1}
     if kind == "C":
         c, _ = cos_sin_pi((2 * (r - 1) - 1) * (j - 1), 2 * N)
         w = np.where(j == 1, np.sqrt(LD(1) / LD(N)), np.sqrt(LD(2) / LD(N)))
@@ -426,5 +437,8 @@ def row_of_T(kind, n, i):
         c, s = cos_sin_pi(2 * (r - 2) * (j - 1), N)
         row = np.zeros(n, dtype=CLD)
         row[1:n - 1] = (c + 1j * s) / np.sqrt(LD(N))
+        if kind == "F3":  # column 3: sqrt(2/N) cos x; column n-1: the unit-norm cubic
+            row[2] = np.sqrt(LD(2)) * row[2].real
+            row[n - 2] = cubic_f3(n)[i]
     row[0], row[n - 1] = q[i], q[n - 1 - i]
     return row
