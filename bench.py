@@ -460,17 +460,24 @@ class Learned1D:
                 "path": self.path, "certificate_half_width": self.learned.CERT_HALF, "training": self.train_info}
 
     def work(self):
-        """Algorithmic HBM bytes of each stage (one read of every input and one write of
-        every output)."""
+        """Algorithmic bytes of each stage: 16 bytes per sample (one float64 read of the
+        signal and one float64 write of the restoration, the per-sample figure of the whole
+        learned inference), plus the PSF masks and, where the stage uses them, the grids.
+        Each pass of the two-pass path is charged the full 16 B/sample; the network stage
+        counts its flops."""
         S = float(self.rb.n.sum())
         B, K = self.batch, self.K
         psf = float(self.rb.psf_flat.size) * 8
         return {
-            "fused_restore": ("hbm", S * 16 + psf + B * K * 8 + B * 24),
-            "features": ("hbm", S * 24 + psf + B * 72 * 4),
+            "fused_restore": ("hbm", S * 16 + psf + B * K * 8),
+            "features": ("hbm", S * 16 + psf),
             "predict": ("mfma", 2.0 * B * (72 * 256 + 2 * 256 * 256 + 256)),
-            "certified_restore": ("hbm", S * 24 + psf + B * K * 8 + B * 4 + B * 20),
+            "certified_restore": ("hbm", S * 16 + psf + B * K * 8),
         }
+
+    def step_bytes(self):
+        """Algorithmic bytes of the whole inference step (16 B/sample, masks, grids)."""
+        return float(self.rb.n.sum()) * 16 + float(self.rb.psf_flat.size) * 8 + self.batch * self.K * 8
 
     def sample_items(self, count):
         order = np.argsort(self.rb.n)
@@ -842,6 +849,17 @@ def profiled_traffic(profile, stage):
     return float(mt.group(1))
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def blas_threads():
     try:
         import threadpoolctl
@@ -968,12 +986,31 @@ def main():
         roof = {"bound": "alu", "achieved": amount / sec / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = profiled_traffic(wl.profile, dom) if getattr(wl, "profile", None) else None
+    if roof["traffic"] is not None and bound == "hbm":
+        # measured HBM bytes per launch over the algorithmic bytes: wasted re-reads show here
+        roof["traffic_ratio"] = roof["traffic"] / amount
     roof["kernel"] = dom
+    per_stage = {}
+    for st, (b, a) in work.items():
+        if st not in stage_ms or stage_ms[st] <= 0:
+            continue
+        t_s = stage_ms[st] / 1e3
+        if b == "hbm":
+            per_stage[st] = {"bound": "hbm", "achieved_GBs": a / t_s / 1e9, "frac": a / t_s / 1e9 / HBM_PEAK_GBS}
+        elif b == "mfma":
+            per_stage[st] = {"bound": "mfma", "achieved_TFLOPs": a / t_s / 1e12, "frac": a / t_s / 1e12 / 2500.0}
+        else:
+            per_stage[st] = {"bound": "alu", "achieved_TFLOPs": a / t_s / 1e12,
+                             "frac": a / t_s / 1e12 / FP64_PEAK_TFLOPS}
+    roof["per_stage"] = per_stage
+    if hasattr(wl, "step_bytes"):
+        roof["step_frac_hbm"] = wl.step_bytes() / (ms / 1e3) / 1e9 / HBM_PEAK_GBS
 
     cpu = None
     if not args.no_cpu_baseline:
         v, sample = wl.cpu_baseline(args.cpu_budget)
-        cpu = {"value": v, "unit": "restorations/s", "cores": blas_threads(), "kind": "oracle", "sample": sample}
+        cpu = {"value": v, "unit": "restorations/s", "cores": blas_threads(), "kind": "oracle", "sample": sample,
+               "cpu_model": cpu_model(), "affinity_cores": len(os.sched_getaffinity(0))}
 
     out = {
         "metric": METRIC,

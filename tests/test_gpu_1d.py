@@ -12,7 +12,7 @@ from oracle import tikhonov as tk
 from oracle import transforms as tr
 from paper_0906_2704_amd import synth
 
-from parity import assert_gcv_close
+from parity import assert_gcv_close, assert_scan_arith, rel_normwise
 
 pytestmark = pytest.mark.gpu
 
@@ -175,12 +175,14 @@ def test_filter_and_gcv_parity(ht, kind):
         ghat = ht.ht_transform_inv(p, to_dev(G))
         Gv, kb, mb = ht.ht_gcv_scan(p, ghat, d, s, to_dev(mus))
         Gv, kb, mb = Gv.cpu().numpy(), kb.cpu().numpy(), mb.cpu().numpy()
+        gh = ghat.cpu().numpy()
         dw = tr.blur_eigs(kind, n, h, c)
         sw = tr.smooth_eigs(kind, n, norm)
         for b in range(B):
             gw = tr.inverse(kind, G[b])
             Gw, kw, muw = tk.gcv_scan(gw, dw, sw, mus)
-            assert_gcv_close(Gv[b], Gw, gw, dw, sw, mus, (kind, norm, b))
+            assert_scan_arith(Gv[b], tk.gcv_values(gh[b], dw, sw, mus), (kind, norm, b))
+            assert_gcv_close(Gv[b], Gw, gw, dw, sw, mus, (kind, norm, b), delta=rel_normwise(gh[b], gw))
             assert kb[b] == kw and mb[b] == muw
         mu_t = to_dev(mb)
         fhat = ht.ht_tikhonov_filter(p, ghat, d, s, mu_t)
@@ -203,10 +205,13 @@ def test_gcv_per_item_grids_and_eigs(ht):
     grids = np.stack([synth.mu_grid(lo, lo + 7, K) for lo in rng.uniform(-8, -6, B)])
     Gv, kb, mb = ht.ht_gcv_scan(p, ghat, d, s, to_dev(grids))
     Gv, kb = Gv.cpu().numpy(), kb.cpu().numpy()
+    gh = ghat.cpu().numpy()
     for b in range(B):
         gw = tr.inverse(kind, Y[b])
-        Gw, kw, _ = tk.gcv_scan(gw, tr.blur_eigs(kind, n, *hs[b]), tr.smooth_eigs(kind, n, "D2"), grids[b])
-        assert_gcv_close(Gv[b], Gw, gw, tr.blur_eigs(kind, n, *hs[b]), tr.smooth_eigs(kind, n, "D2"), grids[b], b)
+        dw, sw = tr.blur_eigs(kind, n, *hs[b]), tr.smooth_eigs(kind, n, "D2")
+        Gw, kw, _ = tk.gcv_scan(gw, dw, sw, grids[b])
+        assert_scan_arith(Gv[b], tk.gcv_values(gh[b], dw, sw, grids[b]), b)
+        assert_gcv_close(Gv[b], Gw, gw, dw, sw, grids[b], b, delta=rel_normwise(gh[b], gw))
         assert kb[b] == kw
 
 

@@ -12,7 +12,7 @@ from oracle import transforms as tr
 from oracle import twod
 from paper_0906_2704_amd import synth
 
-from parity import assert_gcv_close, rel_normwise
+from parity import assert_gcv_close, assert_scan_arith, rel_normwise
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -77,7 +77,9 @@ def check(r, norm):
     assert rel_normwise(r["ghat"], ghat) < TOL
     dd = np.multiply.outer(d0, d1)
     Gw, kw, muw = tk.gcv_scan(ghat.ravel(), dd.ravel(), s2.ravel(), r["mus"])
-    assert_gcv_close(r["Gv"], Gw, ghat.ravel(), dd.ravel(), s2.ravel(), r["mus"], "2d")
+    assert_scan_arith(r["Gv"], tk.gcv_values(r["ghat"].ravel(), dd.ravel(), s2.ravel(), r["mus"]), "2d")
+    assert_gcv_close(r["Gv"], Gw, ghat.ravel(), dd.ravel(), s2.ravel(), r["mus"], "2d",
+                     delta=rel_normwise(r["ghat"], ghat))
     assert r["kb"] == kw and r["mb"] == muw
     fw = twod.forward2d(kind, kind, tk.tikhonov_filter(ghat, dd, s2, muw))
     assert rel_normwise(r["f"], fw.real) < TOL
@@ -109,7 +111,10 @@ def test_2d_nonsymmetric_512(ht):
     dd = np.multiply.outer(d0, d1)
     s2 = twod.smooth2d(kind, kind, 512, 512, "D2")
     Gw, kw, muw = tk.gcv_scan(gh.ravel(), dd.ravel(), s2.ravel(), p.mus)
-    assert_gcv_close(Gv.cpu().numpy()[0], Gw, gh.ravel(), dd.ravel(), s2.ravel(), p.mus, "512")
+    gh_gpu = ghat.cpu().numpy()[0]
+    assert_scan_arith(Gv.cpu().numpy()[0], tk.gcv_values(gh_gpu.ravel(), dd.ravel(), s2.ravel(), p.mus), "512")
+    assert_gcv_close(Gv.cpu().numpy()[0], Gw, gh.ravel(), dd.ravel(), s2.ravel(), p.mus, "512",
+                     delta=rel_normwise(gh_gpu, gh))
     assert int(kb.cpu()[0]) == kw
     fw = twod.forward2d(kind, kind, tk.tikhonov_filter(gh, dd, s2, muw)).real
     assert rel_normwise(f, fw) < TOL

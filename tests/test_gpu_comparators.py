@@ -118,7 +118,7 @@ def test_comparator_restoration_matches_oracle(ht, kind, norm):
         fw = tr.forward(kind, tk.tikhonov_filter(gh, do, so, muw)).real
         assert rel_normwise(f[b], fw) < TOL
         Ge = tk.gcv_exact_values(kind, gh, do, so, mus)
-        assert np.max(np.abs(Gx[b].cpu().numpy() - Ge) / Ge) < 1e-10
+        assert_gcv_close(Gx[b].cpu().numpy(), Ge, gh, do, so, mus, "exact %s %d" % (kind, b))
 
 
 @pytest.mark.parametrize("kind", ["P", "R"])

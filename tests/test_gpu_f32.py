@@ -5,9 +5,8 @@ restoration (Laplacian, 128-point GCV) with its error against the oracle per res
 The core works in float32 on float64 inputs (boundary solve, corrections, eigenvalues, GCV
 sums and filter stay float64).  A float32 FFT convolution of length M has a normwise
 relative error of order log2(M) u (u = 2^-24), about 1e-6, relative to the vector it
-transforms: the coefficients for the inverse, the coefficients again for the forward (the
-forward transform's result can be much smaller than its input when the boundary columns
-cancel the core part, so the bound is stated against the input)."""
+transforms: the signal's coefficients for the inverse, and for the forward the result,
+stated against the norm of the output y (measured <= 5.5e-6)."""
 
 import numpy as np
 import pytest
@@ -18,11 +17,12 @@ from oracle import transforms as tr
 from oracle import twod
 from paper_0906_2704_amd import synth
 
-from parity import rel_normwise
+from parity import record, rel_normwise
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 TOL_CORE = 1e-5
+TOL_F_2D = 1.3e-4  # twice the measured 6.4e-5 of the 512 x 512 T_F (x) T_F restoration
 
 
 @pytest.fixture(scope="module")
@@ -57,9 +57,11 @@ def test_f32_core_1d(ht, degree, sym, family, kind, n):
     Yf = Yf.real if np.iscomplexobj(Yf) else Yf
     e_fwd = np.max(np.linalg.norm(Yg - Yf, axis=1) / np.linalg.norm(X, axis=1))
     e_fwd_y = np.max(np.linalg.norm(Yg - Yf, axis=1) / np.linalg.norm(Yf, axis=1))
-    print("f32 %s n=%d  inverse %.2e  forward %.2e (of ||x||) %.2e (of ||y||)" % (kind, n, e_inv, e_fwd, e_fwd_y))
+    record("f32 inverse %s n=%d" % (kind, n), e_inv, TOL_CORE)
+    record("f32 forward/||x|| %s n=%d" % (kind, n), e_fwd, TOL_CORE)
+    record("f32 forward/||y|| %s n=%d" % (kind, n), e_fwd_y, TOL_CORE)
     assert e_inv < TOL_CORE
-    assert e_fwd < TOL_CORE
+    assert e_fwd_y < TOL_CORE
 
 
 def test_f32_2d_512(ht):
@@ -87,7 +89,16 @@ def test_f32_2d_512(ht):
     rre_o = np.linalg.norm(fo - p.f_true) / np.linalg.norm(p.f_true)
     print("f32 512x512 T_F: ghat %.2e  G %.2e  k* %d (oracle %d)  f %.2e  RRE %.5f (oracle %.5f)"
           % (e_ghat, e_G, k, ko, e_f, rre, rre_o))
-    assert k == ko or G_o[k] <= G_o[ko] * (1 + 2 * e_G)
+    # the restoration's error is the coefficients' error passed through the filter, whose
+    # gain conj(d) / (|d|^2 + mu |s|^2) reaches max_i 1 / (2 sqrt(mu) |s_i|) on the high
+    # frequencies where the blurred coefficients are smallest: it exceeds 1e-5 (measured
+    # 6.4e-5, asserted at twice that); the derived first-order bound is printed beside it
+    gain = np.abs(dd) / (np.abs(dd) ** 2 + float(p.mus[k]) * ss ** 2)
+    e_f_derived = e_ghat * float(np.max(np.abs(gh_o)) * np.max(gain)) / float(np.max(np.abs(fo)))
+    record("f32 2d512 ghat", e_ghat, TOL_CORE)
+    record("f32 2d512 G", e_G, TOL_CORE)
+    record("f32 2d512 f", e_f, TOL_F_2D, k=k, ko=ko, derived=e_f_derived)
+    assert k == ko
     assert e_ghat < TOL_CORE
-    assert e_G < 10 * TOL_CORE
-    assert e_f < 10 * TOL_CORE
+    assert e_G < TOL_CORE
+    assert e_f < TOL_F_2D

@@ -21,6 +21,21 @@ from oracle import transforms as tr
 from oracle import twod
 from paper_0906_2704_amd import synth
 
+from parity import record
+
+
+def check_choice(k, Go):
+    """The chosen index is the oracle's first minimum, except where eq. gcv does not depend
+    on mu at all (every grid value gives the same G up to rounding: e.g. n = 5 with T_F and
+    the second difference, whose two non-polynomial core entries share |d| and s, so the
+    mu-dependence cancels between numerator and denominator); then every index is a
+    minimiser and the GPU's choice is only required to be one."""
+    ko = int(np.argmin(Go))
+    if np.ptp(Go) <= 1e-14 * np.min(Go):
+        assert 0 <= k < len(Go)
+    else:
+        assert k == ko, (k, ko)
+
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
@@ -76,10 +91,10 @@ def test_exact_gcv_parity(ht, degree, family, sym, kind, norm, n):
         Go = tk.gcv_exact_values(kind, ghat[b], d, s, mus)
         amp = max(amplification(kind, ghat[b], d, s, mu) for mu in mus[::8])
         err = np.max(np.abs(Gg[b] - Go) / Go)
-        print("  signal %d: max rel err %.2e (amplification %.1f)" % (b, err, amp))
-        assert err < 1e-12 * (1 + amp)
-        ko = int(np.argmin(Go))
-        assert kb[b] == ko or Go[kb[b]] <= Go[ko] * (1 + 2e-12 * (1 + amp))
+        record("gcv-exact %s %s n=%d signal %d" % (kind, norm, n, b), err, 1e-12, amp=amp,
+               k=int(kb[b]), ko=int(np.argmin(Go)))
+        assert err < 1e-12
+        check_choice(int(kb[b]), Go)
 
 
 def test_exact_gcv_per_item_grids_and_contract(ht):
@@ -93,7 +108,8 @@ def test_exact_gcv_per_item_grids_and_contract(ht):
     Gg, kb, mb = ht.ht_gcv_scan_exact(plan, to_dev(ghat), to_dev(d[None]), to_dev(s[None]), to_dev(grids))
     for b in range(4):
         Go = tk.gcv_exact_values("C", ghat[b], d, s, grids[b])
-        assert np.max(np.abs(Gg[b].cpu().numpy() - Go) / Go) < 1e-10
+        err = record("gcv-exact per-item grid %d" % b, np.max(np.abs(Gg[b].cpu().numpy() - Go) / Go), 1e-12)
+        assert err < 1e-12
         assert float(mb[b]) == grids[b][int(kb[b])]
 
 
@@ -167,11 +183,11 @@ def test_exact_gcv_2d_parity(ht, kind, norm, layout):
         V = sig * gh
         amp = np.sum(np.abs(V) ** 2) / np.sum(np.abs(twod.forward2d(kind, kind, V)) ** 2)
         err = np.max(np.abs(Gx[b] - Go) / Go)
-        print("%s %s %s image %d: max rel err %.2e (amplification %.1f)" % (kind, norm, layout, b, err, amp))
-        assert err < 1e-11 * (1 + amp)
-        ko = int(np.argmin(Go))
         k = int(kx[b])
-        assert k == ko or Go[k] <= Go[ko] * (1 + 1e-10)
+        record("gcv-exact-2d %s %s %s image %d" % (kind, norm, layout, b), err, 1e-12, amp=amp, k=k,
+               ko=int(np.argmin(Go)))
+        assert err < 1e-12
+        check_choice(k, Go)
         assert float(mx[b]) == mus[k]
 
 
@@ -216,6 +232,6 @@ def test_exact_gcv_2d_odd_grid_per_image_and_small_image(ht):
         for b in range(2):
             Go = twod.gcv2d_exact_values(kind, kind, twod.inverse2d(kind, kind, G[b]), D, S, grids[b])
             err = np.max(np.abs(Gx[b].cpu().numpy() - Go) / Go)
-            print("%s %dx%d image %d: max rel err %.2e" % (kind, n0, n1, b, err))
+            record("gcv-exact-2d odd %s %dx%d image %d" % (kind, n0, n1, b), err, 1e-9)
             assert err < 1e-9
             assert float(mx[b]) == grids[b][int(kx[b])]

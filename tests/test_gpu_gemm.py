@@ -24,11 +24,18 @@ from oracle import transforms as tr
 from oracle import twod
 from paper_0906_2704_amd import synth
 
-from parity import rel_normwise
+from parity import record, rel_normwise
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 TOL_PASS = {"bf16x3": 4.6e-5, "f16x3": 2e-6}
+# The 16 x 2048^2 restoration, per result: twice the largest value measured over images 0
+# and 15 (bfloat16: ghat 4.1e-8, G 1.6e-5, f 6.1e-4; float16: ghat 2.7e-8, G 1.25e-7,
+# f 2.1e-5).  They sit well inside the first-order bounds derived above (per-pass bound,
+# times the filter gain max d / (d^2 + mu) = 500 at mu = 1e-6, times ||g|| / ||f|| for f),
+# which the test prints beside them.
+TOL_16X2048 = {"bf16x3": {"ghat": 8.2e-8, "G": 3.2e-5, "f": 1.22e-3},
+               "f16x3": {"ghat": 5.4e-8, "G": 2.5e-7, "f": 4.2e-5}}
 CONFIGS = [(2, "paper", "C"), (1, "paper", "AR"), (2, "dst", "DST2"), (3, "paper+dst3", "DST3")]
 
 
@@ -165,8 +172,7 @@ def test_mixed_precision_16x2048(ht, prec, images3, oracle3):
         e_G = np.max(np.abs(Gi - o["G"]) / o["G"])
         k = int(kb[i])
         ko = int(np.argmin(o["G"]))
-        # k*: exact, or an equally good grid point within the G error
-        assert k == ko or o["G"][k] <= o["G"][ko] * (1 + 2 * e_G), (k, ko)
+        assert k == ko, (k, ko)
         mu = float(p0.mus[k])
         fo = twod.forward2d("C", "C", tk.tikhonov_filter(o["ghat"], o["d"], np.ones((N3, N3)), mu), wide=False)
         e_f = rel_normwise(f[i].cpu().numpy(), fo)
@@ -176,6 +182,11 @@ def test_mixed_precision_16x2048(ht, prec, images3, oracle3):
         rre_o = np.linalg.norm(fo - images3[i].f_true) / np.linalg.norm(images3[i].f_true)
         print("%s image %d: ghat %.2e  G %.2e  k* %d (oracle %d)  f %.2e (filter gain %.0f)  "
               "RRE %.5f (oracle %.5f)" % (prec, i, e_ghat, e_G, k, ko, e_f, amp, rre, rre_o))
-        assert e_ghat < 2 * TOL_PASS[prec]
-        assert e_G < 4 * TOL_PASS[prec]
-        assert e_f < 2 * TOL_PASS[prec] * amp * np.linalg.norm(images3[i].g) / np.linalg.norm(fo)
+        derived = 2 * TOL_PASS[prec] * amp * np.linalg.norm(images3[i].g) / np.linalg.norm(fo)
+        tol = TOL_16X2048[prec]
+        record("%s 16x2048 image %d ghat" % (prec, i), e_ghat, tol["ghat"])
+        record("%s 16x2048 image %d G" % (prec, i), e_G, tol["G"], k=k, ko=ko)
+        record("%s 16x2048 image %d f" % (prec, i), e_f, tol["f"], derived=derived)
+        assert e_ghat < tol["ghat"]
+        assert e_G < tol["G"]
+        assert e_f < tol["f"]
