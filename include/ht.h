@@ -14,8 +14,9 @@
  *   - All array arguments are DEVICE pointers owned by the caller, except where a
  *     parameter is documented as a host array.  The library never frees caller memory.
  *   - Calls are asynchronous on the given HIP stream (0 = legacy default stream) and
- *     allocate nothing: a plan owns every table and workspace it needs (one exception:
- *     ht_gcv_scan_exact on a 2D plan, documented there).
+ *     allocate nothing: a plan owns every table and workspace it needs (set-up calls -
+ *     ht_plan_create, ht_plan_set_precision, ht_plan_reserve_exact_gcv, ht_batch_create,
+ *     ht_mlp_create - allocate and may block).
  *   - Arguments are validated on the host before anything is launched; on error nothing
  *     is launched and a status other than HT_OK is returned.  ht_last_error() returns a
  *     thread-local message describing the most recent failure.  No exception crosses the
@@ -238,15 +239,25 @@ ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const void* d, con
  *   2D plans: ||T0 V T1^T||^2 from the same structure of both axes: the 1D form of every
  *   interior row plus the axis-0 boundary terms, built from the rows' functionals and the
  *   weighted column sums of V (a row pass, a column pass and a combination per grid
- *   value); batch <= max_batch; allocates its workspace (at most 256 MiB, plus the G
- *   values when G is NULL) on the stream with hipMallocAsync and frees it there, so it
- *   is not for graph capture.
+ *   value, images in chunks that fit the plan's workspace); batch <= max_batch and K at
+ *   most the grid size reserved for the plan (128 unless ht_plan_reserve_exact_gcv
+ *   reserved more); allocates nothing.  Calls on one plan must be ordered on one stream
+ *   (they share its workspace).
  *   The periodic and reflective comparators are unitary: eq. gcv is eq. gcv2 (1D plans
  *   run ht_gcv_scan).  HT_ERR_UNSUPPORTED for HT_KIND_F3.                               */
 ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, const void* d, const double* s,
                             int64_t eig_batch, int layout, const double* mu_grid, int32_t K,
                             int grid_per_item, double* G, int32_t* k_best, double* mu_best,
                             int64_t batch, hipStream_t stream);
+
+/* ht_plan_reserve_exact_gcv -- size the workspace of ht_gcv_scan_exact on a 2D plan for
+ * grids of up to max_k values (1..1024): row-pass outputs for a chunk of images (at most
+ * 64 MiB, at least one image: n0 max_k 22 doubles per image), column-pass partials for
+ * the same chunk and max_k doubles of G per image.  ht_plan_create reserves max_k = 128;
+ * a call with a larger K than reserved returns HT_ERR_INVALID_ARG.  Set-up call:
+ * synchronises the device; no-op for 1D plans, the comparators and a max_k already
+ * reserved.                                                                           */
+ht_status ht_plan_reserve_exact_gcv(ht_plan* plan, int32_t max_k);
 
 /* ---------------------------------------------------------------------------------
  * Ragged batches: many 1D signals of uneven length n_b, each with its own PSF mask,
@@ -271,6 +282,8 @@ ht_status ht_batch_destroy(ht_batch* batch);
 int64_t ht_batch_total_length(const ht_batch* batch);
 /* sum of psf_len[b] (length of the PSF array), or -1 */
 int64_t ht_batch_psf_total(const ht_batch* batch);
+/* number of signals, or -1 */
+int64_t ht_batch_count(const ht_batch* batch);
 
 /* ht_batch_restore -- for every signal b: d, s on its grid, ghat = T^{-1} g,
  * G_b(mu_{b,k}) for k < K (eq. mugcv), k_b = first argmin, f = T Phi D^{-1} ghat at
@@ -387,6 +400,99 @@ ht_status ht_outer(const float* dy, const float* w, float* dh, int64_t rows, int
 ht_status ht_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr,
                   float beta1, float beta2, float eps, int64_t step, uint16_t* pb,
                   hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------
+ * The learned-mu predictor as a library object (the network above with its weights,
+ * Adam state, feature standardisation and activation buffers).  Created once; every
+ * other call launches kernels only (no allocation), asynchronously on the stream.  Calls
+ * on one network must be ordered on one stream (they share its buffers).  Not in the
+ * paper: an accelerator of the GCV choice of mu of Section 4 (eq. mugcv), trained on
+ * problems the method labels itself.
+ * Parameters are one float32 vector of ht_mlp_param_count() = 150529 entries:
+ * W1 [72][256], b1 [256], W2 [256][256], b2 [256], W3 [256][256], b3 [256], W4 [256][1],
+ * b4 [1]; W row-major [in][out].
+ * --------------------------------------------------------------------------------- */
+typedef struct ht_mlp ht_mlp;
+
+int64_t ht_mlp_param_count(void);
+
+/* ht_mlp_create -- allocate a network for minibatches / prediction chunks of up to
+ * max_rows rows (1 <= max_rows <= 2^24) on the current device: parameters and Adam
+ * moments zero, standardisation mean 0 / std 1.  HT_ERR_OOM if the allocation fails.   */
+ht_status ht_mlp_create(int64_t max_rows, ht_mlp** out);
+ht_status ht_mlp_destroy(ht_mlp* mlp);
+
+/* ht_mlp_set_params -- copy params (device float32 [150529]) into the network and refresh
+ * its bfloat16 copies.                                                                  */
+ht_status ht_mlp_set_params(ht_mlp* mlp, const float* params, hipStream_t stream);
+
+/* ht_mlp_get -- copy one of the network's vectors into out (device float32): the
+ * parameters, the gradients of the last backward pass, the Adam moments ([150529] each),
+ * or the standardisation mean / std ([72]).                                             */
+typedef enum {
+    HT_MLP_PARAMS_VEC = 0, HT_MLP_GRADS_VEC = 1, HT_MLP_ADAM_M_VEC = 2, HT_MLP_ADAM_V_VEC = 3,
+    HT_MLP_MEAN_VEC = 4, HT_MLP_STD_VEC = 5
+} ht_mlp_vector;
+ht_status ht_mlp_get(const ht_mlp* mlp, int which, float* out, hipStream_t stream);
+
+/* ht_mlp_set_state -- restore Adam moments (adam_m, adam_v: device [150529], both or
+ * neither), the Adam step count, and the standardisation (mean, std: device [72], both or
+ * neither).                                                                            */
+ht_status ht_mlp_set_state(ht_mlp* mlp, const float* adam_m, const float* adam_v, int64_t steps,
+                           const float* mean, const float* std, hipStream_t stream);
+/* Adam steps taken so far, or -1 for a null network. */
+int64_t ht_mlp_steps(const ht_mlp* mlp);
+
+/* ht_mlp_fit_standardisation -- per-feature mean and population standard deviation
+ * (floored at 1e-6) of features (device float32 [rows][72]), float64 sums in a fixed
+ * order; the network standardises its inputs with them from then on.                  */
+ht_status ht_mlp_fit_standardisation(ht_mlp* mlp, const float* features, int64_t rows,
+                                     hipStream_t stream);
+
+/* ht_mlp_forward -- pred[r] (float32, device, nullable: the network keeps its own copy
+ * for ht_mlp_backward) = the network at the standardised features[r] (device float32
+ * [rows][72]): standardised inputs and every hidden activation rounded to bfloat16, exact
+ * GELU, float32 accumulation.  1 <= rows <= max_rows.                                  */
+ht_status ht_mlp_forward(ht_mlp* mlp, const float* features, int64_t rows, float* pred,
+                         hipStream_t stream);
+
+/* ht_mlp_backward -- gradients of the mean squared error mean_r (pred_r - target_r)^2 of
+ * the last ht_mlp_forward (same rows) with respect to every parameter, kept in the
+ * network (read with ht_mlp_get); the pre-activation gradients are rounded to bfloat16
+ * before the products that consume them.  loss (device float32 [1], nullable) receives the
+ * mean squared error (float64 sum in a fixed order).                                    */
+ht_status ht_mlp_backward(ht_mlp* mlp, const float* target, int64_t rows, float* loss,
+                          hipStream_t stream);
+
+/* ht_mlp_adam_step -- one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias corrected by
+ * the network's step count, which this call increments on the host: a captured graph
+ * would replay one fixed step) on every parameter with the current gradients, then the
+ * bfloat16 copies.  lr > 0.                                                             */
+ht_status ht_mlp_adam_step(ht_mlp* mlp, float lr, hipStream_t stream);
+
+/* ht_mlp_train_step -- one minibatch step: rows r of the minibatch are features[idx[r]]
+ * and target[idx[r]] (features device float32 [*][72], target device float32 [*], idx
+ * device int32 [rows], every index valid for the caller's arrays), gathered on the
+ * device; then forward, backward and an Adam step as above.  loss as for ht_mlp_backward.
+ * 1 <= rows <= max_rows.                                                                */
+ht_status ht_mlp_train_step(ht_mlp* mlp, const float* features, const float* target, const int32_t* idx,
+                            int64_t rows, float lr, float* loss, hipStream_t stream);
+
+/* ht_mlp_weights_of -- the network as ht_mlp_weights (device pointers into the network,
+ * valid until it is destroyed) for ht_batch_restore_fused.                             */
+ht_status ht_mlp_weights_of(const ht_mlp* mlp, ht_mlp_weights* out);
+
+/* ht_log10_labels -- labels[i] = float32(log10(mu[i])) (mu device float64 [count], e.g.
+ * the mu_best of ht_batch_restore: the GCV-optimal mu that labels a training problem).  */
+ht_status ht_log10_labels(const double* mu, float* labels, int64_t count, hipStream_t stream);
+
+/* ht_lambda_predict -- predicted log10 mu for every signal of a ragged batch:
+ * ht_batch_features (coeff [total_length], features [count][72], spectrum nullable) then
+ * the network on the features in chunks of max_rows rows; pred device float32 [count].
+ * The result feeds ht_batch_restore_learned.                                           */
+ht_status ht_lambda_predict(const ht_batch* batch, ht_mlp* mlp, const double* signal, const double* psf,
+                            double* coeff, float* features, double* spectrum, float* pred,
+                            hipStream_t stream);
 
 const char* ht_status_str(ht_status status);
 const char* ht_last_error(void);

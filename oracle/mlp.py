@@ -3,7 +3,9 @@
 mean squared error of log10 mu.  Forward and backward in float64, written out layer by
 layer; with `bf16=True` the values the GPU rounds to bfloat16 (inputs, weights, hidden
 activations, backpropagated pre-activation gradients) are rounded at the same points.
-Pinned by central finite differences in pure float64 (tests/test_oracle_learned.py).
+Adam (Kingma and Ba, 2015) in float64, written out step by step.
+Pinned by central finite differences in pure float64, and Adam by its closed form under a
+constant gradient (tests/test_oracle_learned.py).
 """
 
 import numpy as np
@@ -74,3 +76,20 @@ def init_params(rng):
         ps.append((rng.standard_normal((fan_in, fan_out)) * np.sqrt(2.0 / fan_in)).astype(np.float32))
         ps.append(np.zeros(fan_out, dtype=np.float32))
     return ps
+
+
+def adam_step(params, grads, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (step = 1, 2, ... counts this one): moments m <- beta1 m + (1-beta1) g,
+    v <- beta2 v + (1-beta2) g^2, bias corrections 1 - beta^step, update
+    lr m_hat / (sqrt(v_hat) + eps).  Returns new (params, m, v) lists, float64."""
+    out_p, out_m, out_v = [], [], []
+    c1 = 1.0 - beta1 ** step
+    c2 = 1.0 - beta2 ** step
+    for p, g, mi, vi in zip(params, grads, m, v):
+        g = np.asarray(g, dtype=np.float64).reshape(np.shape(p))
+        mi = beta1 * np.asarray(mi, dtype=np.float64) + (1.0 - beta1) * g
+        vi = beta2 * np.asarray(vi, dtype=np.float64) + (1.0 - beta2) * g * g
+        out_p.append(np.asarray(p, dtype=np.float64) - lr * (mi / c1) / (np.sqrt(vi / c2) + eps))
+        out_m.append(mi)
+        out_v.append(vi)
+    return out_p, out_m, out_v

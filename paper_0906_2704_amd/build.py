@@ -11,8 +11,9 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["ht_plan.hip", "ht_transform.hip", "ht_spectral.hip", "ht_batch.hip", "ht_mlp.hip", "ht_gemm.hip",
-           ]
+SOURCES = ["ht_plan.hip", "ht_transform.hip", "ht_spectral.hip", "ht_batch.hip", "ht_batch_k_scan.hip",
+           "ht_batch_k_features.hip", "ht_batch_k_learned.hip", "ht_batch_k_fused.hip", "ht_mlp.hip", "ht_gemm.hip",
+           "ht_learn.hip"]
 LIB = os.path.join(HERE, "libht.so")
 OBJDIR = os.path.join(ROOT, "_build")
 

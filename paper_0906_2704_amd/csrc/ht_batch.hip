@@ -1,14 +1,7 @@
 // Ragged batches: thousands of 1D signals of uneven length, each with its own PSF, boundary
-// degree and mu grid, restored by one persistent fused kernel per FFT size class.
-//
-// For every signal a workgroup runs the whole method without leaving the chip between
-// steps: inverse transform (Theorem th:inv) -> eigenvalues of the blur and of the
-// smoothing operator on the signal's grid (eqs. jcf, Ac) -> GCV over the signal's grid
-// (eq. mugcv) -> Tikhonov filter at the chosen mu (eq. freg) -> forward transform.  The
-// coefficients, eigenvalues and filter factors live in registers; LDS holds the FFT, then
-// the exactly rounded cosine table of the signal's grid, then the (t_i, w_i) pairs the
-// GCV sums read.  Workgroups take signals from a per-class queue (an atomic counter),
-// longest first.
+// degree and mu grid, restored by one persistent fused kernel per FFT size class (the
+// kernel is in batch_kernel.h).  Host side: tables of every distinct (n, kind), the
+// longest-first queues per size class, the schedule, the entry points.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,697 +12,13 @@
 #include <thread>
 #include <vector>
 
-#include "chirp_core.h"
-#include "ht_internal.h"
+#include "batch_kernel.h"
 #include "plan_build.h"
 
 namespace ht {
-
-constexpr int NCLASS = 6;          // (LOGP, S): (9,1) (10,1) (11,1) (12,1) (13,1) (13,2)
-constexpr int BATCH_MAX_K = 256;
-
-struct RSig {
-    int64_t off;        // offset of the signal in the concatenated signal / output arrays
-    int64_t psf_off;    // offset of its mask in the concatenated PSF array
-    int32_t psf_len, psf_center;
-    int32_t axis;       // index of its transform tables
-    int32_t item;       // caller's index (row of the mu grid, outputs)
-};
-
-struct RaggedArgs {
-    const Axis* axes;
-    const RSig* sigs;
-    int* counters;
-    const double* g;
-    const double* psf;
-    const double* mus;
-    int K;
-    int norm;
-    double* f;
-    double* G;
-    int32_t* kbest;
-    double* mubest;
-    double* scratch;    // MAX_N doubles per persistent workgroup of the split class
-    const float* pred;  // learned mode: predicted log10(mu) per item
-    int32_t* fallback;  // learned mode: 1 where the certificate failed and the full scan ran
-    float* feat;        // feature mode: [count][NFEAT]
-    int cert_half;      // learned mode: certificate bracket half-width in grid steps
-    double* spec;       // feature mode: blur eigenvalues written here; learned mode: read (or null)
-    // fused mode: the network 72 -> 256 -> 256 -> 256 -> 1 (bfloat16 weights [in][out],
-    // float32 biases, feature standardisation); pred / feat receive the prediction and the
-    // features when non-null
-    const uint16_t* w[4];
-    const float* bias[4];
-    const float* fmean;
-    const float* fstd;
-    float* pred_out;
-};
-
-// What one pass of the fused kernel does with each signal.
-enum BatchMode {
-    MODE_SCAN = 0,      // inverse, eigenvalues, full GCV scan, filter, forward
-    MODE_FEATURES = 1,  // inverse, eigenvalues, band statistics; the coefficients go to f
-    MODE_LEARNED = 2,   // coefficients from f, eigenvalues, GCV certificate around the
-                        // predicted mu (full scan if it fails), filter, forward
-    MODE_FUSED = 3      // inverse, eigenvalues, features, the network's prediction, then as
-                        // MODE_LEARNED: one pass per signal
-};
-constexpr int MLP_H = 256;  // hidden width of the network
-constexpr int NFEAT_G = 64, NFEAT_D = 8, NFEAT = NFEAT_G + NFEAT_D;
-constexpr double CERT_SLACK = 1.05;   // G(predicted) may exceed the bracket minimum by 5%
-
-static int class_of(const Axis& a) { return a.S == 2 ? 5 : a.logP - MIN_LOGP; }
-
 __global__ void k_reset_counters(int* c) {
     if (threadIdx.x < NCLASS) c[threadIdx.x] = 0;
 }
-
-// 1/u to full float64 accuracy: hardware estimate and two Newton steps.
-__device__ __forceinline__ double rcp_nr(double u) {
-    double r = __builtin_amdgcn_rcp(u);
-    double e = fma(-u, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-u, r, 1.0);
-    return fma(r, e, r);
-}
-
-// Partial GCV sums of two grid values mu_a, mu_b over the staged elements
-// i = part, part + nparts, ... < n.  Two elements share one reciprocal:
-// 1/u0 = u1 / (u0 u1), 1/u1 = u0 / (u0 u1) (u >= mu > 0, the staged t are < 1e150).
-__device__ __forceinline__ void gcv_two(const double2* stage, int n, int part, int nparts, double mua, double mub,
-                                        double& Na, double& Da, double& Nb, double& Db) {
-    double na0 = 0.0, na1 = 0.0, da0 = 0.0, da1 = 0.0;
-    double nb0 = 0.0, nb1 = 0.0, db0 = 0.0, db1 = 0.0;
-    int i = part;
-    for (; i + nparts < n; i += 2 * nparts) {
-        const double2 p0 = stage[i], p1 = stage[i + nparts];
-        const double ua0 = p0.x + mua, ua1 = p1.x + mua;
-        const double ub0 = p0.x + mub, ub1 = p1.x + mub;
-        const double ra = rcp_nr(ua0 * ua1), rb = rcp_nr(ub0 * ub1);
-        const double ra0 = ua1 * ra, ra1 = ua0 * ra, rb0 = ub1 * rb, rb1 = ub0 * rb;
-        da0 += ra0;
-        da1 += ra1;
-        db0 += rb0;
-        db1 += rb1;
-        na0 = fma(p0.y, ra0 * ra0, na0);
-        na1 = fma(p1.y, ra1 * ra1, na1);
-        nb0 = fma(p0.y, rb0 * rb0, nb0);
-        nb1 = fma(p1.y, rb1 * rb1, nb1);
-    }
-    if (i < n) {
-        const double2 p0 = stage[i];
-        const double ra = rcp_nr(p0.x + mua), rb = rcp_nr(p0.x + mub);
-        da0 += ra;
-        db0 += rb;
-        na0 = fma(p0.y, ra * ra, na0);
-        nb0 = fma(p0.y, rb * rb, nb0);
-    }
-    Na = na0 + na1;
-    Da = da0 + da1;
-    Nb = nb0 + nb1;
-    Db = db0 + db1;
-}
-
-// Copy a record that every lane reads at the same address into scalar registers: each
-// 32-bit word goes through readfirstlane, so the compiler knows the fields (sizes, table
-// pointers) are wave-uniform and addresses tables as scalar base + lane offset.
-template <class T>
-__device__ __forceinline__ T uniform_load(const T* p) {
-    static_assert(sizeof(T) % 4 == 0, "record must be a whole number of words");
-    T out;
-    const int* src = reinterpret_cast<const int*>(p);
-    int* dst = reinterpret_cast<int*>(&out);
-#pragma unroll
-    for (unsigned i = 0; i < sizeof(T) / 4; ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
-    return out;
-}
-
-// float32 -> bfloat16 (round to nearest even) -> float32, and the exact GELU: the rounding
-// points and activation of the network kernels of the learned-mu predictor.
-__device__ __forceinline__ float bf16_round(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xffff0000u);
-}
-__device__ __forceinline__ float bf16_load(const uint16_t* p, int i) {
-    return __uint_as_float(static_cast<uint32_t>(p[i]) << 16);
-}
-__device__ __forceinline__ float gelu_exact(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-
-// One dense layer of the network for one signal, in LDS: out[j] = act(sum_k in[k] W[k][j]
-// + b[j]) for j < 256.  With BLOCK >= 256 the contraction is split into BLOCK / 256 equal
-// ranges whose float32 partial sums are added in order; smaller workgroups give each
-// thread 256 / BLOCK outputs.  act: 1 = GELU then bfloat16 rounding, 0 = none.
-template <int BLOCK>
-__device__ __forceinline__ void mlp_layer(const float* in, int K, const uint16_t* __restrict__ W,
-                                          const float* __restrict__ b, float* out, float* part, int act) {
-    const int tid = threadIdx.x;
-    if constexpr (BLOCK >= MLP_H) {
-        constexpr int G = BLOCK / MLP_H;
-        const int j = tid % MLP_H, gi = tid / MLP_H;
-        const int k0 = gi * K / G, k1 = (gi + 1) * K / G;
-        float acc = 0.0f;
-#pragma unroll 2
-        for (int k = k0; k < k1; ++k) acc = fmaf(in[k], bf16_load(W, k * MLP_H + j), acc);
-        part[gi * MLP_H + j] = acc;
-        __syncthreads();
-        if (gi == 0) {
-            float z = part[j];
-#pragma unroll
-            for (int q = 1; q < G; ++q) z += part[q * MLP_H + j];
-            z += b[j];
-            out[j] = act ? bf16_round(gelu_exact(z)) : z;
-        }
-    } else {
-        for (int j = tid; j < MLP_H; j += BLOCK) {
-            float acc = 0.0f;
-#pragma unroll 2
-            for (int k = 0; k < K; ++k) acc = fmaf(in[k], bf16_load(W, k * MLP_H + j), acc);
-            const float z = acc + b[j];
-            out[j] = act ? bf16_round(gelu_exact(z)) : z;
-        }
-    }
-    __syncthreads();
-}
-
-// The 1024-, 2048- and 4096-point classes with 8 points per thread are held to 128
-// registers per lane (four waves per SIMD): two to eight workgroups then share a CU and
-// cover each other's barrier and memory waits, which pays for the spills this costs
-// (measured: 20 % less time in the 2048- and 4096-point classes; the 512-point class of
-// single-wave workgroups is slower so, and the 8192-point classes are bound by their LDS
-// to one workgroup per CU).
-template <int LOGP, int S, int SL>
-constexpr int restore_waves_per_eu() { return LOGP >= 10 && LOGP <= 12 && SL == 8 ? 4 : 1; }
-
-template <int LOGP, int S, int SL, int MODE>
-__global__ __launch_bounds__((1 << LOGP) / SL)
-__attribute__((amdgpu_waves_per_eu(restore_waves_per_eu<LOGP, S, SL>())))
-void k_restore(RaggedArgs a, int cls, int start, int count) {
-    constexpr int P = 1 << LOGP;
-    constexpr int BLOCK = P / SL;
-    // cross-part GCV reduction buffer: only 64-thread groups can need more than one pass
-    // over the grid (K > 2 * BLOCK); otherwise the reduction reuses the staging buffer
-    constexpr int RED = BLOCK < BATCH_MAX_K / 2 ? 2 * BLOCK : 1;
-    __shared__ double2 lds[P];
-    __shared__ double2 red_small[RED];
-    __shared__ double Gs[BATCH_MAX_K];
-    __shared__ double2 bc[3];
-    __shared__ int s_item, s_kbest;
-    __shared__ float s_pred;
-    const int tid = threadIdx.x;
-    double* scratch = a.scratch + static_cast<int64_t>(blockIdx.x) * MAX_N;
-    // Classes of 4096 points and more take their next queue entry while the current signal
-    // runs (the atomic's latency then hides behind the signal's own loads); their long
-    // queues per workgroup make the one reserved entry irrelevant to the load balance,
-    // which it does disturb for the short queues of the small classes.
-    constexpr bool PREFETCH = LOGP >= 12;
-    int nxt = 0;
-    if (PREFETCH && tid == 0) nxt = atomicAdd(&a.counters[cls], 1);
-    for (;;) {
-        if (tid == 0) s_item = PREFETCH ? nxt : atomicAdd(&a.counters[cls], 1);
-        __syncthreads();
-        // uniform across the workgroup: keeps the signal's descriptor and table pointers in
-        // scalar registers
-        const int qi = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (qi >= count) break;
-        if (PREFETCH && tid == 0) nxt = atomicAdd(&a.counters[cls], 1);
-        const RSig sg = uniform_load(a.sigs + start + qi);
-        const Axis ax = uniform_load(a.axes + sg.axis);
-        // read per signal so that no twiddle address is hoisted out of the queue loop
-        const double2* __restrict__ tw = ax.tw;
-        const int n = ax.n, N = ax.N, rank = ax.rank, kind = ax.kind, den = ax.den;
-        const double* g = a.g + sg.off;
-        double* f = a.f + sg.off;
-        const double* h = a.psf + sg.psf_off;
-        const double q1 = ax.q1;
-
-        // ---- inverse transform: boundary coefficients, interior correction, core analysis
-        double x1, xn;
-        double c[SL];
-        if constexpr (MODE == MODE_LEARNED) {  // coefficients left in f by the feature pass
-            x1 = f[0];
-            xn = f[n - 1];
-#pragma unroll
-            for (int k = 0; k < SL; ++k) {
-                const int j = tid + k * BLOCK;
-                c[k] = j < N ? f[j + 1] : 0.0;
-            }
-        } else {
-        {
-            const double y0 = g[0], y1 = g[1], yN = g[n - 2], yL = g[n - 1];
-            if (kind == HT_KIND_C) {
-                const double r1 = y0 - y1, r2 = yL - yN;
-                x1 = ax.minv[0] * r1 + ax.minv[1] * r2;
-                xn = ax.minv[2] * r1 + ax.minv[3] * r2;
-            } else {
-                x1 = y0 / q1;
-                xn = yL / q1;
-            }
-        }
-        {
-            auto in_inv = [&](int, int j) {
-                return make_double2(g[j + 1] - ax.q[j + 1] * x1 - ax.q[N - j] * xn, 0.0);
-            };
-            auto park = [&](int j, double y) { f[j + 1] = y; };
-            auto unpark = [&](int j) { return f[j + 1]; };
-            chirp_core<LOGP, S, SL>(c, ax.ana, ax.ana.mode, N, lds, tw, in_inv, park, unpark);
-        }
-        if (rank > 0) {  // DST family correction x_mid -= U (E^T K)^{-1} E^T x_mid
-            if (tid < rank) bc[tid].x = c[0];
-            __syncthreads();
-            const double s0 = bc[0].x, s1 = rank > 1 ? bc[1].x : 0.0;
-            const double a0 = ax.Gm[0] * s0 + ax.Gm[1] * s1;
-            const double a1 = ax.Gm[2] * s0 + ax.Gm[3] * s1;
-#pragma unroll
-            for (int k = 0; k < SL; ++k) {
-                const int j = tid + k * BLOCK;
-                if (j < N) {
-                    c[k] -= ax.U[j] * a0;
-                    if (rank > 1) c[k] -= ax.U[N + j] * a1;
-                }
-            }
-        }
-        if constexpr (MODE == MODE_FEATURES) {  // the coefficient vector for the learned pass
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < SL; ++k) {
-                const int j = tid + k * BLOCK;
-                if (j < N) f[j + 1] = c[k];
-            }
-            if (tid == 0) {
-                f[0] = x1;
-                f[n - 1] = xn;
-            }
-        }
-        }
-
-        __builtin_amdgcn_sched_barrier(0);
-        // ---- eigenvalues on the signal's grid: cos(pi r / den), r <= den, staged in LDS
-        // (the learned pass reads d from the feature pass and needs only cos(pi num / den)
-        // at its own frequency for s: it reads those straight from the table, coalesced,
-        // and skips the staging)
-        const bool staged = !(MODE == MODE_LEARNED && a.spec);
-        double* ctab = reinterpret_cast<double*>(lds);
-        if (staged) {
-            __syncthreads();
-            for (int r = tid; r <= den; r += BLOCK) ctab[r] = ax.tcos[r];
-            __syncthreads();
-        }
-        double z0 = 0.0;
-        for (int t = 0; t < sg.psf_len; ++t) z0 += h[t];
-        const bool ident = a.norm == HT_NORM_IDENTITY;
-        const double s_poly = ident ? 1.0 : 0.0;
-        const int per = 2 * den;
-        const int pc = sg.psf_center, pl = sg.psf_len;
-        const bool centred = 2 * pc + 1 == pl;
-        // Mirror pairs (centred masks): the frequency of index mj = (C: N - j, sine: N - 1 - j)
-        // is pi - theta_j, where cos(t (pi - theta)) = (-1)^t cos(t theta); summing the even
-        // and the odd taps apart gives d_j = E + O and d_mj = E - O in one pass over the
-        // taps.  The lower index of a pair computes both and leaves d_mj in LDS behind the
-        // staged table (den + 1 + N <= 2P doubles) for the owner of mj.
-        const bool pair = staged && centred;
-        double* dmir = ctab + den + 1;
-        auto mirror = [&](int j) { return kind == HT_KIND_C ? N - j : N - 1 - j; };
-        double dj[SL], sj[SL];
-#pragma unroll
-        for (int k = 0; k < SL; ++k) {
-            const int j = tid + k * BLOCK;
-            dj[k] = z0;
-            sj[k] = s_poly;
-            if (j < N && j >= rank) {
-                const int num = kind == HT_KIND_C ? j : j + 1;  // frequency pi * num / den
-                const int mj = mirror(j);
-                const bool lead = pair && mj > j && mj < N && mj >= rank;
-                const bool follow = pair && mj < j && mj >= rank;
-                double acc = 0.0;
-                if (MODE == MODE_LEARNED && a.spec) {
-                    acc = a.spec[sg.off + 1 + j];  // left by the feature pass
-                } else if (follow) {
-                    // d_j arrives from the owner of mj below
-                } else if (centred) {
-                    // Re z = h_0 + sum_{t>0} (h_t + h_{-t}) cos(t theta), even and odd t apart
-                    double ev = h[pc], od = 0.0;
-                    int r = 0, t = 1;
-                    for (; t + 1 <= pc; t += 2) {
-                        r += num;
-                        if (r >= per) r -= per;
-                        od = fma(h[pc + t] + h[pc - t], ctab[r <= den ? r : per - r], od);
-                        r += num;
-                        if (r >= per) r -= per;
-                        ev = fma(h[pc + t + 1] + h[pc - t - 1], ctab[r <= den ? r : per - r], ev);
-                    }
-                    if (t <= pc) {
-                        r += num;
-                        if (r >= per) r -= per;
-                        od = fma(h[pc + t] + h[pc - t], ctab[r <= den ? r : per - r], od);
-                    }
-                    acc = ev + od;
-                    if (lead) dmir[mj] = ev - od;
-                } else {
-                    int r = static_cast<int>((static_cast<int64_t>(per) * pl - static_cast<int64_t>(pc) * num) % per);
-                    for (int t = 0; t < pl; ++t) {
-                        const double cv = ctab[r <= den ? r : per - r];
-                        acc = fma(h[t], cv, acc);
-                        r += num;
-                        if (r >= per) r -= per;
-                    }
-                }
-                dj[k] = acc;
-                const int rn = num % per;
-                const int rc = rn <= den ? rn : per - rn;
-                sj[k] = ident ? 1.0 : 2.0 - 2.0 * (staged ? ctab[rc] : ax.tcos[rc]);
-            }
-        }
-        __syncthreads();
-        if (pair) {  // uniform: the mirrored halves, then LDS is free for the next phase
-#pragma unroll
-            for (int k = 0; k < SL; ++k) {
-                const int j = tid + k * BLOCK;
-                if (j < N && j >= rank) {
-                    const int mj = mirror(j);
-                    if (mj < j && mj >= rank) dj[k] = dmir[j];
-                }
-            }
-            __syncthreads();
-        }
-
-        __shared__ float s_feat[NFEAT];
-        if constexpr (MODE == MODE_FEATURES || MODE == MODE_FUSED) {
-            // band means of log10(|ghat_j|^2 + 1e-20) (64 bands) and log10(|d_j|^2 + 1e-20) (8 bands) over the
-            // normalised core frequency j / N; band b holds j with floor(B j / N) = b
-            // (float32 logarithms: the features are float32)
-            double2* lg = lds;
-            constexpr float LOG10_2 = 0.30102999566398120f;
-#pragma unroll
-            for (int k = 0; k < SL; ++k) {
-                const int j = tid + k * BLOCK;
-                if (j < N) {
-                    const float lc = __builtin_amdgcn_logf(static_cast<float>(c[k] * c[k] + 1e-20)) * LOG10_2;
-                    const float ld = __builtin_amdgcn_logf(static_cast<float>(dj[k] * dj[k] + 1e-20)) * LOG10_2;
-                    lg[j] = make_double2(lc, ld);
-                    if (a.spec) a.spec[sg.off + 1 + j] = dj[k];
-                }
-            }
-            if (a.spec && tid == 0) {
-                a.spec[sg.off] = z0;
-                a.spec[sg.off + n - 1] = z0;
-            }
-            __syncthreads();
-            // band sums by groups of aligned lanes (a fixed-order butterfly per group):
-            // 64 spectrum bands of ghat with BLOCK/64 lanes each, then 8 bands of d with up
-            // to 64 lanes each
-            {
-                constexpr int G1 = BLOCK / NFEAT_G;
-                const int b = tid / G1, r = tid - b * G1;
-                const int j0 = static_cast<int>((static_cast<int64_t>(b) * N + NFEAT_G - 1) / NFEAT_G);
-                const int j1 = static_cast<int>((static_cast<int64_t>(b + 1) * N + NFEAT_G - 1) / NFEAT_G);
-                double acc = 0.0;
-                for (int j = j0 + r; j < j1; j += G1) acc += lg[j].x;
-#pragma unroll
-                for (int o = G1 / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-                if (r == 0) {
-                    const float v = static_cast<float>(acc / (j1 - j0));
-                    if (MODE == MODE_FUSED) s_feat[b] = v;
-                    if (a.feat) a.feat[static_cast<int64_t>(sg.item) * NFEAT + b] = v;
-                }
-            }
-            {
-                constexpr int G2 = BLOCK / NFEAT_D < 64 ? BLOCK / NFEAT_D : 64;
-                if (tid < NFEAT_D * G2) {  // whole waves
-                    const int b = tid / G2, r = tid - b * G2;
-                    const int j0 = static_cast<int>((static_cast<int64_t>(b) * N + NFEAT_D - 1) / NFEAT_D);
-                    const int j1 = static_cast<int>((static_cast<int64_t>(b + 1) * N + NFEAT_D - 1) / NFEAT_D);
-                    double acc = 0.0;
-                    for (int j = j0 + r; j < j1; j += G2) acc += lg[j].y;
-#pragma unroll
-                    for (int o = G2 / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-                    if (r == 0) {
-                        const float v = static_cast<float>(acc / (j1 - j0));
-                        if (MODE == MODE_FUSED) s_feat[NFEAT_G + b] = v;
-                        if (a.feat) a.feat[static_cast<int64_t>(sg.item) * NFEAT + NFEAT_G + b] = v;
-                    }
-                }
-            }
-            __syncthreads();
-            if constexpr (MODE == MODE_FEATURES) continue;
-            // ---- the network's log10 mu for this signal (fused mode), computed in LDS:
-            // activations at [0, 256) and [256, 512) floats, layer partial sums behind them
-            float* act = reinterpret_cast<float*>(lds);
-            float* part = act + 2 * MLP_H;
-            for (int i = tid; i < NFEAT; i += BLOCK) act[i] = bf16_round((s_feat[i] - a.fmean[i]) / a.fstd[i]);
-            __syncthreads();
-            mlp_layer<BLOCK>(act, NFEAT, a.w[0], a.bias[0], act + MLP_H, part, 1);
-            mlp_layer<BLOCK>(act + MLP_H, MLP_H, a.w[1], a.bias[1], act, part, 1);
-            mlp_layer<BLOCK>(act, MLP_H, a.w[2], a.bias[2], act + MLP_H, part, 1);
-            if (tid < 64) {  // output layer: four inputs per lane, then a fixed-order butterfly
-                float y = 0.0f;
-#pragma unroll
-                for (int k = 4 * tid; k < 4 * tid + 4; ++k) y = fmaf(act[MLP_H + k], bf16_load(a.w[3], k), y);
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) y += __shfl_xor(y, o, 64);
-                if (tid == 0) {
-                    y += a.bias[3][0];
-                    s_pred = y;
-                    if (a.pred_out) a.pred_out[sg.item] = y;
-                }
-            }
-            __syncthreads();
-        }
-
-        __builtin_amdgcn_sched_barrier(0);
-        // ---- GCV: stage t_i = |d_i|^2 / |s_i|^2, w_i = |ghat_i|^2 (s_i = 0: no contribution)
-        double2* stage = lds;
-        auto stage_fill = [&]() {
-#pragma unroll
-            for (int k = 0; k < SL; ++k) {
-                const int j = tid + k * BLOCK;
-                if (j < N) {
-                    const double s2 = sj[k] * sj[k];
-                    stage[j] = s2 != 0.0 ? make_double2(dj[k] * dj[k] / s2, c[k] * c[k]) : make_double2(1e150, 0.0);
-                }
-            }
-            if (tid == 0) {
-                const double s2 = s_poly * s_poly;
-                stage[N] = s2 != 0.0 ? make_double2(z0 * z0 / s2, x1 * x1) : make_double2(1e150, 0.0);
-                stage[N + 1] = s2 != 0.0 ? make_double2(z0 * z0 / s2, xn * xn) : make_double2(1e150, 0.0);
-            }
-            __syncthreads();
-        };
-        const int K = a.K;
-        const double* mus = a.mus + static_cast<int64_t>(sg.item) * K;
-        // G_k for k in [klo, khi] into Gs (and a.G), two grid values per evaluation.  Long
-        // ranges: the lanes take different pairs and the workgroup splits the elements into
-        // at most MAX_PARTS parts (all lanes of a part read the same staged element), the
-        // parts are added in order through LDS (this overwrites the staged pairs).  Short
-        // ranges (would need more parts): one wave per pair, its lanes striding over the
-        // elements, a fixed-order butterfly across the lanes; the staged pairs survive.
-        // Returns whether the staged pairs are still in place.
-        double2* red = lds;
-        auto eval_range = [&](int klo, int khi) -> bool {
-            constexpr int MAX_PARTS = 16;
-            const int cnt = khi - klo + 1;
-            const int Kh = (cnt + 1) / 2;
-            const int Kb = Kh < BLOCK ? Kh : BLOCK;
-            const int nparts = BLOCK / Kb;
-            if (nparts <= MAX_PARTS) {
-                const int part = tid / Kb, kl = tid - part * Kb;
-                const bool one_pass = Kh <= Kb;
-                double2* rbuf = one_pass ? red : red_small;
-                for (int k0 = 0; k0 < Kh; k0 += Kb) {
-                    const int kk = k0 + kl;
-                    double Na = 0.0, Da = 0.0, Nb = 0.0, Db = 0.0;
-                    if (part < nparts && kk < Kh) {
-                        const int ka = klo + 2 * kk, kb2 = ka + 1 <= khi ? ka + 1 : ka;
-                        gcv_two(stage, n, part, nparts, mus[ka], mus[kb2], Na, Da, Nb, Db);
-                    }
-                    if (one_pass) __syncthreads();
-                    rbuf[2 * tid] = make_double2(Na, Da);
-                    rbuf[2 * tid + 1] = make_double2(Nb, Db);
-                    __syncthreads();
-                    if (part == 0 && kk < Kh) {
-                        double2 A = rbuf[2 * kl], B = rbuf[2 * kl + 1];
-                        for (int p = 1; p < nparts; ++p) {
-                            const double2 va = rbuf[2 * (p * Kb + kl)], vb = rbuf[2 * (p * Kb + kl) + 1];
-                            A.x += va.x;
-                            A.y += va.y;
-                            B.x += vb.x;
-                            B.y += vb.y;
-                        }
-                        const int ka = klo + 2 * kk;
-                        Gs[ka] = A.x / (A.y * A.y);
-                        if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka] = Gs[ka];
-                        if (ka + 1 <= khi) {
-                            Gs[ka + 1] = B.x / (B.y * B.y);
-                            if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka + 1] = Gs[ka + 1];
-                        }
-                    }
-                    __syncthreads();
-                }
-                return !one_pass;  // red_small leaves the staged pairs alone
-            }
-            constexpr int NW = BLOCK / 64;
-            const int wv = tid >> 6, lane = tid & 63;
-            for (int k0 = 0; k0 < Kh; k0 += NW) {
-                const int kk = k0 + wv;
-                if (kk < Kh) {  // uniform across the wave
-                    const int ka = klo + 2 * kk, kb2 = ka + 1 <= khi ? ka + 1 : ka;
-                    double Na, Da, Nb, Db;
-                    gcv_two(stage, n, lane, 64, mus[ka], mus[kb2], Na, Da, Nb, Db);
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) {
-                        Na += __shfl_xor(Na, o, 64);
-                        Da += __shfl_xor(Da, o, 64);
-                        Nb += __shfl_xor(Nb, o, 64);
-                        Db += __shfl_xor(Db, o, 64);
-                    }
-                    if (lane == 0) {
-                        Gs[ka] = Na / (Da * Da);
-                        if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka] = Gs[ka];
-                        if (ka + 1 <= khi) {
-                            Gs[ka + 1] = Nb / (Db * Db);
-                            if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka + 1] = Gs[ka + 1];
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            return true;
-        };
-        // first minimum over [klo, khi]; -1 if some G is not finite
-        auto argmin_range = [&](int klo, int khi) {
-            if (tid < 64) {
-                double best = 0.0;
-                int bk = -1, bad = 0;
-                for (int k = klo + tid; k <= khi; k += 64) {
-                    const double gv = Gs[k];
-                    if (!isfinite(gv)) bad = 1;
-                    if (bk < 0 || gv < best) {
-                        best = gv;
-                        bk = k;
-                    }
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double ob = __shfl_xor(best, off, 64);
-                    const int ok = __shfl_xor(bk, off, 64);
-                    bad |= __shfl_xor(bad, off, 64);
-                    if (ok >= 0 && (bk < 0 || ob < best || (ob == best && ok < bk))) {
-                        best = ob;
-                        bk = ok;
-                    }
-                }
-                if (tid == 0) s_kbest = bad ? -1 : bk;
-            }
-            __syncthreads();
-            return __builtin_amdgcn_readfirstlane(s_kbest);
-        };
-        int kstar;
-        if constexpr (MODE == MODE_LEARNED || MODE == MODE_FUSED) {
-            // nearest grid index to the prediction, then the certificate bracket
-            if (tid < 64) {  // wave 0: lane-strided scan, then a first-index argmin across lanes
-                const double pr = static_cast<double>(MODE == MODE_FUSED ? s_pred : a.pred[sg.item]);
-                int kh = K;
-                double bd = __builtin_inf();
-                for (int k = tid; k < K; k += 64) {
-                    const double dd = fabs(log10(mus[k]) - pr);
-                    if (dd < bd) {
-                        bd = dd;
-                        kh = k;
-                    }
-                }
-                for (int o = 32; o > 0; o >>= 1) {
-                    const double od = __shfl_xor(bd, o);
-                    const int ok = __shfl_xor(kh, o);
-                    if (od < bd || (od == bd && ok < kh)) {
-                        bd = od;
-                        kh = ok;
-                    }
-                }
-                if (tid == 0) s_item = kh;  // reused as a broadcast slot (the queue index was already read)
-            }
-            __syncthreads();
-            const int khat = __builtin_amdgcn_readfirstlane(s_item);
-            __syncthreads();
-            const int half = a.cert_half;
-            const int lo = khat - half < 0 ? 0 : khat - half;
-            const int hi = khat + half > K - 1 ? K - 1 : khat + half;
-            stage_fill();
-            const bool staged = eval_range(lo, hi);
-            const int km = argmin_range(lo, hi);
-            const bool edge = (km == lo && lo > 0) || (km == hi && hi < K - 1);
-            const bool ok = km >= 0 && !edge && Gs[khat] <= CERT_SLACK * Gs[km];
-            if (ok) {
-                kstar = km;
-            } else {
-                if (!staged) stage_fill();  // the part sums went through the staging buffer
-                eval_range(0, K - 1);
-                kstar = argmin_range(0, K - 1);
-            }
-            if (tid == 0) a.fallback[sg.item] = ok ? 0 : 1;
-        } else {
-            stage_fill();
-            eval_range(0, K - 1);
-            kstar = argmin_range(0, K - 1);
-        }
-        if (tid == 0) {
-            a.kbest[sg.item] = kstar;
-            a.mubest[sg.item] = kstar >= 0 ? mus[kstar] : __builtin_nan("");
-        }
-        __syncthreads();
-        const int kb = kstar;
-        const double mu_s = kb >= 0 ? mus[kb] : __builtin_nan("");
-
-        __builtin_amdgcn_sched_barrier(0);
-        // ---- Tikhonov filter at mu*: fhat = d ghat / (d^2 + mu s^2)
-#pragma unroll
-        for (int k = 0; k < SL; ++k) c[k] = dj[k] * c[k] / fma(mu_s, sj[k] * sj[k], dj[k] * dj[k]);
-        const double fpoly = z0 / fma(mu_s, s_poly * s_poly, z0 * z0);
-        const double fx1 = fpoly * x1, fxn = fpoly * xn;
-        if (tid < rank) bc[tid].x = c[0];
-        if (S == 2) {  // the second half of the split reads the coefficients again
-#pragma unroll
-            for (int k = 0; k < SL; ++k) {
-                const int j = tid + k * BLOCK;
-                if (j < N) scratch[j] = c[k];
-            }
-        }
-        __syncthreads();
-        const double beta0 = rank > 0 ? bc[0].x : 0.0;
-        const double beta1 = rank > 1 ? bc[1].x : 0.0;
-
-        __builtin_amdgcn_sched_barrier(0);
-        // ---- forward transform of the filtered coefficients
-        {
-            auto in_fwd = [&](int k, int j) {
-                const double v = S == 2 ? scratch[j] : c[k];
-                return make_double2(j >= rank ? v : 0.0, 0.0);
-            };
-            auto park = [&](int j, double y) { f[j + 1] = y; };
-            auto unpark = [&](int j) { return f[j + 1]; };
-            double u[SL];
-            chirp_core<LOGP, S, SL>(u, ax.syn, ax.syn.mode, N, lds, tw, in_fwd, park, unpark);
-#pragma unroll
-            for (int k = 0; k < SL; ++k) {
-                const int j = tid + k * BLOCK;
-                if (j < N) {
-                    double y = u[k] + ax.q[j + 1] * fx1 + ax.q[N - j] * fxn;
-                    if (rank > 0) y += ax.bub[j] * beta0;
-                    if (rank > 1) y += ax.bub[N + j] * beta1;
-                    f[j + 1] = y;
-                    if (kind == HT_KIND_C) {
-                        if (j == 0) f[0] = q1 * fx1 + u[k];
-                        if (j == N - 1) f[n - 1] = q1 * fxn + u[k];
-                    }
-                }
-            }
-            if (tid == 0 && kind != HT_KIND_C) {
-                f[0] = q1 * fx1;
-                f[n - 1] = q1 * fxn;
-            }
-        }
-    }
-}
-
 }  // namespace ht
 
 using namespace ht;
@@ -740,60 +49,17 @@ int class_logp(int c) { return c == 5 ? 13 : MIN_LOGP + c; }
 bool is_split(int c) { return c == 5; }
 bool has_variant(int c) { return class_logp(c) >= 12; }
 
-template <int LOGP, int S, int SL>
-int max_active(int device) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_restore<LOGP, S, SL, MODE_SCAN>, (1 << LOGP) / SL, 0) !=
-        hipSuccess)
-        nb = 1;
-    hipDeviceProp_t prop;
-    int cus = 256;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
-    return std::max(1, nb) * cus;
-}
-
-int full_grid(int cls, int variant, int device) {
-    switch (cls) {
-        case 0: return max_active<9, 1, 8>(device);
-        case 1: return max_active<10, 1, 8>(device);
-        case 2: return max_active<11, 1, 8>(device);
-        case 3: return variant ? max_active<12, 1, 16>(device) : max_active<12, 1, 8>(device);
-        case 4: return variant ? max_active<13, 1, 16>(device) : max_active<13, 1, 8>(device);
-        default: return variant ? max_active<13, 2, 16>(device) : max_active<13, 2, 8>(device);
-    }
-}
-
-template <int LOGP, int S, int SL>
-void launch_class(const RaggedArgs& a, int mode, int c, int start, int cnt, int grid, hipStream_t stream) {
-    const dim3 g(static_cast<unsigned>(grid)), b((1 << LOGP) / SL);
-    if (mode == MODE_FEATURES)
-        hipLaunchKernelGGL((k_restore<LOGP, S, SL, MODE_FEATURES>), g, b, 0, stream, a, c, start, cnt);
-    else if (mode == MODE_LEARNED)
-        hipLaunchKernelGGL((k_restore<LOGP, S, SL, MODE_LEARNED>), g, b, 0, stream, a, c, start, cnt);
-    else if (mode == MODE_FUSED)
-        hipLaunchKernelGGL((k_restore<LOGP, S, SL, MODE_FUSED>), g, b, 0, stream, a, c, start, cnt);
-    else
-        hipLaunchKernelGGL((k_restore<LOGP, S, SL, MODE_SCAN>), g, b, 0, stream, a, c, start, cnt);
-}
+int full_grid(int cls, int variant, int device) { return batch_full_grid(cls, variant, device); }
 
 void launch_any(const RaggedArgs& a, int mode, int c, int variant, int start, int cnt, int grid, hipStream_t stream) {
-    switch (c) {
-        case 0: launch_class<9, 1, 8>(a, mode, c, start, cnt, grid, stream); break;
-        case 1: launch_class<10, 1, 8>(a, mode, c, start, cnt, grid, stream); break;
-        case 2: launch_class<11, 1, 8>(a, mode, c, start, cnt, grid, stream); break;
-        case 3:
-            if (variant) launch_class<12, 1, 16>(a, mode, c, start, cnt, grid, stream);
-            else launch_class<12, 1, 8>(a, mode, c, start, cnt, grid, stream);
-            break;
-        case 4:
-            if (variant) launch_class<13, 1, 16>(a, mode, c, start, cnt, grid, stream);
-            else launch_class<13, 1, 8>(a, mode, c, start, cnt, grid, stream);
-            break;
-        default:
-            if (variant) launch_class<13, 2, 16>(a, mode, c, start, cnt, grid, stream);
-            else launch_class<13, 2, 8>(a, mode, c, start, cnt, grid, stream);
-            break;
-    }
+    if (mode == MODE_FEATURES)
+        batch_launch_features(a, c, variant, start, cnt, grid, stream);
+    else if (mode == MODE_LEARNED)
+        batch_launch_learned(a, c, variant, start, cnt, grid, stream);
+    else if (mode == MODE_FUSED)
+        batch_launch_fused(a, c, variant, start, cnt, grid, stream);
+    else
+        batch_launch_scan(a, c, variant, start, cnt, grid, stream);
 }
 
 ht_status run_classes(const ht_batch* bt, const RaggedArgs& a, int mode, hipStream_t stream) {
@@ -936,6 +202,7 @@ extern "C" ht_status ht_batch_destroy(ht_batch* bt) {
 
 extern "C" int64_t ht_batch_total_length(const ht_batch* bt) { return bt ? bt->total_n : -1; }
 extern "C" int64_t ht_batch_psf_total(const ht_batch* bt) { return bt ? bt->total_psf : -1; }
+extern "C" int64_t ht_batch_count(const ht_batch* bt) { return bt ? bt->count : -1; }
 
 extern "C" ht_status ht_batch_restore_fused(const ht_batch* bt, const double* signal, const double* psf, int norm,
                                             const double* mu_grid, int32_t K, const ht_mlp_weights* net,

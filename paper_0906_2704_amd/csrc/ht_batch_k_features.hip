@@ -1,0 +1,11 @@
+// Kernels of the ragged-batch restore in mode MODE_FEATURES (batch_kernel.h), one source file per
+// mode so that the modes compile in parallel.
+#include "batch_kernel.h"
+
+namespace ht {
+
+void batch_launch_features(const RaggedArgs& a, int c, int variant, int start, int cnt, int grid, hipStream_t stream) {
+    launch_mode<MODE_FEATURES>(a, c, variant, start, cnt, grid, stream);
+}
+
+}  // namespace ht

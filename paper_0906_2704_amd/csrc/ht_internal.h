@@ -112,6 +112,12 @@ struct ht_plan {
     void* arena32 = nullptr;           // their tables
     ht::XgcvParams xg[2]{};            // exact GCV tables per axis (vec in xg_mem)
     void* xg_mem[2] = {nullptr, nullptr};
+    // 2D exact GCV workspace (ht_gcv_scan_exact on 2D plans): row-pass outputs, column-pass
+    // partials and the G values when the caller passes none, sized for grids of up to
+    // xg2_max_k values (ht_plan_reserve_exact_gcv)
+    void* xg2_mem = nullptr;
+    int xg2_max_k = 0;
+    int64_t xg2_rows_elems = 0, xg2_part_elems = 0, xg2_g_elems = 0;
 };
 
 namespace ht {
@@ -129,6 +135,9 @@ void gemm_release(GemmState* g);
 // exact GCV tables of a 1D plan (ht_plan.hip)
 struct HostAxis;
 ht_status build_exact_gcv(const HostAxis& h, ht_plan* p, int axis);
+// the 2D exact GCV workspace of a plan for grids of up to max_k values (ht_spectral.hip)
+ht_status reserve_exact_gcv_2d(ht_plan* p, int max_k);
+constexpr int XG2_DEFAULT_K = 128;  // grid size reserved at plan creation
 
 // float32 chirp-z cores (ht_plan.hip)
 ht_status plan_build_f32(ht_plan* p);

@@ -745,6 +745,13 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
             ht_plan_destroy(p);
             return fail(HT_ERR_OOM, "ht_plan_create: GCV workspace allocation failed");
         }
+        if (p->xg_mem[0]) {  // exact GCV for images: workspace for grids of up to 128 values
+            st = reserve_exact_gcv_2d(p, XG2_DEFAULT_K);
+            if (st != HT_OK) {
+                ht_plan_destroy(p);
+                return st;
+            }
+        }
     }
     *out = p;
     return HT_OK;
@@ -755,6 +762,7 @@ extern "C" ht_status ht_plan_destroy(ht_plan* p) {
     if (p->arena) (void)hipFree(p->arena);
     if (p->work) (void)hipFree(p->work);
     if (p->gcv_part) (void)hipFree(p->gcv_part);
+    if (p->xg2_mem) (void)hipFree(p->xg2_mem);
     for (void* m : p->xg_mem)
         if (m) (void)hipFree(m);
     gemm_release(p->gemm);

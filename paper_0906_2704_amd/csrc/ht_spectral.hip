@@ -1051,37 +1051,79 @@ extern "C" ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const v
 // weighted row sums u_p = sum_i lambda_p[i] v_i; so ||.||^2 = sum_{i interior} ||T1 v_i||^2
 // + sum_{p,q} M0[p,q] (<u_p, u_q>_interior + ell1(u_p)^H M1 ell1(u_q)).  Row pass (the 1D
 // kernel on every row, emitting its functionals), column pass (u_p over the interior
-// columns and their products), combination per grid value.  Images in chunks of at most
-// 256 MiB of row-pass workspace, allocated on the stream.
+// columns and their products), combination per grid value.  Images in chunks that fit the
+// workspace: row-pass outputs n0 K XG2_RW doubles and column-pass partials
+// nblk K XG2_NE double2 per image, and K doubles per image for G when the caller passes
+// none.
+struct Xg2Work {
+    double* rows;
+    int64_t rows_elems;
+    double2* part;
+    int64_t part_elems;
+    double* G;            // used when the caller's G is null
+    int64_t g_elems;
+};
+
+static int64_t xg2_rows_per_img(const ht_plan* p, int K) { return static_cast<int64_t>(p->ax[0].n) * K * XG2_RW; }
+static int64_t xg2_part_per_img(const ht_plan* p, int K) {
+    return static_cast<int64_t>((p->ax[1].n - 2 + 63) / 64) * K * XG2_NE;
+}
+
+namespace ht {
+// Reserve the plan's 2D exact GCV workspace for grids of up to max_k values: row-pass
+// outputs for a chunk of images (at most 64 MiB, at least one image), partials for the
+// same chunk, G for max_batch images.
+ht_status reserve_exact_gcv_2d(ht_plan* p, int max_k) {
+    const int64_t cap = int64_t{1} << 23;  // doubles: 64 MiB
+    const int64_t ri = xg2_rows_per_img(p, max_k);
+    int64_t chunk = cap / ri;
+    chunk = chunk < 1 ? 1 : (chunk > p->max_batch ? p->max_batch : chunk);
+    const int64_t rows = chunk * ri, part = chunk * xg2_part_per_img(p, max_k), g = int64_t{max_k} * p->max_batch;
+    void* mem = nullptr;
+    if (hipMalloc(&mem, sizeof(double) * (rows + g) + sizeof(double2) * part) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HT_ERR_OOM, "exact GCV workspace allocation failed");
+    }
+    if (p->xg2_mem) (void)hipFree(p->xg2_mem);
+    p->xg2_mem = mem;
+    p->xg2_max_k = max_k;
+    p->xg2_rows_elems = rows;
+    p->xg2_part_elems = part;
+    p->xg2_g_elems = g;
+    return HT_OK;
+}
+}  // namespace ht
+
 static ht_status gcv_exact_2d(const ht_plan* plan, const void* coeff, const Spec& sp, GcvOut o, int64_t batch,
-                              hipStream_t stream) {
+                              const Xg2Work& ws, hipStream_t stream) {
     const int n0 = plan->ax[0].n, n1 = plan->ax[1].n, K = o.K;
-    const int64_t per_img = static_cast<int64_t>(n0) * K * XG2_RW;
-    int64_t chunk = (static_cast<int64_t>(1) << 25) / per_img;  // 2^25 doubles = 256 MiB
-    chunk = chunk < 1 ? 1 : (chunk > batch ? batch : chunk);
-    const int nblk = (n1 - 2 + 63) / 64;
-    double* rows = nullptr;
-    double2* part = nullptr;
+    const int64_t ri = xg2_rows_per_img(plan, K), pi = xg2_part_per_img(plan, K);
+    int64_t chunk = ws.rows_elems / ri;
+    if (pi * chunk > ws.part_elems) chunk = ws.part_elems / pi;
+    chunk = chunk > batch ? batch : chunk;
+    if (chunk < 1) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: one image at this K exceeds the workspace");
     double* Gb = o.G;
-    bool ok = hipMallocAsync(reinterpret_cast<void**>(&rows), sizeof(double) * per_img * chunk, stream) == hipSuccess &&
-              hipMallocAsync(reinterpret_cast<void**>(&part), sizeof(double2) * chunk * nblk * K * XG2_NE, stream) ==
-                  hipSuccess;
-    if (ok && !Gb) ok = hipMallocAsync(reinterpret_cast<void**>(&Gb), sizeof(double) * K * batch, stream) == hipSuccess;
-    ht_status st = ok ? HT_OK : fail(HT_ERR_OOM, "ht_gcv_scan_exact: workspace allocation failed");
+    if (!Gb) {
+        if (int64_t{K} * batch > ws.g_elems)
+            return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: the G values exceed the workspace (pass G)");
+        Gb = ws.G;
+    }
+    const int nblk = (n1 - 2 + 63) / 64;
     const bool cp = plan->cplx != 0;
+    ht_status st = HT_OK;
     for (int64_t b0 = 0; st == HT_OK && b0 < batch; b0 += chunk) {
         const unsigned nb = static_cast<unsigned>(batch - b0 < chunk ? batch - b0 : chunk);
         hipLaunchKernelGGL((cp ? k_gcv_exact<true, true> : k_gcv_exact<false, true>), dim3(n0, nb), dim3(XG_THREADS), 0,
-                           stream, sp, coeff, o, plan->xg[1], n1, b0, rows);
+                           stream, sp, coeff, o, plan->xg[1], n1, b0, ws.rows);
         st = check_hip(hipGetLastError(), "ht_gcv_scan_exact row launch");
         if (st != HT_OK) break;
         hipLaunchKernelGGL(cp ? k_xg2_cols<true> : k_xg2_cols<false>, dim3(nblk, nb, (K + XG2_MU - 1) / XG2_MU), dim3(64),
                            0, stream, sp, coeff,
-                           o.mus, o.mu_stride, K, plan->xg[0], n0, n1, b0, part);
+                           o.mus, o.mu_stride, K, plan->xg[0], n0, n1, b0, ws.part);
         st = check_hip(hipGetLastError(), "ht_gcv_scan_exact column launch");
         if (st != HT_OK) break;
-        hipLaunchKernelGGL(k_xg2_combine, dim3(K, nb), dim3(64), 0, stream, static_cast<const double*>(rows),
-                           static_cast<const double2*>(part), nblk, K, plan->xg[0], plan->xg[1], n0, b0, Gb);
+        hipLaunchKernelGGL(k_xg2_combine, dim3(K, nb), dim3(64), 0, stream, static_cast<const double*>(ws.rows),
+                           static_cast<const double2*>(ws.part), nblk, K, plan->xg[0], plan->xg[1], n0, b0, Gb);
         st = check_hip(hipGetLastError(), "ht_gcv_scan_exact combine launch");
     }
     if (st == HT_OK) {
@@ -1089,10 +1131,23 @@ static ht_status gcv_exact_2d(const ht_plan* plan, const void* coeff, const Spec
                            static_cast<const double*>(Gb), o);
         st = check_hip(hipGetLastError(), "ht_gcv_scan_exact argmin launch");
     }
-    if (rows) (void)hipFreeAsync(rows, stream);
-    if (part) (void)hipFreeAsync(part, stream);
-    if (Gb && Gb != o.G) (void)hipFreeAsync(Gb, stream);
     return st;
+}
+
+extern "C" ht_status ht_plan_reserve_exact_gcv(ht_plan* plan, int32_t max_k) {
+    if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_plan_reserve_exact_gcv: null plan");
+    if (max_k < 1 || max_k > 1024) return fail(HT_ERR_INVALID_ARG, "ht_plan_reserve_exact_gcv: max_k must be in [1, 1024]");
+    if (plan->ndim != 2 || !plan->xg_mem[0] || max_k <= plan->xg2_max_k) return HT_OK;
+    ht_status st = check_hip(hipSetDevice(plan->device), "ht_plan_reserve_exact_gcv: hipSetDevice");
+    if (st != HT_OK) return st;
+    st = check_hip(hipDeviceSynchronize(), "ht_plan_reserve_exact_gcv: synchronize");
+    return st != HT_OK ? st : reserve_exact_gcv_2d(plan, max_k);
+}
+
+static Xg2Work plan_xg2_work(const ht_plan* p) {
+    double* base = static_cast<double*>(p->xg2_mem);
+    return Xg2Work{base, p->xg2_rows_elems, reinterpret_cast<double2*>(base + p->xg2_rows_elems + p->xg2_g_elems),
+                   p->xg2_part_elems, base + p->xg2_rows_elems, p->xg2_g_elems};
 }
 
 extern "C" ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, const void* d, const double* s,
@@ -1115,8 +1170,11 @@ extern "C" ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, c
         ht_status st2 = check_spectrum(plan, eig_batch, layout, batch, "ht_gcv_scan_exact");
         if (st2 != HT_OK) return st2;
         const Spec sp = make_spec(plan, d, s, eig_batch, layout);
+        if (K > plan->xg2_max_k)
+            return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact: K exceeds the grid size reserved for the plan "
+                                            "(ht_plan_reserve_exact_gcv)");
         GcvOut o{mu_grid, grid_per_item ? static_cast<int64_t>(K) : 0, K, G, k_best, mu_best};
-        return gcv_exact_2d(plan, coeff, sp, o, batch, stream);
+        return gcv_exact_2d(plan, coeff, sp, o, batch, plan_xg2_work(plan), stream);
     }
     if (!plan->xg_mem[0])  // periodic / reflective: T is unitary and eq. gcv2 is eq. gcv
         return ht_gcv_scan(plan, coeff, d, s, eig_batch, layout, mu_grid, K, grid_per_item, G, k_best, mu_best, batch,

@@ -51,12 +51,14 @@ def lib():
     L.ht_gcv_scan.argtypes = [P, VP, VP, VP, I64, ctypes.c_int, VP, I32, ctypes.c_int, VP, VP, VP, I64, VP]
     L.ht_gcv_scan_exact.argtypes = [P, VP, VP, VP, I64, ctypes.c_int, VP, I32, ctypes.c_int, VP, VP, VP, I64, VP]
     L.ht_plan_set_precision.argtypes = [P, ctypes.c_int]
+    L.ht_plan_reserve_exact_gcv.argtypes = [P, I32]
     L.ht_plan_precision.argtypes = [P]
     L.ht_status_str.argtypes = [ctypes.c_int]
     L.ht_status_str.restype = ctypes.c_char_p
     L.ht_last_error.restype = ctypes.c_char_p
     for name in ("ht_plan_create", "ht_plan_destroy", "ht_eigs", "ht_eigs2d", "ht_transform_inv", "ht_transform_fwd",
-                 "ht_tikhonov_filter", "ht_gcv_scan", "ht_gcv_scan_exact", "ht_plan_set_precision", "ht_plan_precision"):
+                 "ht_tikhonov_filter", "ht_gcv_scan", "ht_gcv_scan_exact", "ht_plan_set_precision", "ht_plan_precision",
+                 "ht_plan_reserve_exact_gcv"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -123,6 +125,10 @@ class Plan:
     def set_precision(self, precision):
         """Core arithmetic: "f64" (default), "bf16x3" or "f16x3" (ht_plan_set_precision)."""
         _check(lib().ht_plan_set_precision(self._h, PRECISIONS.get(precision, precision)), "ht_plan_set_precision")
+
+    def reserve_exact_gcv(self, max_k):
+        """Size the 2D exact GCV workspace for grids of up to max_k values (set-up call)."""
+        _check(lib().ht_plan_reserve_exact_gcv(self._h, int(max_k)), "ht_plan_reserve_exact_gcv")
 
     @property
     def precision(self):
@@ -385,8 +391,30 @@ def _learned_sigs(L):
     L.ht_mse_grad.argtypes = [VP, VP, VP, VP, I64, VP]
     L.ht_outer.argtypes = [VP, VP, VP, I64, Ci, VP]
     L.ht_adam.argtypes = [VP, VP, VP, VP, I64, F, F, F, F, I64, VP, VP]
+    L.ht_mlp_param_count.argtypes = []
+    L.ht_mlp_param_count.restype = I64
+    L.ht_mlp_create.argtypes = [I64, ctypes.POINTER(VP)]
+    L.ht_mlp_destroy.argtypes = [VP]
+    L.ht_mlp_set_params.argtypes = [VP, VP, VP]
+    L.ht_mlp_get.argtypes = [VP, Ci, VP, VP]
+    L.ht_mlp_set_state.argtypes = [VP, VP, VP, I64, VP, VP, VP]
+    L.ht_mlp_steps.argtypes = [VP]
+    L.ht_mlp_steps.restype = I64
+    L.ht_mlp_fit_standardisation.argtypes = [VP, VP, I64, VP]
+    L.ht_mlp_forward.argtypes = [VP, VP, I64, VP, VP]
+    L.ht_mlp_backward.argtypes = [VP, VP, I64, VP, VP]
+    L.ht_mlp_adam_step.argtypes = [VP, F, VP]
+    L.ht_mlp_train_step.argtypes = [VP, VP, VP, VP, I64, F, VP, VP]
+    L.ht_mlp_weights_of.argtypes = [VP, ctypes.POINTER(MlpWeights)]
+    L.ht_log10_labels.argtypes = [VP, VP, I64, VP]
+    L.ht_lambda_predict.argtypes = [VP, VP, VP, VP, VP, VP, VP, VP, VP]
+    L.ht_batch_count.argtypes = [VP]
+    L.ht_batch_count.restype = I64
     for name in ("ht_batch_features", "ht_batch_restore_learned", "ht_batch_restore_fused", "ht_gemm_bf16", "ht_to_bf16", "ht_from_bf16",
-                 "ht_gelu_backward", "ht_colsum", "ht_mse_grad", "ht_outer", "ht_adam"):
+                 "ht_gelu_backward", "ht_colsum", "ht_mse_grad", "ht_outer", "ht_adam", "ht_mlp_create",
+                 "ht_mlp_destroy", "ht_mlp_set_params", "ht_mlp_get", "ht_mlp_set_state", "ht_mlp_fit_standardisation",
+                 "ht_mlp_forward", "ht_mlp_backward", "ht_mlp_adam_step", "ht_mlp_train_step", "ht_mlp_weights_of",
+                 "ht_log10_labels", "ht_lambda_predict"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -527,3 +555,112 @@ def ht_adam(p, g, m, v, lr, step, pb=None, beta1=0.9, beta2=0.999, eps=1e-8):
     _check(_llib().ht_adam(_p(p, "p", torch.float32), _p(g, "g", torch.float32), _p(m, "m", torch.float32),
                            _p(v, "v", torch.float32), p.numel(), float(lr), float(beta1), float(beta2), float(eps),
                            int(step), _p(pb, "pb", BF16), _stream()), "ht_adam")
+
+
+# ----------------------------------------------------------------------------- the network object
+
+MLP_PARAMS_VEC, MLP_GRADS_VEC, MLP_ADAM_M_VEC, MLP_ADAM_V_VEC, MLP_MEAN_VEC, MLP_STD_VEC = range(6)
+
+
+class Mlp:
+    """The learned-mu network owned by the library (ht_mlp_create): parameters, Adam state,
+    standardisation and activation buffers for up to `max_rows` rows."""
+
+    def __init__(self, max_rows):
+        L = _llib()
+        h = ctypes.c_void_p()
+        _check(L.ht_mlp_create(int(max_rows), ctypes.byref(h)), "ht_mlp_create")
+        self._h = h
+        self.max_rows = int(max_rows)
+        self.param_count = int(L.ht_mlp_param_count())
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _check(_llib().ht_mlp_destroy(self._h), "ht_mlp_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def steps(self):
+        return int(_llib().ht_mlp_steps(self._h))
+
+    def get(self, which, out=None):
+        n = 72 if which in (MLP_MEAN_VEC, MLP_STD_VEC) else self.param_count
+        out = torch.empty(n, dtype=torch.float32, device="cuda") if out is None else out
+        _check(_llib().ht_mlp_get(self._h, int(which), _p(out, "out", torch.float32), _stream()), "ht_mlp_get")
+        return out
+
+
+def ht_mlp_set_params(mlp, params):
+    _check(_llib().ht_mlp_set_params(mlp.handle, _p(params, "params", torch.float32), _stream()), "ht_mlp_set_params")
+
+
+def ht_mlp_set_state(mlp, adam_m=None, adam_v=None, steps=0, mean=None, std=None):
+    _check(_llib().ht_mlp_set_state(mlp.handle, _p(adam_m, "adam_m", torch.float32), _p(adam_v, "adam_v", torch.float32),
+                                    int(steps), _p(mean, "mean", torch.float32), _p(std, "std", torch.float32),
+                                    _stream()), "ht_mlp_set_state")
+
+
+def ht_mlp_fit_standardisation(mlp, features):
+    _check(_llib().ht_mlp_fit_standardisation(mlp.handle, _p(features, "features", torch.float32),
+                                              int(features.shape[0]), _stream()), "ht_mlp_fit_standardisation")
+
+
+def ht_mlp_forward(mlp, features, pred=None):
+    rows = int(features.shape[0])
+    _check(_llib().ht_mlp_forward(mlp.handle, _p(features, "features", torch.float32), rows,
+                                  _p(pred, "pred", torch.float32), _stream()), "ht_mlp_forward")
+    return pred
+
+
+def ht_mlp_backward(mlp, target, loss=None):
+    _check(_llib().ht_mlp_backward(mlp.handle, _p(target, "target", torch.float32), int(target.shape[0]),
+                                   _p(loss, "loss", torch.float32), _stream()), "ht_mlp_backward")
+
+
+def ht_mlp_adam_step(mlp, lr):
+    _check(_llib().ht_mlp_adam_step(mlp.handle, float(lr), _stream()), "ht_mlp_adam_step")
+
+
+def ht_mlp_train_step(mlp, features, target, idx, lr, loss=None):
+    _check(_llib().ht_mlp_train_step(mlp.handle, _p(features, "features", torch.float32),
+                                     _p(target, "target", torch.float32), _p(idx, "idx", torch.int32),
+                                     int(idx.shape[0]), float(lr), _p(loss, "loss", torch.float32), _stream()),
+           "ht_mlp_train_step")
+
+
+def ht_mlp_weights_of(mlp):
+    w = MlpWeights()
+    _check(_llib().ht_mlp_weights_of(mlp.handle, ctypes.byref(w)), "ht_mlp_weights_of")
+    return w
+
+
+def ht_log10_labels(mu, labels=None):
+    labels = torch.empty(mu.shape, dtype=torch.float32, device=mu.device) if labels is None else labels
+    _check(_llib().ht_log10_labels(_p(mu, "mu", torch.float64), _p(labels, "labels", torch.float32), mu.numel(),
+                                   _stream()), "ht_log10_labels")
+    return labels
+
+
+def ht_lambda_predict(batch, mlp, signal, psf, coeff=None, features=None, spectrum=None, pred=None):
+    """Returns (pred, coeff, features): predicted log10 mu per signal, with the feature
+    pass's coefficients and features."""
+    L = _llib()
+    dev = signal.device
+    coeff = torch.empty(batch.total_length, dtype=torch.float64, device=dev) if coeff is None else coeff
+    features = torch.empty((batch.count, 72), dtype=torch.float32, device=dev) if features is None else features
+    pred = torch.empty(batch.count, dtype=torch.float32, device=dev) if pred is None else pred
+    _check(L.ht_lambda_predict(batch.handle, mlp.handle, _p(signal, "signal", torch.float64),
+                               _p(psf, "psf", torch.float64), _p(coeff, "coeff", torch.float64),
+                               _p(features, "features", torch.float32), _p(spectrum, "spectrum", torch.float64),
+                               _p(pred, "pred", torch.float32), _stream()), "ht_lambda_predict")
+    return pred, coeff, features

@@ -235,3 +235,31 @@ def test_exact_gcv_2d_odd_grid_per_image_and_small_image(ht):
             record("gcv-exact-2d odd %s %dx%d image %d" % (kind, n0, n1, b), err, 1e-9)
             assert err < 1e-9
             assert float(mx[b]) == grids[b][int(kx[b])]
+
+
+def test_exact_gcv_2d_workspace_grid_size(ht):
+    """The 2D exact GCV runs in the plan's workspace, reserved for 128 grid values at
+    creation: a larger grid is refused until ht_plan_reserve_exact_gcv enlarges it, then
+    gives the oracle's values (also with G = NULL, the plan holding the values)."""
+    n0, n1, K = 24, 21, 200
+    plan = ht.Plan((n0, n1), 2, psf_symmetric=True, max_batch=2)
+    h0, c0 = synth.gaussian_psf(3, 1.2)
+    h1, c1 = synth.gaussian_psf(2, 1.0)
+    d, s = ht.ht_eigs(plan, to_dev(np.concatenate([h0, h1])), [len(h0), len(h1)], [c0, c1], "D2")
+    rng = np.random.default_rng(9)
+    Gs = rng.standard_normal((2, n0, n1))
+    ghat = ht.ht_transform_inv(plan, to_dev(Gs))
+    mus = synth.mu_grid(-7.0, 1.0, K)
+    with pytest.raises(ht.HTError, match="reserve"):
+        ht.ht_gcv_scan_exact(plan, ghat, d, s, to_dev(mus))
+    plan.reserve_exact_gcv(K)
+    Gx, kx, mx = ht.ht_gcv_scan_exact(plan, ghat, d, s, to_dev(mus))
+    _, kx2, _ = ht.ht_gcv_scan_exact(plan, ghat, d, s, to_dev(mus), want_G=False)
+    D = twod.eigs2d_separable("C", "C", n0, n1, h0, c0, h1, c1)
+    S = twod.smooth2d("C", "C", n0, n1, "D2")
+    for b in range(2):
+        Go = twod.gcv2d_exact_values("C", "C", twod.inverse2d("C", "C", Gs[b]), D, S, mus)
+        err = record("gcv-exact-2d K=200 image %d" % b, np.max(np.abs(Gx[b].cpu().numpy() - Go) / Go), 1e-12)
+        assert err < 1e-12
+        check_choice(int(kx[b]), Go)
+        assert int(kx2[b]) == int(kx[b])

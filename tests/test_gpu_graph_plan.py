@@ -4,7 +4,7 @@ Every entry point of a plan launches kernels only (the plan owns its tables and 
 buffers), so a whole restore -- eigenvalues, inverse transform, GCV scan, filter, forward
 transform -- can be captured once and replayed.  Each replay, with unrelated eager work
 and synchronisations in between, must reproduce the eager result bitwise (all reductions
-run in a fixed order).  The 2D exact GCV is left out: it takes a stream-ordered workspace."""
+run in a fixed order).  The 2D exact GCV works in the plan's own workspace as well."""
 
 import numpy as np
 import pytest
@@ -91,10 +91,11 @@ def test_1d_plan_pipeline_graph(ht, family, degree, sym, exact):
     plan.close()
 
 
-@pytest.mark.parametrize("precision", ["f64", "bf16x3", "f32"])
-def test_2d_mask_pipeline_graph(ht, precision):
+@pytest.mark.parametrize("precision,exact", [("f64", False), ("bf16x3", False), ("f32", False), ("f64", True)])
+def test_2d_mask_pipeline_graph(ht, precision, exact):
     """General 2D mask (ht_eigs2d, full spectrum layout) on T_C (x) T_C, in each core
-    arithmetic the plan offers for real kinds."""
+    arithmetic the plan offers for real kinds, and with the exact GCV of eq. gcv (the
+    plan's workspace)."""
     n0, n1, batch, K = 96, 80, 3, 24
     rng = np.random.default_rng(17)
     H, c0, c1 = synth.disk_psf(3.0)
@@ -117,10 +118,12 @@ def test_2d_mask_pipeline_graph(ht, precision):
     kb = torch.empty(batch, dtype=torch.int32, device=DEV)
     mb = torch.empty(batch, dtype=torch.float64, device=DEV)
 
+    scan = ht.ht_gcv_scan_exact if exact else ht.ht_gcv_scan
+
     def step():
         ht.ht_eigs2d(plan, psf, (c0, c1), "D2", d=d, s=s)
         ht.ht_transform_inv(plan, g, out=ghat)
-        ht.ht_gcv_scan(plan, ghat, d, s, mus, G=G, kb=kb, mb=mb)
+        scan(plan, ghat, d, s, mus, G=G, kb=kb, mb=mb)
         ht.ht_tikhonov_filter(plan, ghat, d, s, mb, out=fhat)
         ht.ht_transform_fwd(plan, fhat, out=f)
 

@@ -67,7 +67,7 @@ def test_network_forward_backward_match_oracle(ht):
     net.set_params(params)
     y = net.forward(torch.tensor(X, device=DEV)).cpu().numpy()
     net.backward(torch.tensor(t, device=DEV))
-    grads = [g.cpu().numpy() for g in net.G]
+    grads = net.grads_numpy()
     yw, cache = omlp.forward(params, X, bf=True)
     gw = omlp.backward(cache, yw, t.astype(np.float64), bf=True)
     assert rel_normwise(y, yw) < 5e-3

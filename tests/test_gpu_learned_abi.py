@@ -1,0 +1,183 @@
+"""The learned-mu network through the C ABI alone (ht_mlp_*, ht_log10_labels,
+ht_lambda_predict called by ctypes with raw device pointers; torch only allocates): one
+epoch of training against the float64 oracle network trained on the same minibatches
+(same bfloat16 rounding points, oracle Adam), the standardisation fit, the labels, and
+the batched prediction against the oracle's features and network."""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import learned as olearned
+from oracle import mlp as omlp
+from oracle import transforms as tr
+from paper_0906_2704_amd import synth
+
+from parity import record, rel_normwise
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+VP = ctypes.c_void_p
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_0906_2704_amd import ht
+    ht._llib()
+    return ht._llib()
+
+
+def ptr(t):
+    return VP(t.data_ptr())
+
+
+def stream():
+    return VP(torch.cuda.current_stream().cuda_stream)
+
+
+def ok(status, L, what):
+    assert status == 0, (what, L.ht_last_error().decode())
+
+
+def flat(params):
+    return np.concatenate([np.asarray(p, dtype=np.float32).ravel() for p in params])
+
+
+def unflat(v):
+    out, off = [], 0
+    for shp in [(72, 256), (256,), (256, 256), (256,), (256, 256), (256,), (256, 1), (1,)]:
+        k = int(np.prod(shp))
+        out.append(np.asarray(v[off:off + k], dtype=np.float64).reshape(shp))
+        off += k
+    return out
+
+
+def test_one_epoch_matches_oracle(L):
+    assert L.ht_mlp_param_count() == 150529
+    rng = np.random.default_rng(11)
+    rows, batch, lr = 1536, 256, 1e-3
+    # features with a learnable target (a smooth function of a few inputs), 72 columns on
+    # different scales, as the band statistics are
+    X = (rng.standard_normal((rows, 72)) * rng.uniform(0.5, 4.0, 72) + rng.uniform(-6, 2, 72)).astype(np.float32)
+    Xs = (X - X.mean(axis=0)) / X.std(axis=0)
+    t = (np.tanh(Xs[:, 0]) - 0.5 * Xs[:, 3] + 0.25 * Xs[:, 7] * Xs[:, 11] - 3.0).astype(np.float32)
+    params = omlp.init_params(rng)
+    h = VP()
+    ok(L.ht_mlp_create(batch, ctypes.byref(h)), L, "create")
+    try:
+        Xd, td = torch.tensor(X, device=DEV), torch.tensor(t, device=DEV)
+        ok(L.ht_mlp_set_params(h, ptr(torch.tensor(flat(params), device=DEV)), stream()), L, "set_params")
+        ok(L.ht_mlp_fit_standardisation(h, ptr(Xd), rows, stream()), L, "fit")
+        mean = torch.empty(72, dtype=torch.float32, device=DEV)
+        std = torch.empty(72, dtype=torch.float32, device=DEV)
+        ok(L.ht_mlp_get(h, 4, ptr(mean), stream()), L, "get mean")
+        ok(L.ht_mlp_get(h, 5, ptr(std), stream()), L, "get std")
+        mean_w = X.astype(np.float64).mean(axis=0)
+        std_w = X.astype(np.float64).std(axis=0)
+        # float32 results of float64 sums: measured 3.8e-8 / 3.0e-8
+        e_mean = record("mlp standardisation mean", rel_normwise(mean.cpu().numpy(), mean_w), 8e-8)
+        e_std = record("mlp standardisation std", rel_normwise(std.cpu().numpy(), std_w), 8e-8)
+        assert e_mean < 8e-8 and e_std < 8e-8
+        # one epoch: the GPU through ht_mlp_train_step, the oracle on the same minibatches
+        perm = rng.permutation(rows).astype(np.int32)
+        permd = torch.tensor(perm, device=DEV)
+        loss = torch.zeros(rows // batch, dtype=torch.float32, device=DEV)
+        P = [np.asarray(p, dtype=np.float64) for p in params]
+        M = [np.zeros_like(p) for p in P]
+        V = [np.zeros_like(p) for p in P]
+        mean32, std32 = mean.cpu().numpy(), std.cpu().numpy()
+        loss_w = []
+        for s in range(rows // batch):
+            idx = permd[s * batch:(s + 1) * batch]
+            ok(L.ht_mlp_train_step(h, ptr(Xd), ptr(td), ptr(idx), batch, ctypes.c_float(lr),
+                                   ptr(loss[s:s + 1]), stream()), L, "train_step")
+            sel = perm[s * batch:(s + 1) * batch]
+            xs = ((X[sel] - mean32) / std32).astype(np.float32)  # standardised in float32, as the kernel
+            yw, cache = omlp.forward([p.astype(np.float32) for p in P], xs, bf=True)
+            loss_w.append(float(np.mean((yw - t[sel]) ** 2)))
+            gw = omlp.backward(cache, yw, t[sel].astype(np.float64), bf=True)
+            P, M, V = omlp.adam_step(P, gw, M, V, s + 1, lr)
+        assert L.ht_mlp_steps(h) == rows // batch
+        pg = torch.empty(150529, dtype=torch.float32, device=DEV)
+        ok(L.ht_mlp_get(h, 0, ptr(pg), stream()), L, "get params")
+        Pg = unflat(pg.cpu().numpy())
+        # the update of every weight matrix against the oracle's (params differ from their
+        # start by 6 Adam steps of size <= lr; float32 against float64 accumulation flips
+        # occasional bfloat16 roundings of hidden activations, which changes a few
+        # near-zero gradient components and so their Adam steps): twice the measured
+        # 6.0e-3, 1.3e-3, 9.2e-4, 6.4e-4 for W1..W4
+        for l, tol in enumerate((1.2e-2, 2.6e-3, 1.9e-3, 1.3e-3)):
+            dg = Pg[2 * l] - params[2 * l]
+            dw = P[2 * l] - params[2 * l]
+            e = record("mlp epoch update W%d" % (l + 1), np.linalg.norm(dg - dw) / np.linalg.norm(dw), tol)
+            assert e < tol, l
+        e_loss = record("mlp epoch loss curve", np.max(np.abs(loss.cpu().numpy() - loss_w)) / np.max(loss_w), 1.7e-4)
+        assert e_loss < 1.7e-4
+        # the trained network's predictions on fresh rows against the oracle's trained network
+        Xt = (rng.standard_normal((200, 72)) * 2.0).astype(np.float32)
+        Xtd = torch.tensor(Xt, device=DEV)
+        pred = torch.empty(200, dtype=torch.float32, device=DEV)
+        ok(L.ht_mlp_forward(h, ptr(Xtd), 200, ptr(pred), stream()), L, "forward")
+        yw, _ = omlp.forward([p.astype(np.float32) for p in P], ((Xt - mean32) / std32).astype(np.float32), bf=True)
+        e_pred = record("mlp epoch predictions", rel_normwise(pred.cpu().numpy(), yw), 4.3e-3)
+        assert e_pred < 4.3e-3  # twice the measured 2.1e-3
+        # rows outside [1, max_rows] are refused before any launch
+        assert L.ht_mlp_forward(h, ptr(Xtd), batch + 1, ptr(pred), stream()) == 1
+    finally:
+        ok(L.ht_mlp_destroy(h), L, "destroy")
+
+
+def test_labels_and_batched_prediction(L):
+    from paper_0906_2704_amd import ht
+    nv = [256, 300, 700, 1030, 2050, 4096, 3000, 257]
+    rb = synth.ragged_batch(len(nv), n_lo=256, n_hi=4096, config=4, first_item=2100, sort_desc=False,
+                            n_values=nv, grid=(-8.0, 1.0))
+    bt = ht.Batch(rb.n, rb.degree, np.diff(rb.psf_offsets), rb.psf_center)
+    assert L.ht_batch_count(bt.handle) == len(nv)
+    g = torch.tensor(rb.g, device=DEV)
+    psf = torch.tensor(rb.psf_flat, device=DEV)
+    # labels: log10 of float64 values, rounded to float32
+    mu = torch.tensor(10.0 ** np.linspace(-8, 1, 37), device=DEV)
+    lab = torch.empty(37, dtype=torch.float32, device=DEV)
+    ok(L.ht_log10_labels(ptr(mu), ptr(lab), 37, stream()), L, "labels")
+    assert np.array_equal(lab.cpu().numpy(), np.log10(mu.cpu().numpy()).astype(np.float32))
+    # prediction in chunks of max_rows = 3 rows (three chunks for eight signals)
+    rng = np.random.default_rng(4)
+    params = omlp.init_params(rng)
+    for i in (1, 3, 5):
+        params[i] = (0.1 * rng.standard_normal(params[i].shape)).astype(np.float32)
+    h = VP()
+    ok(L.ht_mlp_create(3, ctypes.byref(h)), L, "create")
+    try:
+        ok(L.ht_mlp_set_params(h, ptr(torch.tensor(flat(params), device=DEV)), stream()), L, "set_params")
+        coeff = torch.empty_like(g)
+        feats = torch.empty((len(nv), 72), dtype=torch.float32, device=DEV)
+        pred = torch.empty(len(nv), dtype=torch.float32, device=DEV)
+        ok(L.ht_mlp_fit_standardisation(h, ptr(torch.tensor(
+            np.random.default_rng(5).standard_normal((50, 72)).astype(np.float32) * 3 - 4, device=DEV)), 50,
+            stream()), L, "fit")
+        ok(L.ht_lambda_predict(bt.handle, h, ptr(g), ptr(psf), ptr(coeff), ptr(feats), None, ptr(pred), stream()),
+           L, "predict")
+        mean = torch.empty(72, dtype=torch.float32, device=DEV)
+        std = torch.empty(72, dtype=torch.float32, device=DEV)
+        ok(L.ht_mlp_get(h, 4, ptr(mean), stream()), L, "mean")
+        ok(L.ht_mlp_get(h, 5, ptr(std), stream()), L, "std")
+        mean, std, feats, pred = (x.cpu().numpy() for x in (mean, std, feats, pred))
+        worst = 0.0
+        for b in range(len(nv)):
+            kind = {1: "AR", 2: "C", 3: "DST3"}[int(rb.degree[b])]
+            n = int(rb.n[b])
+            hh, c = rb.psf[b]
+            gb = rb.g[rb.offsets[b]:rb.offsets[b + 1]]
+            fw = olearned.features(tr.inverse(kind, gb), tr.blur_eigs(kind, n, hh, c))
+            assert np.max(np.abs(feats[b] - fw)) < 1e-5 * max(1.0, np.max(np.abs(fw))), b
+            yw, _ = omlp.forward(params, ((feats[b] - mean) / std)[None].astype(np.float32), bf=True)
+            worst = max(worst, abs(float(yw.ravel()[0]) - float(pred[b])) / max(1.0, abs(float(pred[b]))))
+        # the oracle network on the GPU's features with the same rounding points: measured
+        # 8.5e-8 (no bfloat16 rounding of a hidden activation falls differently here)
+        record("lambda_predict vs oracle network", worst, 1.7e-7)
+        assert worst < 1.7e-7
+    finally:
+        ok(L.ht_mlp_destroy(h), L, "destroy")

@@ -69,3 +69,25 @@ def test_feature_bands_and_certificate():
     G2[0] = 0.5
     assert learned.certify(G2, 0, half=4) == (0, False)         # minimum at the grid end is allowed
     assert learned.nearest_index([1e-3, 1e-2, 1e-1], -1.6) == 1
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g from zero moments, the bias-corrected moments are exactly
+    g and g^2 at every step, so each step moves a parameter by lr g / (|g| + eps)."""
+    g = [np.array([[0.5, -2.0], [1e-3, 3.0]]), np.array([-0.25])]
+    p = [np.zeros((2, 2)), np.ones(1)]
+    m = [np.zeros_like(x) for x in p]
+    v = [np.zeros_like(x) for x in p]
+    lr, eps = 1e-2, 1e-8
+    for step in range(1, 6):
+        p, m, v = mlp.adam_step(p, g, m, v, step, lr, eps=eps)
+        for pi, gi, p0 in zip(p, g, ([np.zeros((2, 2)), np.ones(1)])):
+            want = p0 - step * lr * gi / (np.abs(gi) + eps)
+            assert np.allclose(pi, want, rtol=0, atol=1e-15), step
+
+
+def test_adam_first_step_is_sign_step():
+    """From zero moments the first step is lr sign(g) |g| / (|g| + eps), whatever beta."""
+    g = [np.array([2.0, -1e-4, 0.0])]
+    p, _, _ = mlp.adam_step([np.zeros(3)], g, [np.zeros(3)], [np.zeros(3)], 1, 0.1, beta1=0.5, beta2=0.7)
+    assert np.allclose(p[0], -0.1 * g[0] / (np.abs(g[0]) + 1e-8), rtol=0, atol=1e-15)
