@@ -250,6 +250,23 @@ ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, const void* 
                             int grid_per_item, double* G, int32_t* k_best, double* mu_best,
                             int64_t batch, hipStream_t stream);
 
+/* ht_gcv_scan_exact_static -- ht_gcv_scan_exact with its 2D workspace in a fixed 64 MiB
+ * device array of the library instead of the plan's workspace: for callers that cannot
+ * allocate or rely on a per-plan reservation (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, results and error behaviour;
+ * K may be up to 1024 regardless of ht_plan_reserve_exact_gcv, but one image's row-pass
+ * outputs and partials (about n0 K 22 doubles plus 44 K ceil((n1-2)/64) doubles), plus
+ * K batch doubles when G is NULL, must fit the 2^23 doubles: otherwise
+ * HT_ERR_INVALID_ARG before any launch.  Allocates nothing (hipMalloc is never called; the
+ * array's device address is looked up once per device, at ht_plan_create).  Every call on
+ * one GPU shares that GPU's array, so calls that overlap on one GPU (different streams or
+ * threads) race: order them on one stream.  1D plans and the comparators delegate to
+ * ht_gcv_scan_exact, which needs no workspace.  The plan's device must be current.     */
+ht_status ht_gcv_scan_exact_static(const ht_plan* plan, const void* coeff, const void* d, const double* s,
+                                   int64_t eig_batch, int layout, const double* mu_grid, int32_t K,
+                                   int grid_per_item, double* G, int32_t* k_best, double* mu_best,
+                                   int64_t batch, hipStream_t stream);
+
 /* ht_plan_reserve_exact_gcv -- size the workspace of ht_gcv_scan_exact on a 2D plan for
  * grids of up to max_k values (1..1024): row-pass outputs for a chunk of images (at most
  * 64 MiB, at least one image: n0 max_k 22 doubles per image), column-pass partials for

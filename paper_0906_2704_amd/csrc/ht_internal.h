@@ -138,6 +138,8 @@ ht_status build_exact_gcv(const HostAxis& h, ht_plan* p, int axis);
 // the 2D exact GCV workspace of a plan for grids of up to max_k values (ht_spectral.hip)
 ht_status reserve_exact_gcv_2d(ht_plan* p, int max_k);
 constexpr int XG2_DEFAULT_K = 128;  // grid size reserved at plan creation
+// device address of the static scratch of ht_gcv_scan_exact_static on `device` (current)
+ht_status static_scratch_init(int device, double** out);
 
 // float32 chirp-z cores (ht_plan.hip)
 ht_status plan_build_f32(ht_plan* p);

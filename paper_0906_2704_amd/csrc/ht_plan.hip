@@ -706,6 +706,7 @@ extern "C" ht_status ht_plan_create(int ndim, const int64_t* n, int degree, int 
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return fail(HT_ERR_HIP, "ht_plan_create: no HIP device");
     const double2* tw = device_twiddles(device, &st);
+    if (tw && (st = static_scratch_init(device, nullptr)) != HT_OK) return st;
     if (!tw) return st;
     HostAxis hs[2];
     for (int a = 0; a < ndim; ++a) {

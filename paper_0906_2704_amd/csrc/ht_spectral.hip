@@ -2,6 +2,8 @@
 // Tikhonov filter (eq. freg) and the GCV scan (eqs. gcv2, mugcv).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "fft_lds.h"
 #include "ht_internal.h"
 
@@ -1144,10 +1146,78 @@ extern "C" ht_status ht_plan_reserve_exact_gcv(ht_plan* plan, int32_t max_k) {
     return st != HT_OK ? st : reserve_exact_gcv_2d(plan, max_k);
 }
 
+// ---- the allocation-free variant (ht_gcv_scan_exact_static): the workspace is one
+// file-scope device array of fixed size.  Host code never passes the array's name to a
+// kernel (in host code it is a stand-in, not a device address): its device address is
+// taken once per device with hipGetSymbolAddress, with that device current, and kept.
+constexpr int64_t STATIC_SCRATCH_DOUBLES = int64_t{1} << 23;  // 64 MiB per device
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[MAX_DEVICES] = {};
+
+namespace ht {
+// Device address of the static scratch on `device` (which must be current).
+ht_status static_scratch_init(int device, double** out) {
+    if (device < 0 || device >= MAX_DEVICES) return fail(HT_ERR_INVALID_ARG, "static scratch: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return check_hip(e, "static scratch: hipGetSymbolAddress");
+        g_scratch_ptr[device] = static_cast<double*>(ptr);
+    }
+    if (out) *out = g_scratch_ptr[device];
+    return HT_OK;
+}
+}  // namespace ht
+
 static Xg2Work plan_xg2_work(const ht_plan* p) {
     double* base = static_cast<double*>(p->xg2_mem);
     return Xg2Work{base, p->xg2_rows_elems, reinterpret_cast<double2*>(base + p->xg2_rows_elems + p->xg2_g_elems),
                    p->xg2_part_elems, base + p->xg2_rows_elems, p->xg2_g_elems};
+}
+
+extern "C" ht_status ht_gcv_scan_exact_static(const ht_plan* plan, const void* coeff, const void* d,
+                                              const double* s, int64_t eig_batch, int layout, const double* mu_grid,
+                                              int32_t K, int grid_per_item, double* G, int32_t* k_best,
+                                              double* mu_best, int64_t batch, hipStream_t stream) {
+    if (!plan) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact_static: null plan");
+    if (plan->ndim != 2 || !plan->xg_mem[0])  // 1D plans and the comparators use no workspace
+        return ht_gcv_scan_exact(plan, coeff, d, s, eig_batch, layout, mu_grid, K, grid_per_item, G, k_best, mu_best,
+                                 batch, stream);
+    if (K < 1 || K > 1024) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact_static: K must be in [1, 1024]");
+    if (batch < 0 || batch > plan->max_batch)
+        return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact_static: batch exceeds the plan's max_batch");
+    if (batch == 0) return HT_OK;
+    if (!coeff || !d || !s || !mu_grid || !k_best)
+        return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact_static: null argument");
+    ht_status st = check_spectrum(plan, eig_batch, layout, batch, "ht_gcv_scan_exact_static");
+    if (st != HT_OK) return st;
+    int dev = -1;
+    if ((st = check_hip(hipGetDevice(&dev), "ht_gcv_scan_exact_static: hipGetDevice")) != HT_OK) return st;
+    if (dev != plan->device)
+        return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact_static: the plan's device is not the current device");
+    double* base = nullptr;
+    if ((st = static_scratch_init(dev, &base)) != HT_OK) return st;
+    // partition for this call: G values (when the caller passes none), then row-pass
+    // outputs and column-pass partials for as many images per chunk as fit
+    const int64_t ri = xg2_rows_per_img(plan, K), pi = xg2_part_per_img(plan, K);
+    const int64_t g_need = G ? 0 : int64_t{K} * batch;
+    const int64_t chunk = (STATIC_SCRATCH_DOUBLES - g_need) / (ri + 2 * pi);
+    if (chunk < 1)
+        return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact_static: one image at this K exceeds the 64 MiB static "
+                                        "workspace");
+    const int64_t c = chunk > batch ? batch : chunk;
+    // 256-byte aligned pieces (the array is 256-byte aligned, ri and 2 pi are whole doubles)
+    auto up = [](int64_t e) { return (e + 31) & ~int64_t{31}; };
+    if (up(g_need) + up(c * ri) + 2 * c * pi > STATIC_SCRATCH_DOUBLES)
+        return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan_exact_static: workspace partition does not fit");
+    const Xg2Work ws{base + up(g_need), c * ri, reinterpret_cast<double2*>(base + up(g_need) + up(c * ri)), c * pi,
+                     base, g_need};
+    const Spec sp = make_spec(plan, d, s, eig_batch, layout);
+    GcvOut o{mu_grid, grid_per_item ? static_cast<int64_t>(K) : 0, K, G, k_best, mu_best};
+    return gcv_exact_2d(plan, coeff, sp, o, batch, ws, stream);
 }
 
 extern "C" ht_status ht_gcv_scan_exact(const ht_plan* plan, const void* coeff, const void* d, const double* s,

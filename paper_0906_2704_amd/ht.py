@@ -50,6 +50,8 @@ def lib():
     L.ht_tikhonov_filter.argtypes = [P, VP, VP, VP, I64, ctypes.c_int, VP, VP, I64, VP]
     L.ht_gcv_scan.argtypes = [P, VP, VP, VP, I64, ctypes.c_int, VP, I32, ctypes.c_int, VP, VP, VP, I64, VP]
     L.ht_gcv_scan_exact.argtypes = [P, VP, VP, VP, I64, ctypes.c_int, VP, I32, ctypes.c_int, VP, VP, VP, I64, VP]
+    L.ht_gcv_scan_exact_static.argtypes = [P, VP, VP, VP, I64, ctypes.c_int, VP, I32, ctypes.c_int, VP, VP, VP, I64,
+                                           VP]
     L.ht_plan_set_precision.argtypes = [P, ctypes.c_int]
     L.ht_plan_reserve_exact_gcv.argtypes = [P, I32]
     L.ht_plan_precision.argtypes = [P]
@@ -58,7 +60,7 @@ def lib():
     L.ht_last_error.restype = ctypes.c_char_p
     for name in ("ht_plan_create", "ht_plan_destroy", "ht_eigs", "ht_eigs2d", "ht_transform_inv", "ht_transform_fwd",
                  "ht_tikhonov_filter", "ht_gcv_scan", "ht_gcv_scan_exact", "ht_plan_set_precision", "ht_plan_precision",
-                 "ht_plan_reserve_exact_gcv"):
+                 "ht_plan_reserve_exact_gcv", "ht_gcv_scan_exact_static"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
