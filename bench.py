@@ -312,10 +312,12 @@ class Learned1D:
 
     profile = "k_restore_learned65536.md"
 
-    def __init__(self, torch, ht, synth, batch, train=200000, epochs=25, graph=True, workers=16, path="two-pass"):
+    def __init__(self, torch, ht, synth, batch, train=200000, epochs=25, graph=True, workers=16, path="two-pass",
+                 autotune=True):
         self.torch, self.ht, self.synth = torch, ht, synth
         self.batch, self.train_count, self.epochs = batch, train, epochs
         self.graph = graph
+        self.autotune = autotune
         self.path = path
         # fused: one kernel pass per signal (features, network, certificate, filter, forward);
         # two-pass: feature kernel -> batched network GEMMs -> certified-restore kernel
@@ -370,6 +372,23 @@ class Learned1D:
         self._launch()  # allocates the network's buffers outside any capture
         self._launch_scan()
         torch.cuda.synchronize()
+        self.tuning = None
+        if self.autotune and self.path != "fused":
+            # persistent grid and kernel variant per size class, timed on the feature pass
+            # plus the certified pass with the predictions of the trained network
+            from paper_0906_2704_amd import autotune
+            pred = self.pred.clone()
+
+            def run():
+                ht.ht_batch_features(self.bt, self.g, self.psf, self.coeff, self.feats, self.spec)
+                ht.ht_batch_restore_learned(self.bt, self.coeff, self.psf, "D2", self.mus, pred, self.learned.CERT_HALF,
+                                            kb=self.kb, mb=self.mb, fallback=self.fb, spectrum=self.spec)
+            choice, ms = autotune.tune(self.bt, run, use_cache=False,
+                                       log=lambda m: print(m, file=sys.stderr, flush=True))
+            self.tuning = {"choice": {str(c): list(v) for c, v in choice.items()},
+                           "class_ms": {str(c): round(t, 4) for c, t in ms.items()}}
+            self._launch()
+            torch.cuda.synchronize()
         self.cuda_graph = self.scan_graph = None
         if self.graph:
             self.cuda_graph = torch.cuda.CUDAGraph()
@@ -384,7 +403,9 @@ class Learned1D:
         self.ht.ht_batch_features(self.bt, self.g, self.psf, self.coeff, self.feats, self.spec)
 
     def _predict(self):
-        self.pred = self.net.forward(self.feats)
+        if not hasattr(self, "pred"):
+            self.pred = self.torch.empty(self.batch, dtype=self.torch.float32, device="cuda")
+        self.net.predict(self.feats, self.pred)
 
     def _certified(self):
         self.ht.ht_batch_restore_learned(self.bt, self.coeff, self.psf, "D2", self.mus, self.pred,
@@ -457,7 +478,8 @@ class Learned1D:
     def config(self):
         return {"workload": self.name, "batch": self.batch, "n": "U{256..4096}", "sum_n": int(self.rb.n.sum()),
                 "degree": "U{1,2,3}", "norm": "D2", "K": self.K, "grid": "1e-8..10", "graph": self.graph,
-                "path": self.path, "certificate_half_width": self.learned.CERT_HALF, "training": self.train_info}
+                "path": self.path, "certificate_half_width": self.learned.CERT_HALF, "training": self.train_info,
+                "schedule": self.tuning}
 
     def work(self):
         """Algorithmic bytes of each stage: 16 bytes per sample (one float64 read of the
@@ -906,7 +928,8 @@ def main():
     if args.workload == "learned":
         # host data before anything touches the GPU (the generator forks workers)
         pre = Learned1D(None, None, synth, args.batch or 65536, train=args.train, epochs=args.epochs,
-                        graph=not args.no_graph, workers=min(16, os.cpu_count() or 1), path=args.learned_path)
+                        graph=not args.no_graph, workers=min(16, os.cpu_count() or 1), path=args.learned_path,
+                        autotune=not args.no_autotune)
 
     import torch
     from paper_0906_2704_amd import ht

@@ -473,6 +473,12 @@ ht_status ht_mlp_fit_standardisation(ht_mlp* mlp, const float* features, int64_t
 ht_status ht_mlp_forward(ht_mlp* mlp, const float* features, int64_t rows, float* pred,
                          hipStream_t stream);
 
+/* ht_mlp_predict -- pred[r] (device float32 [rows], required) = the network at features[r]
+ * as ht_mlp_forward computes it, for any rows >= 0 (chunks of max_rows); keeps no
+ * activations for a backward pass (ht_mlp_backward is refused until the next
+ * ht_mlp_forward), so it writes only what the next layer reads.                         */
+ht_status ht_mlp_predict(ht_mlp* mlp, const float* features, int64_t rows, float* pred, hipStream_t stream);
+
 /* ht_mlp_backward -- gradients of the mean squared error mean_r (pred_r - target_r)^2 of
  * the last ht_mlp_forward (same rows) with respect to every parameter, kept in the
  * network (read with ht_mlp_get); the pre-activation gradients are rounded to bfloat16

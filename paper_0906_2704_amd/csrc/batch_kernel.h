@@ -182,6 +182,223 @@ __device__ __forceinline__ void mlp_layer(const float* in, int K, const uint16_t
     __syncthreads();
 }
 
+// ---- Half-length real cores (the algebra is in make_half, ht_plan.hip).  They run on an
+// LDS FFT of 2^LOGP points (no split); the input comes through x(j) (core index j < N),
+// which may read LDS; the result goes to the caller's slots; LDS is free on return.
+
+// Chirp-z DFT of length H on slot values: v[k] holds the input of j = tid + k BLOCK < H and
+// receives post_j * (b * (pre x))_j.
+template <int LOGP, int SL>
+__device__ __forceinline__ void chirp_slots(double2 (&v)[SL], const Chirp& ch, int H, double2* lds,
+                                            const double2* __restrict__ tw) {
+    constexpr int BLOCK = (1 << LOGP) / SL;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int j = tid + k * BLOCK;
+        v[k] = j < H ? cmul(v[k], tload(ch.pre, j)) : make_double2(0.0, 0.0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    fft_slots<LOGP, -1, SL>(v, lds, tw);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < SL; ++k) v[k] = cmul(v[k], tload(ch.B, static_cast<unsigned>(tid + k * BLOCK)));
+    __builtin_amdgcn_sched_barrier(0);
+    fft_slots<LOGP, 1, SL>(v, lds, tw);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int j = tid + k * BLOCK;
+        if (j < H) v[k] = cmul(v[k], tload(ch.post, j));
+    }
+}
+
+// Split a complex DFT Z of length H of z_m = y_{2m} + i y_{2m+1} (held in LDS) into the
+// two real-input halves at index k: E_k = (Z_k + conj Z_{H-k}) / 2 and
+// O_k = (Z_k - conj Z_{H-k}) / (2i) (indices mod H).
+__device__ __forceinline__ void split_real(const double2* Z, int H, int k, double2& E, double2& O) {
+    const double2 a = Z[k == H ? 0 : k], b = Z[k == 0 ? 0 : H - k];
+    E = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    O = make_double2(0.5 * (a.y + b.y), -0.5 * (a.x - b.x));
+}
+
+// DCT-II analysis of the cosine core (N = 2H): X_j = w_j sum_i x_i cos(pi j (2i+1) / (2N)).
+template <int LOGP, int SL, class X>
+__device__ __forceinline__ void half_dct2(double (&out)[SL], const Axis& ax, double2* lds,
+                                          const double2* __restrict__ tw, X x) {
+    constexpr int BLOCK = (1 << LOGP) / SL;
+    const int tid = threadIdx.x, N = ax.N, H = ax.H;
+    auto vsrc = [&](int p) { return p < H ? 2 * p : 2 * N - 2 * p - 1; };  // Makhoul order
+    double2 v[SL];
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int m = tid + k * BLOCK;
+        v[k] = m < H ? make_double2(x(vsrc(2 * m)), x(vsrc(2 * m + 1))) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    chirp_slots<LOGP, SL>(v, ax.ana, H, lds, tw);
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int m = tid + k * BLOCK;
+        if (m < H) lds[m] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int j = tid + k * BLOCK;
+        if (j < N) {
+            const int kk = j <= H ? j : N - j;
+            double2 E, O;
+            split_real(lds, H, kk, E, O);
+            const double2 V = cadd(E, cmul(tload(ax.htw, kk), O));        // V_kk = E + e^{-2 pi i kk/N} O
+            const double2 W = cmul(tload(ax.htw, H + 1 + kk), V);         // e^{-i pi kk/(2N)} V_kk
+            const double w = j == 0 ? ax.hw[0] : ax.hw[1];
+            out[k] = j <= H ? w * W.x : -w * W.y;
+        }
+    }
+    __syncthreads();
+}
+
+// DCT-III synthesis of the cosine core: u_i = sum_j w_j y_j cos(pi j (2i+1) / (2N)).
+template <int LOGP, int SL, class Y>
+__device__ __forceinline__ void half_dct3(double (&out)[SL], const Axis& ax, double2* lds,
+                                          const double2* __restrict__ tw, Y y) {
+    constexpr int BLOCK = (1 << LOGP) / SL;
+    const int tid = threadIdx.x, N = ax.N, H = ax.H;
+    auto wy = [&](int j) { return j < N ? (j == 0 ? ax.hw[0] : ax.hw[1]) * y(j) : 0.0; };
+    // V_k = e^{i pi k/(2N)} (Y_k - i Y_{N-k}) for 0 < k <= H, and V_0 = 2 Y_0 (the k = 0
+    // term has no mirror partner in v_p = sum_k V_k e^{2 pi i kp/N} / 2)
+    auto Vof = [&](int k) {
+        return k == 0 ? make_double2(2.0 * wy(0), 0.0)
+                      : cmulc(make_double2(wy(k), -wy(N - k)), tload(ax.htw, H + 1 + k));
+    };
+    double2 v[SL];
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int m = tid + k * BLOCK;
+        if (m < H) {
+            const double2 a = Vof(m), b = Vof(H - m);
+            // U_m = ((V_m + conj V_{H-m}) + i e^{2 pi i m/N} (V_m - conj V_{H-m})) / 2
+            const double2 T = cmulc(make_double2(a.x - b.x, a.y + b.y), tload(ax.htw, m));
+            v[k] = make_double2(0.5 * (a.x + b.x - T.y), 0.5 * (a.y - b.y + T.x));
+        } else {
+            v[k] = make_double2(0.0, 0.0);
+        }
+    }
+    __syncthreads();
+    chirp_slots<LOGP, SL>(v, ax.syn, H, lds, tw);
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int m = tid + k * BLOCK;
+        if (m < H) lds[m] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int j = tid + k * BLOCK;
+        if (j < N) {
+            const int p = (j & 1) ? N - 1 - (j >> 1) : (j >> 1);  // Makhoul position of u_j
+            const double2 um = lds[p >> 1];
+            out[k] = (p & 1) ? um.y : um.x;
+        }
+    }
+    __syncthreads();
+}
+
+// Sine core (L = N + 1 = 2H), both directions: out_j = sqrt(2/L) S_{j+1},
+// S_s = sum_t x_t sin(pi s t / L) (1-based, x_t = x(t - 1)).  wsum: 16 doubles of LDS.
+template <int LOGP, int SL, class X>
+__device__ __forceinline__ void half_dst(double (&out)[SL], const Axis& ax, double2* lds,
+                                         const double2* __restrict__ tw, X x, double* wsum) {
+    constexpr int BLOCK = (1 << LOGP) / SL;
+    const int tid = threadIdx.x, N = ax.N, H = ax.H, L = 2 * H;
+    auto xs = [&](int t) { return t >= 1 && t <= N ? x(t - 1) : 0.0; };
+    auto ys = [&](int t) {  // y_t = sin(pi t/L) (x_t + x_{L-t}) + (x_t - x_{L-t}) / 2
+        const double sn = tload(ax.htw, H + 1 + (t <= H ? t : L - t)).x;
+        const double a = xs(t), b = xs(L - t);
+        return fma(sn, a + b, 0.5 * (a - b));
+    };
+    double2 v[SL];
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int m = tid + k * BLOCK;
+        v[k] = m < H ? make_double2(ys(2 * m), ys(2 * m + 1)) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    chirp_slots<LOGP, SL>(v, ax.ana, H, lds, tw);
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int m = tid + k * BLOCK;
+        if (m < H) lds[m] = v[k];
+    }
+    __syncthreads();
+    // real DFT Y_k = E_k + e^{2 pi i k/L} O_k: R_k = Re Y_k (R_0 halved), I_k = Im Y_k
+    double rr[SL], ii[SL];
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int kk = tid + k * BLOCK;
+        rr[k] = ii[k] = 0.0;
+        if (kk < H) {
+            double2 E, O;
+            split_real(lds, H, kk, E, O);
+            const double2 Y = cadd(E, cmul(tload(ax.htw, kk), O));
+            rr[k] = kk == 0 ? 0.5 * Y.x : Y.x;
+            ii[k] = Y.y;
+        }
+    }
+    __syncthreads();
+    double* Rs = reinterpret_cast<double*>(lds);  // [H]: R, then its inclusive prefix sums
+    double* Is = Rs + H;                          // [H]
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int kk = tid + k * BLOCK;
+        if (kk < H) {
+            Rs[kk] = rr[k];
+            Is[kk] = ii[k];
+        }
+    }
+    __syncthreads();
+    // inclusive prefix sums of Rs: a contiguous chunk per thread (H <= P/2, so at most SL/2
+    // entries), the chunk totals scanned across each wave, then across the waves (fixed order)
+    {
+        constexpr int CMAX = SL / 2;
+        const int C = (H + BLOCK - 1) / BLOCK;
+        const int k0 = tid * C;
+        double loc[CMAX];
+        double run = 0.0;
+#pragma unroll
+        for (int e = 0; e < CMAX; ++e) {
+            if (e < C && k0 + e < H) run += Rs[k0 + e];
+            loc[e] = run;
+        }
+        const int lane = tid & 63, wv = tid >> 6;
+        double incl = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        double off = incl - run;
+        for (int w = 0; w < wv; ++w) off += wsum[w];
+#pragma unroll
+        for (int e = 0; e < CMAX; ++e)
+            if (e < C && k0 + e < H) Rs[k0 + e] = off + loc[e];
+        __syncthreads();
+    }
+    const double sc = ax.hw[0];
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int j = tid + k * BLOCK;
+        if (j < N) {
+            const int s = j + 1;
+            out[k] = sc * ((s & 1) ? Rs[s >> 1] : Is[s >> 1]);
+        }
+    }
+    __syncthreads();
+}
+
 // The 1024-, 2048- and 4096-point classes with 8 points per thread are held to 128
 // registers per lane (four waves per SIMD): two to eight workgroups then share a CU and
 // cover each other's barrier and memory waits, which pays for the spills this costs
@@ -206,6 +423,7 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
     __shared__ double2 bc[3];
     __shared__ int s_item, s_kbest;
     __shared__ float s_pred;
+    __shared__ double s_wsum[16];  // wave totals of the half sine core's prefix sums
     const int tid = threadIdx.x;
     double* scratch = a.scratch + static_cast<int64_t>(blockIdx.x) * MAX_N;
     // Classes of 4096 points and more take their next queue entry while the current signal
@@ -263,7 +481,18 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             };
             auto park = [&](int j, double y) { f[j + 1] = y; };
             auto unpark = [&](int j) { return f[j + 1]; };
-            chirp_core<LOGP, S, SL>(c, ax.ana, ax.ana.mode, N, lds, tw, in_inv, park, unpark);
+            bool done = false;
+            if constexpr (S == 1) {
+                if (ax.half) {  // uniform per signal
+                    auto xr = [&](int j) { return g[j + 1] - ax.q[j + 1] * x1 - ax.q[N - j] * xn; };
+                    if (kind == HT_KIND_C)
+                        half_dct2<LOGP, SL>(c, ax, lds, tw, xr);
+                    else
+                        half_dst<LOGP, SL>(c, ax, lds, tw, xr, s_wsum);
+                    done = true;
+                }
+            }
+            if (!done) chirp_core<LOGP, S, SL>(c, ax.ana, ax.ana.mode, N, lds, tw, in_inv, park, unpark);
         }
         if (rank > 0) {  // DST family correction x_mid -= U (E^T K)^{-1} E^T x_mid
             if (tid < rank) bc[tid].x = c[0];
@@ -677,7 +906,25 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             auto park = [&](int j, double y) { f[j + 1] = y; };
             auto unpark = [&](int j) { return f[j + 1]; };
             double u[SL];
-            chirp_core<LOGP, S, SL>(u, ax.syn, ax.syn.mode, N, lds, tw, in_fwd, park, unpark);
+            bool done = false;
+            if constexpr (S == 1) {
+                if (ax.half) {  // uniform per signal; the coefficients go through LDS
+                    double* ys = reinterpret_cast<double*>(lds);
+#pragma unroll
+                    for (int k = 0; k < SL; ++k) {
+                        const int j = tid + k * BLOCK;
+                        if (j < N) ys[j] = j >= rank ? c[k] : 0.0;
+                    }
+                    __syncthreads();
+                    auto yr = [&](int j) { return ys[j]; };
+                    if (kind == HT_KIND_C)
+                        half_dct3<LOGP, SL>(u, ax, lds, tw, yr);
+                    else
+                        half_dst<LOGP, SL>(u, ax, lds, tw, yr, s_wsum);
+                    done = true;
+                }
+            }
+            if (!done) chirp_core<LOGP, S, SL>(u, ax.syn, ax.syn.mode, N, lds, tw, in_fwd, park, unpark);
 #pragma unroll
             for (int k = 0; k < SL; ++k) {
                 const int j = tid + k * BLOCK;

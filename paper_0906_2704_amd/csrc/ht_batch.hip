@@ -128,7 +128,7 @@ extern "C" ht_status ht_batch_create(int64_t count, const int64_t* n, const int*
         std::vector<std::thread> pool;
         for (int t = 0; t < nthr; ++t)
             pool.emplace_back([&]() {
-                for (int64_t a = next++; a < nax; a = next++) status[a] = build_axis(keys[a].first, keys[a].second, hs[a]);
+                for (int64_t a = next++; a < nax; a = next++) status[a] = build_axis(keys[a].first, keys[a].second, hs[a], true);
             });
         for (auto& th : pool) th.join();
     }

@@ -64,6 +64,15 @@ struct Axis {
     const double2* f3v;   // [n]
     const double* f3b;    // [2][n]: cosine column, cubic column (all n rows)
     double2 f3vi[4];      // Vi, row-major
+    // Half-length real cores (ragged batches, real kinds with an even real-DFT length:
+    // N for the cosine core, N + 1 for the sine core): the core is a real DFT of that
+    // length, computed as a complex DFT of H = half of it by the chirp-z tables in ana
+    // (analysis) / syn (synthesis), with pre- and post-processing on htw.  0 otherwise.
+    int half;
+    int H;
+    double hw[2];         // cosine core: sqrt(1/N), sqrt(2/N); sine core: sqrt(2/(N+1)), 0
+    const double2* htw;   // [2][H + 1]: cosine core e^{-2 pi i k/N}, e^{-i pi k/(2N)};
+                          //             sine core e^{2 pi i k/(N+1)}, (sin(pi k/(N+1)), 0)
 };
 
 // Strided view of a batch of 1D signals: signal b lives at

@@ -138,19 +138,21 @@ struct ht_mlp {
 
 namespace {
 
-ht_status mlp_forward_rows(ht_mlp* m, const float* X, int64_t B, float* pred, hipStream_t st) {
+// keep: write the pre-activations and the float32 last hidden layer that the backward pass
+// reads (training); inference writes only the bfloat16 activations the next layer reads
+ht_status mlp_forward_rows(ht_mlp* m, const float* X, int64_t B, float* pred, hipStream_t st, bool keep = true) {
     const MlpLayout& L = LAYOUT;
     const int H = MLP_H;
     ht_status s = ht_to_bf16(X, m->Xb, B, MLP_IN, m->mean, m->stdv, st);
     if (s) return s;
     s = ht_gemm_bf16(static_cast<int>(B), H, MLP_IN, m->Xb, MLP_IN, 1, m->Pb + L.w[0], H, 1, m->P + L.b[0], 1,
-                     m->Z[0], nullptr, H, m->Hb[0], st);
+                     keep ? m->Z[0] : nullptr, nullptr, H, m->Hb[0], st);
     if (s) return s;
-    s = ht_gemm_bf16(static_cast<int>(B), H, H, m->Hb[0], H, 1, m->Pb + L.w[1], H, 1, m->P + L.b[1], 1, m->Z[1],
-                     nullptr, H, m->Hb[1], st);
+    s = ht_gemm_bf16(static_cast<int>(B), H, H, m->Hb[0], H, 1, m->Pb + L.w[1], H, 1, m->P + L.b[1], 1,
+                     keep ? m->Z[1] : nullptr, nullptr, H, m->Hb[1], st);
     if (s) return s;
-    s = ht_gemm_bf16(static_cast<int>(B), H, H, m->Hb[1], H, 1, m->Pb + L.w[2], H, 1, m->P + L.b[2], 1, m->Z[2],
-                     m->H3, H, m->Hb[2], st);
+    s = ht_gemm_bf16(static_cast<int>(B), H, H, m->Hb[1], H, 1, m->Pb + L.w[2], H, 1, m->P + L.b[2], 1,
+                     keep ? m->Z[2] : nullptr, keep ? m->H3 : nullptr, H, m->Hb[2], st);
     if (s) return s;
     return ht_gemm_bf16(static_cast<int>(B), 1, H, m->Hb[2], H, 1, m->Pb + L.w[3], 1, 1, m->P + L.b[3], 0, nullptr,
                         pred, 1, nullptr, st);
@@ -341,6 +343,17 @@ extern "C" ht_status ht_mlp_forward(ht_mlp* m, const float* features, int64_t ro
     return check_hip(hipMemcpyAsync(pred, m->y, rows * 4, hipMemcpyDeviceToDevice, st), "ht_mlp_forward: copy");
 }
 
+extern "C" ht_status ht_mlp_predict(ht_mlp* m, const float* features, int64_t rows, float* pred, hipStream_t st) {
+    if (!m || !features || !pred || rows < 0) return fail(HT_ERR_INVALID_ARG, "ht_mlp_predict: bad argument");
+    m->fwd_rows = 0;  // the activations left behind are not those of an ht_mlp_forward
+    for (int64_t r0 = 0; r0 < rows; r0 += m->max_rows) {
+        const int64_t r = rows - r0 < m->max_rows ? rows - r0 : m->max_rows;
+        ht_status s = mlp_forward_rows(m, features + r0 * MLP_IN, r, pred + r0, st, false);
+        if (s) return s;
+    }
+    return HT_OK;
+}
+
 extern "C" ht_status ht_mlp_backward(ht_mlp* m, const float* target, int64_t rows, float* loss, hipStream_t st) {
     ht_status s = check_rows(m, rows, "ht_mlp_backward");
     if (s) return s;
@@ -393,10 +406,5 @@ extern "C" ht_status ht_lambda_predict(const ht_batch* bt, ht_mlp* m, const doub
     const int64_t count = ht_batch_count(bt);
     ht_status s = ht_batch_features(bt, signal, psf, coeff, features, spectrum, st);
     if (s) return s;
-    m->fwd_rows = 0;  // the activations left behind are not those of an ht_mlp_forward
-    for (int64_t r0 = 0; r0 < count; r0 += m->max_rows) {
-        const int64_t rows = count - r0 < m->max_rows ? count - r0 : m->max_rows;
-        if ((s = mlp_forward_rows(m, features + r0 * MLP_IN, rows, pred + r0, st))) return s;
-    }
-    return HT_OK;
+    return ht_mlp_predict(m, features, count, pred, st);
 }

@@ -1,9 +1,11 @@
 // Kernels of the learned-mu predictor: a small MLP trained and evaluated on the GPU.
 //
 //   GEMM      C = act(A B + bias) with A, B in bfloat16 and float32 accumulation on the
-//             matrix cores (v_mfma_f32_16x16x16bf16_1k): 64 x 64 blocks of four waves with
-//             the contraction staged through LDS; A and B addressed through strides so that
-//             transposed operands need no copy
+//             matrix cores: 64 x 64 blocks of four waves with the contraction staged
+//             through LDS; unit-stride operands as 16-byte vectors on
+//             v_mfma_f32_16x16x32_bf16, strided ones (the transposed operands of the
+//             backward pass, which need no copy) element by element on
+//             v_mfma_f32_16x16x16bf16_1k
 //   GELU      exact, 0.5 x (1 + erf(x / sqrt 2)); derivative Phi(x) + x phi(x)
 //   reductions column sums (bias gradients) in a fixed order: deterministic
 //   Adam      float32 master weights and moments, bfloat16 copies for the GEMMs
@@ -91,6 +93,81 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
             for (int t = 0; t < 4; ++t) {
                 const bf16x4 b = *reinterpret_cast<const bf16x4*>(&sB[16 * t + r][kk + 4 * q]);
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t cj = col0 + 16 * t + r;
+        if (cj >= g.N) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t ci = row0 + 16 * w + 4 * q + i;
+            if (ci >= g.M) continue;
+            float z = acc[t][i] + (g.bias ? g.bias[cj] : 0.0f);
+            if (g.Z) g.Z[ci * g.ldc + cj] = z;
+            const float y = g.act ? gelu(z) : z;
+            const uint16_t yb = f32_to_bf16(y);
+            if (g.C) g.C[ci * g.ldc + cj] = g.Cb ? bf16_to_f32(yb) : y;
+            if (g.Cb) g.Cb[ci * g.ldc + cj] = yb;
+        }
+    }
+}
+
+// Unit-stride operands (A row-major [M][K], B row-major [K][N], K and N multiples of 8,
+// 16-byte aligned rows): the same 64 x 64 block per workgroup of four waves, but the
+// operands arrive as 16-byte vectors (eight bfloat16) and the contraction runs in steps of
+// 32 on v_mfma_f32_16x16x32_bf16.  A is staged as [row][k]; B is transposed into [col][k]
+// as it is staged.  Rows of 72 elements (144 bytes) keep the 16-byte fragment reads of
+// the 16 rows of a lane group in distinct banks.  Lane l supplies A row l % 16 and B
+// column l % 16 with k = 8 (l / 16) + 0..7, and receives D rows 4 (l / 16) + 0..3 of
+// column l % 16.
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
+constexpr int VKC = 64, VPAD = VKC + 8;
+
+__global__ __launch_bounds__(256) void k_gemm_vec(Gemm g) {
+    __shared__ __attribute__((aligned(16))) uint16_t sA[GB][VPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[GB][VPAD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nbj = (g.N + GB - 1) / GB;
+    const int bi = blockIdx.x / nbj, bj = blockIdx.x - bi * nbj;
+    const int64_t row0 = static_cast<int64_t>(bi) * GB, col0 = static_cast<int64_t>(bj) * GB;
+    const int r = lane & 15, q = lane >> 4;
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < g.K; k0 += VKC) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int v = tid + 256 * u;
+            const int ar = v >> 3, seg = (v & 7) * 8;
+            const int64_t gi = row0 + ar;
+            const int gk = k0 + seg;
+            u32x4v va = u32x4v{0u, 0u, 0u, 0u};
+            if (gi < g.M && gk < g.K) va = *reinterpret_cast<const u32x4v*>(g.A + gi * g.sa_i + gk);
+            *reinterpret_cast<u32x4v*>(&sA[ar][seg]) = va;
+            const int bk = v >> 3;
+            const int64_t gj = col0 + seg;
+            const int gk2 = k0 + bk;
+            u32x4v vb = u32x4v{0u, 0u, 0u, 0u};
+            if (gj < g.N && gk2 < g.K) vb = *reinterpret_cast<const u32x4v*>(g.B + gk2 * g.sb_k + gj);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                sB[seg + 2 * i][bk] = static_cast<uint16_t>(vb[i] & 0xffffu);
+                sB[seg + 2 * i + 1][bk] = static_cast<uint16_t>(vb[i] >> 16);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < VKC; kk += 32) {
+            const u32x4v a = *reinterpret_cast<const u32x4v*>(&sA[16 * w + r][kk + 8 * q]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const u32x4v b = *reinterpret_cast<const u32x4v*>(&sB[16 * t + r][kk + 8 * q]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8v, a),
+                                                                 __builtin_bit_cast(bf16x8v, b), acc[t], 0, 0, 0);
             }
         }
         __syncthreads();
@@ -215,7 +292,12 @@ extern "C" ht_status ht_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_
     const int64_t blocks = static_cast<int64_t>((M + GB - 1) / GB) * ((N + GB - 1) / GB);
     if (blocks > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_gemm_bf16: too large");
     Gemm g{M, N, K, A, sa_i, sa_k, B, sb_k, sb_j, bias, act, Z, C, ldc, Cb};
-    hipLaunchKernelGGL(k_gemm, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, g);
+    const bool vec = sa_k == 1 && sb_j == 1 && K % 8 == 0 && N % 8 == 0 && sa_i % 8 == 0 && sb_k % 8 == 0 &&
+                     (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+    if (vec)
+        hipLaunchKernelGGL(k_gemm_vec, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, g);
+    else
+        hipLaunchKernelGGL(k_gemm, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, g);
     return check_hip(hipGetLastError(), "ht_gemm_bf16 launch");
 }
 

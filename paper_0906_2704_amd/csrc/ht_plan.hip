@@ -165,6 +165,69 @@ static void make_chirp(int kind, bool synthesis, int N, int M, HostChirp& hc) {
     hc.B.swap(bc);
 }
 
+// Chirp-z tables of the plain complex DFT of length H, Y_k = sum_j x_j e^{sign 2 pi i jk/H}
+// (unscaled), on an FFT of length M >= 2H - 1: pre_j = e^{sign i pi j^2/H}, post_k likewise,
+// b_m = e^{-sign i pi m^2/H}.
+static void make_dft_chirp(int H, int sign, int M, HostChirp& hc) {
+    hc.pre.assign(H, cd());
+    hc.post.assign(H, cd());
+    std::vector<cd> bc(M, cd());
+    for (int64_t m = 0; m < H; ++m) {
+        hc.pre[m] = cis_exact(sign * m * m, 2LL * H);
+        hc.post[m] = hc.pre[m];
+        const cd b = cis_exact(-sign * m * m, 2LL * H);
+        bc[m] = b;
+        if (m > 0) bc[M - m] = b;
+    }
+    host_fft(bc, -1);
+    const double inv = 1.0 / M;
+    for (auto& v : bc) v *= inv;
+    hc.B.swap(bc);
+    hc.mode = MODE_CPLX;
+}
+
+// Half-length real cores.  The cosine core (N even, H = N/2): Makhoul's reordering
+// v_p = x_{2p}, v_{N-1-p} = x_{2p+1} turns the DCT-II into X_k = Re(e^{-i pi k/(2N)} V_k)
+// with V the real DFT of v, a complex DFT of length H of u_m = v_{2m} + i v_{2m+1};
+// the DCT-III is the same steps reversed.  The sine core (N + 1 = L even, H = L/2): with
+// y_t = sin(pi t/L)(x_t + x_{L-t}) + (x_t - x_{L-t})/2 (x_0 = x_L = 0) and Y its real DFT
+// (e^{+}), the sine transform is S_{2k} = Im Y_k and S_{2k+1} = S_{2k-1} + Re Y_k
+// (S_1 = Re Y_0 / 2); Y again from a complex DFT of length H.  The FFT length becomes the
+// smallest power of two >= N + 2 (>= 2H - 1, and room in LDS for the eigenvalue staging)
+// instead of >= 2N - 1.
+static ht_status make_half(HostAxis& h) {
+    Axis& a = h.ax;
+    const int N = a.N;
+    const bool cosine = a.kind == HT_KIND_C;
+    const int L = cosine ? N : N + 1;
+    if (L % 2 != 0 || L < 4) return HT_OK;  // odd length: the full chirp-z core
+    const int H = L / 2;
+    int M = 512;
+    while (M < N + 2) M <<= 1;
+    if (M >= h.M) return HT_OK;  // no gain
+    a.half = 1;
+    a.H = H;
+    a.hw[0] = static_cast<double>(cosine ? sqrtl(1.0L / N) : sqrtl(2.0L / L));
+    a.hw[1] = static_cast<double>(cosine ? sqrtl(2.0L / N) : 0.0L);
+    h.M = M;
+    a.S = 1;
+    a.logP = 0;
+    while ((1 << a.logP) < M) ++a.logP;
+    make_dft_chirp(H, cosine ? -1 : 1, M, h.ana);
+    make_dft_chirp(H, 1, M, h.syn);
+    h.htw.assign(2 * static_cast<size_t>(H + 1), cd());
+    for (int k = 0; k <= H; ++k) {
+        if (cosine) {
+            h.htw[k] = cis_exact(-k, N);
+            h.htw[H + 1 + k] = cis_exact(-k, 4LL * N);
+        } else {
+            h.htw[k] = cis_exact(k, L);
+            h.htw[H + 1 + k] = cd(cis_exact(k, 2LL * L).imag(), 0.0);
+        }
+    }
+    return HT_OK;
+}
+
 // Host replica of the chirp-z core (used at plan creation only): the core transform of a
 // real vector, as the device core returns it (real part, imaginary part for the sine
 // core, or the complex value for the DFT analysis).
@@ -277,7 +340,7 @@ static ht_status build_comparator_axis(int n, int kind, HostAxis& h) {
 
 static ht_status build_f3_tables(HostAxis& h);
 
-ht_status build_axis(int n, int kind_in, HostAxis& h) {
+ht_status build_axis(int n, int kind_in, HostAxis& h, bool half_cores) {
     if (kind_in == HT_KIND_P || kind_in == HT_KIND_R) return build_comparator_axis(n, kind_in, h);
     // F3 is T_F plus a rank-2 modification: every T_F table, then its own
     const int kind = kind_in == HT_KIND_F3 ? HT_KIND_F : kind_in;
@@ -381,6 +444,9 @@ ht_status build_axis(int n, int kind_in, HostAxis& h) {
         a.kind = HT_KIND_F3;
         return build_f3_tables(h);
     }
+    // the DST correction above used the full core (host_core); only then the half tables
+    if (half_cores && (kind == HT_KIND_C || kind == HT_KIND_AR || kind == HT_KIND_DST2 || kind == HT_KIND_DST3))
+        return make_half(h);
     return HT_OK;
 }
 
@@ -526,24 +592,26 @@ ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* a
         bytes += (nbytes + 255) & ~static_cast<size_t>(255);
         return off;
     };
-    struct Offs { size_t q, bub, U, tcos, tsin, apre, apost, aB, spre, spost, sB, f3v, f3b; };
+    struct Offs { size_t q, bub, U, tcos, tsin, apre, apost, aB, spre, spost, sB, f3v, f3b, htw; };
     std::vector<Offs> o(nax);
     for (int64_t a = 0; a < nax; ++a) {
         const HostAxis& h = hs[a];
         const size_t N = h.ax.N;
         o[a].f3v = reserve(sizeof(double2) * (h.f3v.size() + 1));
         o[a].f3b = reserve(sizeof(double) * (h.f3b.size() + 1));
+        o[a].htw = reserve(sizeof(double2) * (h.htw.size() + 1));
         o[a].q = reserve(sizeof(double) * h.q.size());
         o[a].bub = reserve(sizeof(double) * (h.bub.size() + 1));
         o[a].U = reserve(sizeof(double) * (h.U.size() + 1));
         o[a].tcos = reserve(sizeof(double) * h.tcos.size());
         o[a].tsin = reserve(sizeof(double) * h.tsin.size());
-        o[a].apre = reserve(sizeof(double2) * N);
-        o[a].apost = reserve(sizeof(double2) * N);
+        o[a].apre = reserve(sizeof(double2) * h.ana.pre.size());
+        o[a].apost = reserve(sizeof(double2) * h.ana.post.size());
         o[a].aB = reserve(sizeof(double2) * h.M);
-        o[a].spre = reserve(sizeof(double2) * N);
-        o[a].spost = reserve(sizeof(double2) * N);
+        o[a].spre = reserve(sizeof(double2) * h.syn.pre.size());
+        o[a].spost = reserve(sizeof(double2) * h.syn.post.size());
         o[a].sB = reserve(sizeof(double2) * h.M);
+        (void)N;
     }
     std::vector<char> host;
     try {
@@ -572,6 +640,7 @@ ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* a
         const HostAxis& h = hs[a];
         put(o[a].q, h.q.data(), sizeof(double) * h.q.size());
         putc(o[a].f3v, h.f3v);
+        putc(o[a].htw, h.htw);
         put(o[a].f3b, h.f3b.data(), sizeof(double) * h.f3b.size());
         put(o[a].bub, h.bub.data(), sizeof(double) * h.bub.size());
         put(o[a].U, h.U.data(), sizeof(double) * h.U.size());
@@ -596,6 +665,7 @@ ht_status upload_axes(const HostAxis* hs, int64_t nax, void** arena_out, Axis* a
         ax.q = reinterpret_cast<const double*>(dev + o[a].q);
         ax.f3v = reinterpret_cast<const double2*>(dev + o[a].f3v);
         ax.f3b = reinterpret_cast<const double*>(dev + o[a].f3b);
+        ax.htw = reinterpret_cast<const double2*>(dev + o[a].htw);
         ax.bub = reinterpret_cast<const double*>(dev + o[a].bub);
         ax.U = reinterpret_cast<const double*>(dev + o[a].U);
         ax.tcos = reinterpret_cast<const double*>(dev + o[a].tcos);

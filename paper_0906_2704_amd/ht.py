@@ -405,6 +405,7 @@ def _learned_sigs(L):
     L.ht_mlp_fit_standardisation.argtypes = [VP, VP, I64, VP]
     L.ht_mlp_forward.argtypes = [VP, VP, I64, VP, VP]
     L.ht_mlp_backward.argtypes = [VP, VP, I64, VP, VP]
+    L.ht_mlp_predict.argtypes = [VP, VP, I64, VP, VP]
     L.ht_mlp_adam_step.argtypes = [VP, F, VP]
     L.ht_mlp_train_step.argtypes = [VP, VP, VP, VP, I64, F, VP, VP]
     L.ht_mlp_weights_of.argtypes = [VP, ctypes.POINTER(MlpWeights)]
@@ -415,7 +416,7 @@ def _learned_sigs(L):
     for name in ("ht_batch_features", "ht_batch_restore_learned", "ht_batch_restore_fused", "ht_gemm_bf16", "ht_to_bf16", "ht_from_bf16",
                  "ht_gelu_backward", "ht_colsum", "ht_mse_grad", "ht_outer", "ht_adam", "ht_mlp_create",
                  "ht_mlp_destroy", "ht_mlp_set_params", "ht_mlp_get", "ht_mlp_set_state", "ht_mlp_fit_standardisation",
-                 "ht_mlp_forward", "ht_mlp_backward", "ht_mlp_adam_step", "ht_mlp_train_step", "ht_mlp_weights_of",
+                 "ht_mlp_forward", "ht_mlp_predict", "ht_mlp_backward", "ht_mlp_adam_step", "ht_mlp_train_step", "ht_mlp_weights_of",
                  "ht_log10_labels", "ht_lambda_predict"):
         getattr(L, name).restype = ctypes.c_int
 
@@ -621,6 +622,14 @@ def ht_mlp_forward(mlp, features, pred=None):
     rows = int(features.shape[0])
     _check(_llib().ht_mlp_forward(mlp.handle, _p(features, "features", torch.float32), rows,
                                   _p(pred, "pred", torch.float32), _stream()), "ht_mlp_forward")
+    return pred
+
+
+def ht_mlp_predict(mlp, features, pred=None):
+    rows = int(features.shape[0])
+    pred = torch.empty(rows, dtype=torch.float32, device=features.device) if pred is None else pred
+    _check(_llib().ht_mlp_predict(mlp.handle, _p(features, "features", torch.float32), rows,
+                                  _p(pred, "pred", torch.float32), _stream()), "ht_mlp_predict")
     return pred
 
 

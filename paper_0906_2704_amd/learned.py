@@ -77,6 +77,11 @@ class Net:
         ht.ht_mlp_forward(self.mlp, X, self.y[:B])
         return self.y[:B]
 
+    def predict(self, X, out=None):
+        """Inference only (ht_mlp_predict): predictions for any number of rows, no
+        activations kept for a backward pass."""
+        return ht.ht_mlp_predict(self.mlp, X, out)
+
     def backward(self, t, loss=None):
         """Gradients of mean((y - t)^2) for the last forward pass (kept in the library)."""
         ht.ht_mlp_backward(self.mlp, t, loss)

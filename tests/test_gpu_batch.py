@@ -80,10 +80,43 @@ def test_ragged_small_classes(ht, norm):
     check_items(items, bt, f, G, kb, mb, norm)
 
 
+def fft_class(n, kind):
+    """Size class of a signal: the FFT length is the smallest power of two >= 2N - 1 for the
+    chirp-z core, or >= N + 2 for the half-length real core when the core's real DFT length
+    (N for the cosine core, N + 1 for the sine core) is even and that is shorter."""
+    N = n - 2
+    pow2 = lambda v: 1 << max(9, int(np.ceil(np.log2(v))))
+    M = pow2(2 * N - 1)
+    L = N if kind == "C" else N + 1
+    if L % 2 == 0 and L >= 4:
+        M = min(M, pow2(N + 2))
+    return 5 if M >= 16384 else int(np.log2(M)) - 9
+
+
 def test_ragged_large_classes(ht):
     items = make_items(LARGE, seed=3)
     bt, f, G, kb, mb = run_batch(ht, items, "D2")
-    assert [bt.class_count(c) for c in range(6)] == [0, 0, 0, 1, 3, 2]
+    want = np.bincount([fft_class(len(p.g), KIND_OF_DEGREE[p.degree]) for p in items], minlength=6)
+    assert [bt.class_count(c) for c in range(6)] == list(want)
+    check_items(items, bt, f, G, kb, mb, "D2")
+
+
+# half-length real cores in every size class: even n for the cosine core (T_C, N even),
+# odd n for the sine cores (antireflective, DST3: N + 1 even), up to the largest length
+HALF_N = {2: [130, 258, 600, 1200, 2500, 5000, 8190], 1: [131, 257, 601, 1201, 2501, 5001, 8191],
+          3: [131, 259, 603, 1203, 2503, 5003, 8189]}
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3])
+def test_ragged_half_cores_every_class(ht, degree):
+    ns = HALF_N[degree]
+    items = make_items(ns, seed=20 + degree, K=64)
+    for p, n in zip(items, ns):
+        assert len(p.g) == n
+        p.degree = degree
+    bt, f, G, kb, mb = run_batch(ht, items, "D2")
+    kind = KIND_OF_DEGREE[degree]
+    assert [bt.class_count(c) for c in range(6)] == list(np.bincount([fft_class(n, kind) for n in ns], minlength=6))
     check_items(items, bt, f, G, kb, mb, "D2")
 
 

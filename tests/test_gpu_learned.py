@@ -143,8 +143,10 @@ def test_features_and_certified_restore_match_oracle(ht):
 
 def test_features_every_size_class(ht):
     """Signals of every FFT size class, including the smallest (n = 256, 257: 64-thread
-    workgroups, fewer threads than features)."""
-    nv = [256, 257, 258, 511, 1000, 1030, 2000, 2050, 4096, 4000, 256, 300]
+    workgroups, fewer threads than features).  The lengths sit where the chirp-z core and
+    the half-length real core (whichever the kind and parity give) land in the same class:
+    N = 2^c - 1 or 2^c, so each class holds both core forms."""
+    nv = [256, 257, 513, 514, 1025, 1026, 2049, 2050, 4097, 4098, 300, 700]
     rb = synth.ragged_batch(len(nv), n_lo=256, n_hi=4096, config=4, first_item=900, sort_desc=False,
                             n_values=nv, grid=(-8.0, 1.0))
     bt = ht.Batch(rb.n, rb.degree, np.diff(rb.psf_offsets), rb.psf_center)
