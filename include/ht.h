@@ -388,7 +388,9 @@ ht_status ht_batch_restore_fused(const ht_batch* batch, const double* signal, co
 
 /* Network kernels (row-major matrices; bfloat16 stored as uint16_t bit patterns):
  * ht_gemm_bf16: C = act(A B + bias), A(i,k) = A[i sa_i + k sa_k], B(k,j) = B[k sb_k + j sb_j]
- *   (bfloat16), float32 accumulation on the matrix cores; act 0 = none, 1 = GELU
+ *   (bfloat16), float32 accumulation on the matrix cores (operands contiguous along the
+ *   contraction, or B contiguous along j, in 16-byte vectors when the strides and sizes
+ *   are multiples of 8); act 0 = none, 1 = GELU
  *   0.5 x (1 + erf(x / sqrt 2)); Z (pre-activation), C (activation; rounded to bfloat16
  *   when Cb is also given, so that C and Cb hold the same values) and Cb may each be NULL;
  *   all outputs use leading dimension ldc.
@@ -414,6 +416,9 @@ ht_status ht_mse_grad(const float* y, const float* t, float* dy, float* sq, int6
                       hipStream_t stream);
 ht_status ht_outer(const float* dy, const float* w, float* dh, int64_t rows, int cols,
                    hipStream_t stream);
+/* ht_transpose_bf16: dst[c][r] = src[r][c] for a [rows][cols] bfloat16 matrix (dst must not
+ * overlap src).                                                                       */
+ht_status ht_transpose_bf16(const uint16_t* src, uint16_t* dst, int rows, int cols, hipStream_t stream);
 ht_status ht_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr,
                   float beta1, float beta2, float eps, int64_t step, uint16_t* pb,
                   hipStream_t stream);

@@ -19,6 +19,13 @@
 namespace ht {
 
 constexpr int NCLASS = 6;          // (LOGP, S): (9,1) (10,1) (11,1) (12,1) (13,1) (13,2)
+// Each size class's queue is cut into one contiguous segment per XCD (the GPU hands
+// workgroup b to XCD b mod 8): a workgroup drains its own XCD's segment first, so signals of
+// equal length and kind, which sit next to each other in the longest-first order, run on
+// one XCD and share its L2 copy of their transform tables; then it takes work from the
+// other segments in turn.
+constexpr int NSEG = 8;
+static_assert(NCLASS * NSEG <= 64, "the counter reset kernel has 64 threads");
 constexpr int BATCH_MAX_K = 256;
 
 struct RSig {
@@ -56,6 +63,9 @@ struct RaggedArgs {
     const float* fmean;
     const float* fstd;
     float* pred_out;
+    // per class, NSEG contiguous segments of its longest-first queue ([NCLASS][NSEG + 1]
+    // offsets within the class); counters then hold one queue head per (class, segment)
+    const int* seg;
 };
 
 // What one pass of the fused kernel does with each signal.
@@ -64,12 +74,15 @@ enum BatchMode {
     MODE_FEATURES = 1,  // inverse, eigenvalues, band statistics; the coefficients go to f
     MODE_LEARNED = 2,   // coefficients from f, eigenvalues, GCV certificate around the
                         // predicted mu (full scan if it fails), filter, forward
-    MODE_FUSED = 3      // inverse, eigenvalues, features, the network's prediction, then as
+    MODE_FUSED = 3,     // inverse, eigenvalues, features, the network's prediction, then as
                         // MODE_LEARNED: one pass per signal
+    MODE_LEARNED_RC = 4 // MODE_LEARNED without the feature pass's spectrum: the eigenvalues
+                        // are recomputed from the PSF
 };
 constexpr int MLP_H = 256;  // hidden width of the network
 constexpr int NFEAT_G = 64, NFEAT_D = 8, NFEAT = NFEAT_G + NFEAT_D;
 constexpr double CERT_SLACK = 1.05;   // G(predicted) may exceed the bracket minimum by 5%
+constexpr float LOG10_2F = 0.30102999566398120f;
 
 inline int class_of(const Axis& a) { return a.S == 2 ? 5 : a.logP - MIN_LOGP; }
 
@@ -186,17 +199,17 @@ __device__ __forceinline__ void mlp_layer(const float* in, int K, const uint16_t
 // LDS FFT of 2^LOGP points (no split); the input comes through x(j) (core index j < N),
 // which may read LDS; the result goes to the caller's slots; LDS is free on return.
 
-// Chirp-z DFT of length H on slot values: v[k] holds the input of j = tid + k BLOCK < H and
-// receives post_j * (b * (pre x))_j.
+// Chirp-z DFT on slot values: v[k] holds the input of j = tid + k BLOCK < nin and receives
+// post_j * (b * (pre x))_j for j < nout (the tables fix the length and sign).
 template <int LOGP, int SL>
-__device__ __forceinline__ void chirp_slots(double2 (&v)[SL], const Chirp& ch, int H, double2* lds,
+__device__ __forceinline__ void chirp_slots(double2 (&v)[SL], const Chirp& ch, int nin, int nout, double2* lds,
                                             const double2* __restrict__ tw) {
     constexpr int BLOCK = (1 << LOGP) / SL;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;
-        v[k] = j < H ? cmul(v[k], tload(ch.pre, j)) : make_double2(0.0, 0.0);
+        v[k] = j < nin ? cmul(v[k], tload(ch.pre, j)) : make_double2(0.0, 0.0);
     }
     __builtin_amdgcn_sched_barrier(0);
     fft_slots<LOGP, -1, SL>(v, lds, tw);
@@ -209,7 +222,7 @@ __device__ __forceinline__ void chirp_slots(double2 (&v)[SL], const Chirp& ch, i
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;
-        if (j < H) v[k] = cmul(v[k], tload(ch.post, j));
+        if (j < nout) v[k] = cmul(v[k], tload(ch.post, j));
     }
 }
 
@@ -222,21 +235,48 @@ __device__ __forceinline__ void split_real(const double2* Z, int H, int k, doubl
     O = make_double2(0.5 * (a.y + b.y), -0.5 * (a.x - b.x));
 }
 
-// DCT-II analysis of the cosine core (N = 2H): X_j = w_j sum_i x_i cos(pi j (2i+1) / (2N)).
+// DCT-II analysis of the cosine core: X_j = w_j sum_i x_i cos(pi j (2i+1) / (2N)).
 template <int LOGP, int SL, class X>
 __device__ __forceinline__ void half_dct2(double (&out)[SL], const Axis& ax, double2* lds,
                                           const double2* __restrict__ tw, X x) {
     constexpr int BLOCK = (1 << LOGP) / SL;
     const int tid = threadIdx.x, N = ax.N, H = ax.H;
-    auto vsrc = [&](int p) { return p < H ? 2 * p : 2 * N - 2 * p - 1; };  // Makhoul order
+    auto vsrc = [&](int p) { return p < (N + 1) / 2 ? 2 * p : 2 * N - 2 * p - 1; };  // Makhoul order
     double2 v[SL];
+    if (ax.half == 2) {  // N odd: V_k (k < H = (N+1)/2) of the real v, by chirp-z of length N
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int p = tid + k * BLOCK;
+            v[k] = make_double2(p < N ? x(vsrc(p)) : 0.0, 0.0);
+        }
+        __syncthreads();
+        chirp_slots<LOGP, SL>(v, ax.ana, N, H, lds, tw);
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int m = tid + k * BLOCK;
+            if (m < H) lds[m] = v[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int j = tid + k * BLOCK;
+            if (j < N) {
+                const int kk = j < H ? j : N - j;                      // V_{N-j} = conj V_j
+                const double2 W = cmul(tload(ax.htw, kk), lds[kk]);   // e^{-i pi kk/(2N)} V_kk
+                const double w = j == 0 ? ax.hw[0] : ax.hw[1];
+                out[k] = j < H ? w * W.x : -w * W.y;
+            }
+        }
+        __syncthreads();
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int m = tid + k * BLOCK;
         v[k] = m < H ? make_double2(x(vsrc(2 * m)), x(vsrc(2 * m + 1))) : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    chirp_slots<LOGP, SL>(v, ax.ana, H, lds, tw);
+    chirp_slots<LOGP, SL>(v, ax.ana, H, H, lds, tw);
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int m = tid + k * BLOCK;
@@ -273,6 +313,33 @@ __device__ __forceinline__ void half_dct3(double (&out)[SL], const Axis& ax, dou
                       : cmulc(make_double2(wy(k), -wy(N - k)), tload(ax.htw, H + 1 + k));
     };
     double2 v[SL];
+    if (ax.half == 2) {
+        // N odd: u_p = Re sum_{k < H} U_k e^{2 pi i kp/N} with U_0 = w_0 y_0 and
+        // U_k = e^{i pi k/(2N)} (w y_k - i w y_{N-k}), by chirp-z of length N (H inputs)
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int m = tid + k * BLOCK;
+            v[k] = m == 0 ? make_double2(wy(0), 0.0)
+                 : m < H  ? cmulc(make_double2(wy(m), -wy(N - m)), tload(ax.htw, m))
+                          : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        chirp_slots<LOGP, SL>(v, ax.syn, H, N, lds, tw);
+        double* ur = reinterpret_cast<double*>(lds);
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int p = tid + k * BLOCK;
+            if (p < N) ur[p] = v[k].x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int j = tid + k * BLOCK;
+            if (j < N) out[k] = ur[(j & 1) ? N - 1 - (j >> 1) : (j >> 1)];  // Makhoul position of u_j
+        }
+        __syncthreads();
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int m = tid + k * BLOCK;
@@ -286,7 +353,7 @@ __device__ __forceinline__ void half_dct3(double (&out)[SL], const Axis& ax, dou
         }
     }
     __syncthreads();
-    chirp_slots<LOGP, SL>(v, ax.syn, H, lds, tw);
+    chirp_slots<LOGP, SL>(v, ax.syn, H, H, lds, tw);
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int m = tid + k * BLOCK;
@@ -325,7 +392,7 @@ __device__ __forceinline__ void half_dst(double (&out)[SL], const Axis& ax, doub
         v[k] = m < H ? make_double2(ys(2 * m), ys(2 * m + 1)) : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    chirp_slots<LOGP, SL>(v, ax.ana, H, lds, tw);
+    chirp_slots<LOGP, SL>(v, ax.ana, H, H, lds, tw);
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int m = tid + k * BLOCK;
@@ -431,17 +498,40 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
     // queues per workgroup make the one reserved entry irrelevant to the load balance,
     // which it does disturb for the short queues of the small classes.
     constexpr bool PREFETCH = LOGP >= 12;
+    // queue position of thread 0: the segment it takes from, and how many it has left
+    const int* segb = a.seg + cls * (NSEG + 1);
+    int* qc = a.counters + cls * NSEG;
+    int sq = blockIdx.x % NSEG, left = NSEG;
+    auto next_item = [&]() -> int {
+        while (left > 0) {
+            const int lo = segb[sq], hi = segb[sq + 1];
+            if (hi > lo) {
+                const int i = lo + atomicAdd(&qc[sq], 1);
+                if (i < hi) return i;
+            }
+            sq = sq + 1 == NSEG ? 0 : sq + 1;
+            --left;
+        }
+        return count;
+    };
+    // the certified pass: coefficients from f (left there by the feature pass); the lean
+    // form also takes d from the feature pass's spectrum and keeps neither the coefficients
+    // nor d, s in registers across the GCV phase (it re-reads them), which is what bounds
+    // its register use
+    constexpr bool FROM_F = MODE == MODE_LEARNED || MODE == MODE_LEARNED_RC;
+    constexpr bool LEAN = MODE == MODE_LEARNED;
+    constexpr bool CERT = FROM_F || MODE == MODE_FUSED;
     int nxt = 0;
-    if (PREFETCH && tid == 0) nxt = atomicAdd(&a.counters[cls], 1);
+    if (PREFETCH && tid == 0) nxt = next_item();
     for (;;) {
-        if (tid == 0) s_item = PREFETCH ? nxt : atomicAdd(&a.counters[cls], 1);
+        if (tid == 0) s_item = PREFETCH ? nxt : next_item();
         __syncthreads();
         // uniform across the workgroup: keeps the signal's descriptor and table pointers in
         // scalar registers
         const int qi = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (qi >= count) break;
-        if (PREFETCH && tid == 0) nxt = atomicAdd(&a.counters[cls], 1);
+        if (PREFETCH && tid == 0) nxt = next_item();
         const RSig sg = uniform_load(a.sigs + start + qi);
         const Axis ax = uniform_load(a.axes + sg.axis);
         // read per signal so that no twiddle address is hoisted out of the queue loop
@@ -455,13 +545,16 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
         // ---- inverse transform: boundary coefficients, interior correction, core analysis
         double x1, xn;
         double c[SL];
-        if constexpr (MODE == MODE_LEARNED) {  // coefficients left in f by the feature pass
+        float lcf[SL];  // feature pass: log10(c^2 + 1e-20)
+        if constexpr (FROM_F) {  // coefficients left in f by the feature pass
             x1 = f[0];
             xn = f[n - 1];
 #pragma unroll
             for (int k = 0; k < SL; ++k) {
                 const int j = tid + k * BLOCK;
-                c[k] = j < N ? f[j + 1] : 0.0;
+                // the lean pass re-reads them where it needs them (no registers held
+                // across the GCV phase)
+                c[k] = (!LEAN && j < N) ? f[j + 1] : 0.0;
             }
         } else {
         {
@@ -515,6 +608,9 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             for (int k = 0; k < SL; ++k) {
                 const int j = tid + k * BLOCK;
                 if (j < N) f[j + 1] = c[k];
+                // only the logarithm is needed from here on (the features): one float
+                // register per slot instead of a double across the eigenvalue sums
+                lcf[k] = __builtin_amdgcn_logf(static_cast<float>(c[k] * c[k] + 1e-20)) * LOG10_2F;
             }
             if (tid == 0) {
                 f[0] = x1;
@@ -528,7 +624,7 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
         // (the learned pass reads d from the feature pass and needs only cos(pi num / den)
         // at its own frequency for s: it reads those straight from the table, coalesced,
         // and skips the staging)
-        const bool staged = !(MODE == MODE_LEARNED && a.spec);
+        const bool staged = !LEAN;
         double* ctab = reinterpret_cast<double*>(lds);
         if (staged) {
             __syncthreads();
@@ -556,14 +652,14 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             const int j = tid + k * BLOCK;
             dj[k] = z0;
             sj[k] = s_poly;
-            if (j < N && j >= rank) {
+            if (!LEAN && j < N && j >= rank) {
                 const int num = kind == HT_KIND_C ? j : j + 1;  // frequency pi * num / den
                 const int mj = mirror(j);
                 const bool lead = pair && mj > j && mj < N && mj >= rank;
                 const bool follow = pair && mj < j && mj >= rank;
                 double acc = 0.0;
-                if (MODE == MODE_LEARNED && a.spec) {
-                    acc = a.spec[sg.off + 1 + j];  // left by the feature pass
+                if (LEAN) {
+                    // d and s are read where they are used (lean_ds)
                 } else if (follow) {
                     // d_j arrives from the owner of mj below
                 } else if (centred) {
@@ -624,7 +720,9 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             for (int k = 0; k < SL; ++k) {
                 const int j = tid + k * BLOCK;
                 if (j < N) {
-                    const float lc = __builtin_amdgcn_logf(static_cast<float>(c[k] * c[k] + 1e-20)) * LOG10_2;
+                    const float lc = MODE == MODE_FEATURES
+                                         ? lcf[k]
+                                         : __builtin_amdgcn_logf(static_cast<float>(c[k] * c[k] + 1e-20)) * LOG10_2;
                     const float ld = __builtin_amdgcn_logf(static_cast<float>(dj[k] * dj[k] + 1e-20)) * LOG10_2;
                     lg[j] = make_double2(lc, ld);
                     if (a.spec) a.spec[sg.off + 1 + j] = dj[k];
@@ -699,13 +797,28 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
         __builtin_amdgcn_sched_barrier(0);
         // ---- GCV: stage t_i = |d_i|^2 / |s_i|^2, w_i = |ghat_i|^2 (s_i = 0: no contribution)
         double2* stage = lds;
+        // lean pass: d_j from the feature pass's spectrum, s_j from the cosine table
+        auto lean_ds = [&](int j, double& d, double& sv) {
+            d = a.spec[sg.off + 1 + j];
+            if (j < rank) {
+                sv = s_poly;
+            } else {
+                const int rn = (kind == HT_KIND_C ? j : j + 1) % per;
+                sv = ident ? 1.0 : 2.0 - 2.0 * ax.tcos[rn <= den ? rn : per - rn];
+            }
+        };
         auto stage_fill = [&]() {
 #pragma unroll
             for (int k = 0; k < SL; ++k) {
                 const int j = tid + k * BLOCK;
                 if (j < N) {
-                    const double s2 = sj[k] * sj[k];
-                    stage[j] = s2 != 0.0 ? make_double2(dj[k] * dj[k] / s2, c[k] * c[k]) : make_double2(1e150, 0.0);
+                    double d = dj[k], sv = sj[k], cj = c[k];
+                    if (LEAN) {
+                        lean_ds(j, d, sv);
+                        cj = f[j + 1];
+                    }
+                    const double s2 = sv * sv;
+                    stage[j] = s2 != 0.0 ? make_double2(d * d / s2, cj * cj) : make_double2(1e150, 0.0);
                 }
             }
             if (tid == 0) {
@@ -823,7 +936,7 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             return __builtin_amdgcn_readfirstlane(s_kbest);
         };
         int kstar;
-        if constexpr (MODE == MODE_LEARNED || MODE == MODE_FUSED) {
+        if constexpr (CERT) {
             // nearest grid index to the prediction, then the certificate bracket
             if (tid < 64) {  // wave 0: lane-strided scan, then a first-index argmin across lanes
                 const double pr = static_cast<double>(MODE == MODE_FUSED ? s_pred : a.pred[sg.item]);
@@ -881,7 +994,19 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
         __builtin_amdgcn_sched_barrier(0);
         // ---- Tikhonov filter at mu*: fhat = d ghat / (d^2 + mu s^2)
 #pragma unroll
-        for (int k = 0; k < SL; ++k) c[k] = dj[k] * c[k] / fma(mu_s, sj[k] * sj[k], dj[k] * dj[k]);
+        for (int k = 0; k < SL; ++k) {
+            if constexpr (LEAN) {
+                const int j = tid + k * BLOCK;
+                c[k] = 0.0;
+                if (j < N) {
+                    double d, sv;
+                    lean_ds(j, d, sv);
+                    c[k] = d * f[j + 1] / fma(mu_s, sv * sv, d * d);
+                }
+            } else {
+                c[k] = dj[k] * c[k] / fma(mu_s, sj[k] * sj[k], dj[k] * dj[k]);
+            }
+        }
         const double fpoly = z0 / fma(mu_s, s_poly * s_poly, z0 * z0);
         const double fx1 = fpoly * x1, fxn = fpoly * xn;
         if (tid < rank) bc[tid].x = c[0];
@@ -979,6 +1104,8 @@ void launch_mode(const RaggedArgs& a, int c, int variant, int start, int cnt, in
 void batch_launch_scan(const RaggedArgs& a, int c, int variant, int start, int cnt, int grid, hipStream_t stream);
 void batch_launch_features(const RaggedArgs& a, int c, int variant, int start, int cnt, int grid, hipStream_t stream);
 void batch_launch_learned(const RaggedArgs& a, int c, int variant, int start, int cnt, int grid, hipStream_t stream);
+void batch_launch_learned_rc(const RaggedArgs& a, int c, int variant, int start, int cnt, int grid,
+                             hipStream_t stream);
 void batch_launch_fused(const RaggedArgs& a, int c, int variant, int start, int cnt, int grid, hipStream_t stream);
 // persistent workgroups that fill the device for class c (occupancy of the scan kernel)
 int batch_full_grid(int cls, int variant, int device);

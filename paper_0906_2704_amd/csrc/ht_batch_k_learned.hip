@@ -8,4 +8,9 @@ void batch_launch_learned(const RaggedArgs& a, int c, int variant, int start, in
     launch_mode<MODE_LEARNED>(a, c, variant, start, cnt, grid, stream);
 }
 
+void batch_launch_learned_rc(const RaggedArgs& a, int c, int variant, int start, int cnt, int grid,
+                             hipStream_t stream) {
+    launch_mode<MODE_LEARNED_RC>(a, c, variant, start, cnt, grid, stream);
+}
+
 }  // namespace ht

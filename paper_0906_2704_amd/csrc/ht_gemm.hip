@@ -43,6 +43,7 @@ namespace ht {
 constexpr int GT_M = 128;  // GEMM block tile (rows of A and rows of B)
 constexpr int GT_K = 32;   // contraction tile (one v_mfma_f32_16x16x32 step)
 constexpr int K_ALIGN = 64;
+static_assert(K_ALIGN == 2 * GT_K, "the split GEMM runs its contraction steps in pairs");
 constexpr int LDS_ROW = GT_K + 8;  // 80-byte rows: conflict-free 16-byte fragment reads
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -422,9 +423,11 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
 // D = A B^T for A [rows_a][Kp], B [rows_b][Kp] (high and low parts), one 128 x 128 tile per
 // workgroup of four waves (64 x 64 each, 4 x 4 MFMA tiles of 16 x 16).  Lane l supplies
 // A row l % 16 and B row l % 16 with the contraction slice 8 (l / 16) + 0..7, and holds
-// D rows 4 (l / 16) + 0..3 of column l % 16.  Double-buffered LDS, one barrier per step.
+// D rows 4 (l / 16) + 0..3 of column l % 16.  Double-buffered LDS, one barrier per step;
+// the global loads run two steps ahead (two register sets), so that each has two steps of
+// matrix-core work to arrive before its LDS store.
 template <int PREC>
-__global__ __launch_bounds__(256) void k_gemm_split(GemmSplitArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_split(GemmSplitArgs g) {
     __shared__ __attribute__((aligned(16))) uint16_t sm[2][4][GT_M][LDS_ROW];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
@@ -451,20 +454,20 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmSplitArgs g) {
     const uint16_t* src[4] = {g.a_hi + z * g.a_img + a_row0 * Kp, g.a_lo + z * g.a_img + a_row0 * Kp,
                               g.b_hi + z * g.b_img + b_row0 * Kp, g.b_lo + z * g.b_img + b_row0 * Kp};
     const int lrow = tid >> 2, lseg = (tid & 3) * 8;
-    u32x4 pre[8];
-    auto gload = [&](int k0) {
+    u32x4 pre[2][8];
+    auto gload = [&](u32x4 (&r)[8], int k0) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
             for (int h = 0; h < 2; ++h)
-                pre[2 * a + h] = *reinterpret_cast<const u32x4*>(src[a] + static_cast<int64_t>(lrow + 64 * h) * Kp + k0 + lseg);
+                r[2 * a + h] = *reinterpret_cast<const u32x4*>(src[a] + static_cast<int64_t>(lrow + 64 * h) * Kp + k0 + lseg);
         }
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](const u32x4 (&r)[8], int buf) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) *reinterpret_cast<u32x4*>(&sm[buf][a][lrow + 64 * h][lseg]) = pre[2 * a + h];
+            for (int h = 0; h < 2; ++h) *reinterpret_cast<u32x4*>(&sm[buf][a][lrow + 64 * h][lseg]) = r[2 * a + h];
         }
     };
 
@@ -474,14 +477,22 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmSplitArgs g) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    const int nk = Kp / GT_K;
-    gload(0);
-    sstore(0);
+    const int nk = Kp / GT_K;  // even: Kp is a multiple of K_ALIGN = 2 GT_K
+    gload(pre[0], 0);
+    gload(pre[1], GT_K);
+    sstore(pre[0], 0);
     __syncthreads();
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    for (int kt = 0; kt < nk; ++kt) {
+    // step kt: the loads of step kt + 2 go to register set kt % 2 (its data, step kt, is in
+    // LDS since the end of step kt - 1); set (kt + 1) % 2, loaded during step kt - 1, is
+    // stored at the end of the step.  Two steps per loop trip keep the set indices static.
+    // The loads and stores are unconditional (past the end they repeat the last slice into
+    // the buffer nobody reads again), so that the wait before each store only covers the
+    // older register set.
+    auto step = [&](int kt, u32x4 (&rnow)[8], u32x4 (&rnext)[8]) {
         const int buf = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * GT_K);
+        gload(rnow, (kt + 2 < nk ? kt + 2 : nk - 1) * GT_K);
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the step's work
         u32x4 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -502,8 +513,12 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmSplitArgs g) {
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = mfma16<PREC>(al[i], bh[j], acc[i][j]);
-        if (kt + 1 < nk) sstore(buf ^ 1);
+        sstore(rnext, buf ^ 1);
         __syncthreads();
+    };
+    for (int kt = 0; kt < nk; kt += 2) {
+        step(kt, pre[0], pre[1]);
+        step(kt + 1, pre[1], pre[0]);
     }
 
     // epilogue (float64)

@@ -64,15 +64,18 @@ struct Axis {
     const double2* f3v;   // [n]
     const double* f3b;    // [2][n]: cosine column, cubic column (all n rows)
     double2 f3vi[4];      // Vi, row-major
-    // Half-length real cores (ragged batches, real kinds with an even real-DFT length:
-    // N for the cosine core, N + 1 for the sine core): the core is a real DFT of that
-    // length, computed as a complex DFT of H = half of it by the chirp-z tables in ana
-    // (analysis) / syn (synthesis), with pre- and post-processing on htw.  0 otherwise.
+    // Half-length real cores (ragged batches, real kinds): the core is a real DFT of
+    // length L (N for the cosine core, N + 1 for the sine core) of which only the outputs
+    // k <= L/2 are needed.  half = 1 (L even): a complex DFT of H = L/2 packed pairs;
+    // half = 2 (cosine core, N odd): a chirp-z DFT of length N that keeps H = (N + 1)/2
+    // outputs (the synthesis: reads H inputs).  Tables in ana (analysis) / syn
+    // (synthesis), pre- and post-processing on htw.  0: the full chirp-z core.
     int half;
     int H;
     double hw[2];         // cosine core: sqrt(1/N), sqrt(2/N); sine core: sqrt(2/(N+1)), 0
-    const double2* htw;   // [2][H + 1]: cosine core e^{-2 pi i k/N}, e^{-i pi k/(2N)};
-                          //             sine core e^{2 pi i k/(N+1)}, (sin(pi k/(N+1)), 0)
+    const double2* htw;   // half = 1: [2][H + 1]: cosine core e^{-2 pi i k/N}, e^{-i pi k/(2N)};
+                          //   sine core e^{2 pi i k/(N+1)}, (sin(pi k/(N+1)), 0).
+                          // half = 2: [H]: e^{-i pi k/(2N)}.
 };
 
 // Strided view of a batch of 1D signals: signal b lives at

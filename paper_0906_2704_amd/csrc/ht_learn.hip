@@ -118,6 +118,9 @@ struct ht_mlp {
     float* M = nullptr;         // Adam first moments
     float* V = nullptr;         // Adam second moments
     uint16_t* Pb = nullptr;     // bfloat16 copies (every entry; the GEMMs read the weights)
+    uint16_t* Wt = nullptr;     // the bfloat16 weights transposed ([out][in] per layer, at the
+                                // offsets of LAYOUT.w): contiguous along the contraction for the
+                                // forward GEMMs
     float* mean = nullptr;      // [72]
     float* stdv = nullptr;      // [72]
     float* w4r = nullptr;       // [256] float32 value of the bfloat16 W4
@@ -145,16 +148,17 @@ ht_status mlp_forward_rows(ht_mlp* m, const float* X, int64_t B, float* pred, hi
     const int H = MLP_H;
     ht_status s = ht_to_bf16(X, m->Xb, B, MLP_IN, m->mean, m->stdv, st);
     if (s) return s;
-    s = ht_gemm_bf16(static_cast<int>(B), H, MLP_IN, m->Xb, MLP_IN, 1, m->Pb + L.w[0], H, 1, m->P + L.b[0], 1,
+    // B(k, j) = W[k][j] read from the transposed copy Wt[j][k] (sb_k = 1, sb_j = fan_in)
+    s = ht_gemm_bf16(static_cast<int>(B), H, MLP_IN, m->Xb, MLP_IN, 1, m->Wt + L.w[0], 1, MLP_IN, m->P + L.b[0], 1,
                      keep ? m->Z[0] : nullptr, nullptr, H, m->Hb[0], st);
     if (s) return s;
-    s = ht_gemm_bf16(static_cast<int>(B), H, H, m->Hb[0], H, 1, m->Pb + L.w[1], H, 1, m->P + L.b[1], 1,
+    s = ht_gemm_bf16(static_cast<int>(B), H, H, m->Hb[0], H, 1, m->Wt + L.w[1], 1, H, m->P + L.b[1], 1,
                      keep ? m->Z[1] : nullptr, nullptr, H, m->Hb[1], st);
     if (s) return s;
-    s = ht_gemm_bf16(static_cast<int>(B), H, H, m->Hb[1], H, 1, m->Pb + L.w[2], H, 1, m->P + L.b[2], 1,
+    s = ht_gemm_bf16(static_cast<int>(B), H, H, m->Hb[1], H, 1, m->Wt + L.w[2], 1, H, m->P + L.b[2], 1,
                      keep ? m->Z[2] : nullptr, keep ? m->H3 : nullptr, H, m->Hb[2], st);
     if (s) return s;
-    return ht_gemm_bf16(static_cast<int>(B), 1, H, m->Hb[2], H, 1, m->Pb + L.w[3], 1, 1, m->P + L.b[3], 0, nullptr,
+    return ht_gemm_bf16(static_cast<int>(B), 1, H, m->Hb[2], H, 1, m->Wt + L.w[3], 1, H, m->P + L.b[3], 0, nullptr,
                         pred, 1, nullptr, st);
 }
 
@@ -189,9 +193,20 @@ ht_status mlp_backward_rows(ht_mlp* m, const float* t, int64_t B, float* loss, h
     return HT_OK;
 }
 
+// the transposed bfloat16 weights, after every change of the bfloat16 copies
+ht_status refresh_wt(ht_mlp* m, hipStream_t st) {
+    for (int l = 0; l < 4; ++l) {
+        ht_status s = ht_transpose_bf16(m->Pb + LAYOUT.w[l], m->Wt + LAYOUT.w[l], static_cast<int>(MLP_DIMS[l]),
+                                        static_cast<int>(MLP_DIMS[l + 1]), st);
+        if (s) return s;
+    }
+    return HT_OK;
+}
+
 ht_status mlp_adam(ht_mlp* m, float lr, hipStream_t st) {
     m->steps += 1;
-    return ht_adam(m->P, m->G, m->M, m->V, LAYOUT.total, lr, 0.9f, 0.999f, 1e-8f, m->steps, m->Pb, st);
+    ht_status s = ht_adam(m->P, m->G, m->M, m->V, LAYOUT.total, lr, 0.9f, 0.999f, 1e-8f, m->steps, m->Pb, st);
+    return s ? s : refresh_wt(m, st);
 }
 
 ht_status check_rows(const ht_mlp* m, int64_t rows, const char* what) {
@@ -219,7 +234,7 @@ extern "C" ht_status ht_mlp_create(int64_t max_rows, ht_mlp** out) {
     const int64_t P = LAYOUT.total, R = max_rows, H = MLP_H;
     // arena: float32 blocks then bfloat16 blocks, each block 256-byte aligned
     int64_t f32[] = {P, P, P, P, MLP_IN, MLP_IN, H, R * H, R * H, R * H, R * H, R, R, R, R * H, R * H, R * MLP_IN, R};
-    int64_t b16[] = {P, R * MLP_IN, R * H, R * H, R * H, R * H};
+    int64_t b16[] = {P, P, R * MLP_IN, R * H, R * H, R * H, R * H};
     size_t bytes = 0;
     auto pad = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
     for (int64_t e : f32) bytes += pad(static_cast<size_t>(e) * 4);
@@ -252,6 +267,7 @@ extern "C" ht_status ht_mlp_create(int64_t max_rows, ht_mlp** out) {
     m->Xg = static_cast<float*>(take(R * MLP_IN, 4));
     m->tg = static_cast<float*>(take(R, 4));
     m->Pb = static_cast<uint16_t*>(take(P, 2));
+    m->Wt = static_cast<uint16_t*>(take(P, 2));
     m->Xb = static_cast<uint16_t*>(take(R * MLP_IN, 2));
     for (int l = 0; l < 3; ++l) m->Hb[l] = static_cast<uint16_t*>(take(R * H, 2));
     m->dZb = static_cast<uint16_t*>(take(R * H, 2));
@@ -285,7 +301,8 @@ extern "C" ht_status ht_mlp_set_params(ht_mlp* m, const float* params, hipStream
     ht_status s = check_hip(hipMemcpyAsync(m->P, params, LAYOUT.total * 4, hipMemcpyDeviceToDevice, st),
                             "ht_mlp_set_params: copy");
     if (s) return s;
-    return ht_to_bf16(m->P, m->Pb, LAYOUT.total, 1, nullptr, nullptr, st);
+    s = ht_to_bf16(m->P, m->Pb, LAYOUT.total, 1, nullptr, nullptr, st);
+    return s ? s : refresh_wt(m, st);
 }
 
 extern "C" ht_status ht_mlp_get(const ht_mlp* m, int what, float* out, hipStream_t st) {

@@ -127,6 +127,7 @@ typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
 constexpr int VKC = 64, VPAD = VKC + 8;
 
+template <bool BT>  // BT: B is given transposed (B(k, j) = B[j sb_j + k]), staged without a transpose
 __global__ __launch_bounds__(256) void k_gemm_vec(Gemm g) {
     __shared__ __attribute__((aligned(16))) uint16_t sA[GB][VPAD];
     __shared__ __attribute__((aligned(16))) uint16_t sB[GB][VPAD];
@@ -148,15 +149,22 @@ __global__ __launch_bounds__(256) void k_gemm_vec(Gemm g) {
             u32x4v va = u32x4v{0u, 0u, 0u, 0u};
             if (gi < g.M && gk < g.K) va = *reinterpret_cast<const u32x4v*>(g.A + gi * g.sa_i + gk);
             *reinterpret_cast<u32x4v*>(&sA[ar][seg]) = va;
-            const int bk = v >> 3;
-            const int64_t gj = col0 + seg;
-            const int gk2 = k0 + bk;
-            u32x4v vb = u32x4v{0u, 0u, 0u, 0u};
-            if (gj < g.N && gk2 < g.K) vb = *reinterpret_cast<const u32x4v*>(g.B + gk2 * g.sb_k + gj);
+            if constexpr (BT) {  // column ar of C, contraction slice seg .. seg + 7
+                const int64_t gj = col0 + ar;
+                u32x4v vb = u32x4v{0u, 0u, 0u, 0u};
+                if (gj < g.N && gk < g.K) vb = *reinterpret_cast<const u32x4v*>(g.B + gj * g.sb_j + gk);
+                *reinterpret_cast<u32x4v*>(&sB[ar][seg]) = vb;
+            } else {
+                const int bk = v >> 3;
+                const int64_t gj = col0 + seg;
+                const int gk2 = k0 + bk;
+                u32x4v vb = u32x4v{0u, 0u, 0u, 0u};
+                if (gj < g.N && gk2 < g.K) vb = *reinterpret_cast<const u32x4v*>(g.B + gk2 * g.sb_k + gj);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                sB[seg + 2 * i][bk] = static_cast<uint16_t>(vb[i] & 0xffffu);
-                sB[seg + 2 * i + 1][bk] = static_cast<uint16_t>(vb[i] >> 16);
+                for (int i = 0; i < 4; ++i) {
+                    sB[seg + 2 * i][bk] = static_cast<uint16_t>(vb[i] & 0xffffu);
+                    sB[seg + 2 * i + 1][bk] = static_cast<uint16_t>(vb[i] >> 16);
+                }
             }
         }
         __syncthreads();
@@ -188,6 +196,18 @@ __global__ __launch_bounds__(256) void k_gemm_vec(Gemm g) {
             if (g.Cb) g.Cb[ci * g.ldc + cj] = yb;
         }
     }
+}
+
+// dst[c][r] = src[r][c] for a [rows][cols] bfloat16 matrix (32 x 32 tiles through LDS)
+__global__ __launch_bounds__(256) void k_transpose16(const uint16_t* src, uint16_t* dst, int rows, int cols) {
+    __shared__ uint16_t t[32][33];
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int i = ty; i < 32; i += 8)
+        if (r0 + i < rows && c0 + tx < cols) t[i][tx] = src[static_cast<int64_t>(r0 + i) * cols + c0 + tx];
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8)
+        if (c0 + i < cols && r0 + tx < rows) dst[static_cast<int64_t>(c0 + i) * rows + r0 + tx] = t[tx][i];
 }
 
 // dst = bf16((src - mean[col]) / std[col]) (mean/std may be null: plain conversion)
@@ -292,10 +312,14 @@ extern "C" ht_status ht_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_
     const int64_t blocks = static_cast<int64_t>((M + GB - 1) / GB) * ((N + GB - 1) / GB);
     if (blocks > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "ht_gemm_bf16: too large");
     Gemm g{M, N, K, A, sa_i, sa_k, B, sb_k, sb_j, bias, act, Z, C, ldc, Cb};
-    const bool vec = sa_k == 1 && sb_j == 1 && K % 8 == 0 && N % 8 == 0 && sa_i % 8 == 0 && sb_k % 8 == 0 &&
-                     (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
-    if (vec)
-        hipLaunchKernelGGL(k_gemm_vec, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, g);
+    const bool avec = sa_k == 1 && K % 8 == 0 && sa_i % 8 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+    const bool brow = sb_j == 1 && N % 8 == 0 && sb_k % 8 == 0;       // B row-major [K][N]
+    const bool bcol = sb_k == 1 && sb_j % 8 == 0;                     // B^T row-major [N][K]
+    if (avec && bcol)
+        hipLaunchKernelGGL(k_gemm_vec<true>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, g);
+    else if (avec && brow)
+        hipLaunchKernelGGL(k_gemm_vec<false>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, g);
     else
         hipLaunchKernelGGL(k_gemm, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, g);
     return check_hip(hipGetLastError(), "ht_gemm_bf16 launch");
@@ -360,4 +384,13 @@ extern "C" ht_status ht_adam(float* p, const float* g, float* m, float* v, int64
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(count)), dim3(256), 0, stream, p, g, m, v, count, lr, beta1, beta2, eps,
                        c1, c2, pb);
     return check_hip(hipGetLastError(), "ht_adam launch");
+}
+
+extern "C" ht_status ht_transpose_bf16(const uint16_t* src, uint16_t* dst, int rows, int cols, hipStream_t stream) {
+    if (rows < 0 || cols < 0 || (rows > 0 && cols > 0 && (!src || !dst)) || src == dst)
+        return fail(HT_ERR_INVALID_ARG, "ht_transpose_bf16: bad argument");
+    if (rows == 0 || cols == 0) return HT_OK;
+    hipLaunchKernelGGL(k_transpose16, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, stream, src, dst, rows,
+                       cols);
+    return check_hip(hipGetLastError(), "ht_transpose_bf16 launch");
 }

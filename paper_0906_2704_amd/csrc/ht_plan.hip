@@ -14,6 +14,7 @@
 //   trig        cos / sin (pi r / den) for the eigenvalue grid
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -165,19 +166,22 @@ static void make_chirp(int kind, bool synthesis, int N, int M, HostChirp& hc) {
     hc.B.swap(bc);
 }
 
-// Chirp-z tables of the plain complex DFT of length H, Y_k = sum_j x_j e^{sign 2 pi i jk/H}
-// (unscaled), on an FFT of length M >= 2H - 1: pre_j = e^{sign i pi j^2/H}, post_k likewise,
-// b_m = e^{-sign i pi m^2/H}.
-static void make_dft_chirp(int H, int sign, int M, HostChirp& hc) {
-    hc.pre.assign(H, cd());
-    hc.post.assign(H, cd());
+// Chirp-z tables of the plain complex DFT of length L, Y_k = sum_j x_j e^{sign 2 pi i jk/L}
+// (unscaled), for an input of nin leading entries of which the first nout outputs are
+// kept: pre_j = post_j = e^{sign i pi j^2/L}, b_m = e^{-sign i pi m^2/L} for -nin < m < nout,
+// stored circularly in M >= nin + nout - 1 points so that no wrapped term reaches a kept
+// output.
+static void make_dft_chirp(int L, int sign, int M, int nin, int nout, HostChirp& hc) {
+    hc.pre.assign(nin, cd());
+    hc.post.assign(nout, cd());
     std::vector<cd> bc(M, cd());
-    for (int64_t m = 0; m < H; ++m) {
-        hc.pre[m] = cis_exact(sign * m * m, 2LL * H);
-        hc.post[m] = hc.pre[m];
-        const cd b = cis_exact(-sign * m * m, 2LL * H);
-        bc[m] = b;
-        if (m > 0) bc[M - m] = b;
+    for (int64_t m = 0; m < std::max(nin, nout); ++m) {
+        const cd c = cis_exact(sign * m * m, 2LL * L);
+        if (m < nin) hc.pre[m] = c;
+        if (m < nout) hc.post[m] = c;
+        const cd b = cis_exact(-sign * m * m, 2LL * L);
+        if (m < nout) bc[m] = b;
+        if (m > 0 && m < nin) bc[M - m] = b;
     }
     host_fft(bc, -1);
     const double inv = 1.0 / M;
@@ -186,26 +190,41 @@ static void make_dft_chirp(int H, int sign, int M, HostChirp& hc) {
     hc.mode = MODE_CPLX;
 }
 
-// Half-length real cores.  The cosine core (N even, H = N/2): Makhoul's reordering
-// v_p = x_{2p}, v_{N-1-p} = x_{2p+1} turns the DCT-II into X_k = Re(e^{-i pi k/(2N)} V_k)
-// with V the real DFT of v, a complex DFT of length H of u_m = v_{2m} + i v_{2m+1};
-// the DCT-III is the same steps reversed.  The sine core (N + 1 = L even, H = L/2): with
-// y_t = sin(pi t/L)(x_t + x_{L-t}) + (x_t - x_{L-t})/2 (x_0 = x_L = 0) and Y its real DFT
-// (e^{+}), the sine transform is S_{2k} = Im Y_k and S_{2k+1} = S_{2k-1} + Re Y_k
-// (S_1 = Re Y_0 / 2); Y again from a complex DFT of length H.  The FFT length becomes the
-// smallest power of two >= N + 2 (>= 2H - 1, and room in LDS for the eigenvalue staging)
-// instead of >= 2N - 1.
+// Half-length real cores.  Both core transforms are real DFTs of length L (N for the
+// cosine core, N + 1 for the sine core) with pre- and post-processing; a real DFT needs
+// only its outputs k <= L/2.
+//  * Even L (half = 1, H = L/2): a complex DFT of length H of the packed pairs.  The
+//    cosine core (Makhoul's reordering v_p = x_{2p}, v_{N-1-p} = x_{2p+1}) turns the
+//    DCT-II into X_k = Re(e^{-i pi k/(2N)} V_k) with V the real DFT of v, computed as the
+//    complex DFT of u_m = v_{2m} + i v_{2m+1}; the DCT-III is the same steps reversed.  The
+//    sine core: with y_t = sin(pi t/L)(x_t + x_{L-t}) + (x_t - x_{L-t})/2 (x_0 = x_L = 0)
+//    and Y its real DFT (e^{+}), S_{2k} = Im Y_k and S_{2k+1} = S_{2k-1} + Re Y_k
+//    (S_1 = Re Y_0 / 2).  FFT length: the smallest power of two >= N + 2 (>= 2H - 1, and
+//    room in LDS for the eigenvalue staging).
+//  * Odd L, cosine core only (half = 2, H = (N + 1)/2): the same real DFT taken as a
+//    chirp-z transform of length N that keeps only the H outputs the post-processing reads
+//    (DCT-II), or reads only the H inputs that are not conjugate mirrors (DCT-III, the real
+//    part of a DFT of its first H terms with the k = 0 term not doubled).  FFT length: the
+//    smallest power of two >= N + H - 1 instead of >= 2N - 1.  The sine core keeps the
+//    full chirp-z core for odd L: its odd outputs are a running sum over about L/2 DFT
+//    outputs, whose rounding errors add up to 10-20 times the error of the direct core
+//    (float64 emulation against an exact sum), more than the restorations' 1e-12 relative
+//    accuracy leaves room for when the filter gain is large.  (The even-L sine form has the
+//    same running sum; it is kept, with its measured errors in the tests.)
 static ht_status make_half(HostAxis& h) {
     Axis& a = h.ax;
     const int N = a.N;
     const bool cosine = a.kind == HT_KIND_C;
     const int L = cosine ? N : N + 1;
-    if (L % 2 != 0 || L < 4) return HT_OK;  // odd length: the full chirp-z core
-    const int H = L / 2;
+    if (L < 4) return HT_OK;
+    const bool odd = L % 2 != 0;
+    if (odd && !cosine) return HT_OK;
+    const int H = odd ? (N + 1) / 2 : L / 2;
+    const int need = odd ? N + H - 1 : N + 2;
     int M = 512;
-    while (M < N + 2) M <<= 1;
+    while (M < need) M <<= 1;
     if (M >= h.M) return HT_OK;  // no gain
-    a.half = 1;
+    a.half = odd ? 2 : 1;
     a.H = H;
     a.hw[0] = static_cast<double>(cosine ? sqrtl(1.0L / N) : sqrtl(2.0L / L));
     a.hw[1] = static_cast<double>(cosine ? sqrtl(2.0L / N) : 0.0L);
@@ -213,8 +232,15 @@ static ht_status make_half(HostAxis& h) {
     a.S = 1;
     a.logP = 0;
     while ((1 << a.logP) < M) ++a.logP;
-    make_dft_chirp(H, cosine ? -1 : 1, M, h.ana);
-    make_dft_chirp(H, 1, M, h.syn);
+    if (odd) {  // analysis: N inputs, H outputs; synthesis: H inputs, N outputs
+        make_dft_chirp(N, -1, M, N, H, h.ana);
+        make_dft_chirp(N, 1, M, H, N, h.syn);
+        h.htw.assign(H, cd());  // e^{-i pi k/(2N)}, k < H
+        for (int k = 0; k < H; ++k) h.htw[k] = cis_exact(-k, 4LL * N);
+        return HT_OK;
+    }
+    make_dft_chirp(H, cosine ? -1 : 1, M, H, H, h.ana);
+    make_dft_chirp(H, 1, M, H, H, h.syn);
     h.htw.assign(2 * static_cast<size_t>(H + 1), cd());
     for (int k = 0; k <= H; ++k) {
         if (cosine) {

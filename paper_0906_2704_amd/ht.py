@@ -393,6 +393,7 @@ def _learned_sigs(L):
     L.ht_mse_grad.argtypes = [VP, VP, VP, VP, I64, VP]
     L.ht_outer.argtypes = [VP, VP, VP, I64, Ci, VP]
     L.ht_adam.argtypes = [VP, VP, VP, VP, I64, F, F, F, F, I64, VP, VP]
+    L.ht_transpose_bf16.argtypes = [VP, VP, Ci, Ci, VP]
     L.ht_mlp_param_count.argtypes = []
     L.ht_mlp_param_count.restype = I64
     L.ht_mlp_create.argtypes = [I64, ctypes.POINTER(VP)]
@@ -414,7 +415,7 @@ def _learned_sigs(L):
     L.ht_batch_count.argtypes = [VP]
     L.ht_batch_count.restype = I64
     for name in ("ht_batch_features", "ht_batch_restore_learned", "ht_batch_restore_fused", "ht_gemm_bf16", "ht_to_bf16", "ht_from_bf16",
-                 "ht_gelu_backward", "ht_colsum", "ht_mse_grad", "ht_outer", "ht_adam", "ht_mlp_create",
+                 "ht_gelu_backward", "ht_colsum", "ht_mse_grad", "ht_outer", "ht_adam", "ht_transpose_bf16", "ht_mlp_create",
                  "ht_mlp_destroy", "ht_mlp_set_params", "ht_mlp_get", "ht_mlp_set_state", "ht_mlp_fit_standardisation",
                  "ht_mlp_forward", "ht_mlp_predict", "ht_mlp_backward", "ht_mlp_adam_step", "ht_mlp_train_step", "ht_mlp_weights_of",
                  "ht_log10_labels", "ht_lambda_predict"):

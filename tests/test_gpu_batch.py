@@ -10,7 +10,7 @@ from oracle import tikhonov as tk
 from oracle import transforms as tr
 from paper_0906_2704_amd import synth
 
-from parity import assert_gcv_close
+from parity import assert_gcv_close, record
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -64,11 +64,13 @@ def check_items(items, bt, f, G, kb, mb, norm, kind_of=KIND_OF_DEGREE):
         fw = tr.forward(kind, tk.tikhonov_filter(ghat, d, s, muw)).real
         fb = f[bt.offsets[b]:bt.offsets[b + 1]]
         err = np.max(np.abs(fb - fw)) / np.max(np.abs(fw))
+        record("restore %s core %s n=%d" % (core_form(n, kind)[1], kind, n), err, TOL)
         assert err < TOL, (b, n, kind, err)
 
 
-# one or more lengths in every size class: FFT 512 (n <= 258), 1024 (<= 514),
-# 2048 (<= 1026), 4096 (<= 2050), 8192 (<= 4098), split 2 x 8192 (> 4098)
+# one or more lengths in every size class (for the full chirp-z core: FFT 512 (n <= 258),
+# 1024 (<= 514), 2048 (<= 1026), 4096 (<= 2050), 8192 (<= 4098), split 2 x 8192 (> 4098);
+# the half-length cores move lengths down, see fft_class)
 SMALL = [5, 7, 40, 130, 258, 259, 300, 514, 515, 777, 1026, 1027, 1500]
 LARGE = [2050, 2051, 3001, 4098, 4099, 6000]
 
@@ -80,16 +82,24 @@ def test_ragged_small_classes(ht, norm):
     check_items(items, bt, f, G, kb, mb, norm)
 
 
-def fft_class(n, kind):
-    """Size class of a signal: the FFT length is the smallest power of two >= 2N - 1 for the
-    chirp-z core, or >= N + 2 for the half-length real core when the core's real DFT length
-    (N for the cosine core, N + 1 for the sine core) is even and that is shorter."""
+def core_form(n, kind):
+    """(FFT length, core form) of a signal: the chirp-z core needs the smallest power of two
+    >= 2N - 1; where shorter, the half-length real core of an even real-DFT length L (N for
+    the cosine core, N + 1 for the sine core) needs >= N + 2 and the half-output cosine core
+    of an odd N needs >= N + (N+1)/2 - 1."""
     N = n - 2
     pow2 = lambda v: 1 << max(9, int(np.ceil(np.log2(v))))
-    M = pow2(2 * N - 1)
+    M, form = pow2(2 * N - 1), "chirp"
     L = N if kind == "C" else N + 1
-    if L % 2 == 0 and L >= 4:
-        M = min(M, pow2(N + 2))
+    if L >= 4 and L % 2 == 0 and pow2(N + 2) < M:
+        M, form = pow2(N + 2), "half"
+    elif kind == "C" and L >= 4 and pow2(N + (N + 1) // 2 - 1) < M:
+        M, form = pow2(N + (N + 1) // 2 - 1), "half-output"
+    return M, form
+
+
+def fft_class(n, kind):
+    M, _ = core_form(n, kind)
     return 5 if M >= 16384 else int(np.log2(M)) - 9
 
 
@@ -105,6 +115,10 @@ def test_ragged_large_classes(ht):
 # odd n for the sine cores (antireflective, DST3: N + 1 even), up to the largest length
 HALF_N = {2: [130, 258, 600, 1200, 2500, 5000, 8190], 1: [131, 257, 601, 1201, 2501, 5001, 8191],
           3: [131, 259, 603, 1203, 2503, 5003, 8189]}
+# half-output cosine cores (odd N: odd n for T_C): the largest length of each class, the
+# first length past it, a length the chirp-z core would put one class higher, the first
+# split-class length and the largest length
+ODD_N = [7, 259, 343, 345, 685, 687, 1367, 2733, 2735, 5463, 5465, 8191]
 
 
 @pytest.mark.parametrize("degree", [1, 2, 3])
@@ -117,6 +131,18 @@ def test_ragged_half_cores_every_class(ht, degree):
     bt, f, G, kb, mb = run_batch(ht, items, "D2")
     kind = KIND_OF_DEGREE[degree]
     assert [bt.class_count(c) for c in range(6)] == list(np.bincount([fft_class(n, kind) for n in ns], minlength=6))
+    check_items(items, bt, f, G, kb, mb, "D2")
+
+
+def test_ragged_half_output_cores_every_class(ht):
+    items = make_items(ODD_N, seed=32, K=64)
+    for p in items:
+        p.degree = 2
+    bt, f, G, kb, mb = run_batch(ht, items, "D2")
+    want = np.bincount([fft_class(n, "C") for n in ODD_N], minlength=6)
+    assert min(want) > 0
+    assert [bt.class_count(c) for c in range(6)] == list(want)
+    assert sum(core_form(n, "C")[1] == "half-output" for n in ODD_N) >= 6
     check_items(items, bt, f, G, kb, mb, "D2")
 
 

@@ -125,8 +125,14 @@ def test_features_and_certified_restore_match_oracle(ht):
     shifts = np.array([0, 1, -2, 3, 8, -9, 0, 2, -1, 20, 4, -4])
     kh = np.clip(kscan + shifts, 0, learned.GRID_K - 1)
     pred = torch.tensor(lm[kh].astype(np.float32), device=DEV)
+    coeff_rc = coeff.clone()
     out, kb, mb, fb = ht.ht_batch_restore_learned(bt, coeff, psf, "D2", mus, pred, cert_half=8, spectrum=spec)
     out, kb, fb = out.cpu().numpy(), kb.cpu().numpy(), fb.cpu().numpy()
+    # without the feature pass's spectrum the certified pass recomputes d from the PSF:
+    # the same choices, restorations equal to rounding
+    out_rc, kb_rc, _, fb_rc = ht.ht_batch_restore_learned(bt, coeff_rc, psf, "D2", mus, pred, cert_half=8)
+    assert np.array_equal(kb_rc.cpu().numpy(), kb) and np.array_equal(fb_rc.cpu().numpy(), fb)
+    assert rel_normwise(out_rc.cpu().numpy(), out) < 1e-13
     for b in range(rb.n.size):
         kind, d, s, ghat = _oracle_item(rb, b)
         assert rel_normwise(coeff_h[rb.offsets[b]:rb.offsets[b + 1]], ghat) < 1e-12
