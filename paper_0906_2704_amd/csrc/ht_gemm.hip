@@ -40,11 +40,17 @@
 
 namespace ht {
 
-constexpr int GT_M = 128;  // GEMM block tile (rows of A and rows of B)
+constexpr int GT_M = 256;  // GEMM block tile (rows of A and rows of B)
+constexpr int GEMM_THREADS = 512;  // eight waves per GEMM workgroup
 constexpr int GT_K = 32;   // contraction tile (one v_mfma_f32_16x16x32 step)
 constexpr int K_ALIGN = 64;
-static_assert(K_ALIGN == 2 * GT_K, "the split GEMM runs its contraction steps in pairs");
-constexpr int LDS_ROW = GT_K + 8;  // 80-byte rows: conflict-free 16-byte fragment reads
+// LDS rows of GT_K elements (64 bytes, four 16-byte chunks), chunk c of row r stored at
+// chunk c ^ lds_swz(r).  A 16-byte access by 8 consecutive lanes covers 128 bytes and by 16
+// consecutive lanes 256 bytes; both the fragment reads (16 consecutive rows, one chunk) and
+// the tile stores (4 consecutive rows, all chunks) then touch distinct banks whether the
+// LDS serves 32 or 64 four-byte banks per cycle.
+constexpr int LDS_ROW = GT_K;
+__device__ __forceinline__ int lds_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -420,14 +426,19 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
                                                       0, 0, 0);
 }
 
-// D = A B^T for A [rows_a][Kp], B [rows_b][Kp] (high and low parts), one 128 x 128 tile per
-// workgroup of four waves (64 x 64 each, 4 x 4 MFMA tiles of 16 x 16).  Lane l supplies
-// A row l % 16 and B row l % 16 with the contraction slice 8 (l / 16) + 0..7, and holds
-// D rows 4 (l / 16) + 0..3 of column l % 16.  Double-buffered LDS, one barrier per step;
-// the global loads run two steps ahead (two register sets), so that each has two steps of
-// matrix-core work to arrive before its LDS store.
+// D = A B^T for A [rows_a][Kp], B [rows_b][Kp] (high and low parts), one 256 x 256 tile per
+// workgroup of eight waves (4 x 2; 64 x 128 each, 4 x 8 MFMA tiles of 16 x 16).  Lane l
+// supplies A row l % 16 and B row l % 16 with the contraction slice 8 (l / 16) + 0..7, and
+// holds D rows 4 (l / 16) + 0..3 of column l % 16.  The operand slices of a contraction step
+// go from global memory straight into LDS (global_load_lds_dwordx4: no register staging, no
+// LDS store instructions), double-buffered: the loads of step k + 1 run under the fragment
+// reads and matrix-core work of step k, one barrier per step.  The B fragments are read in
+// two halves so that at most 16 fragments are live.
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+typedef const __attribute__((address_space(1))) void* global_void_ptr;
+
 template <int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_split(GemmSplitArgs g) {
+__global__ __launch_bounds__(GEMM_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_split(GemmSplitArgs g) {
     __shared__ __attribute__((aligned(16))) uint16_t sm[2][4][GT_M][LDS_ROW];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
@@ -453,80 +464,83 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int64_t a_row0 = static_cast<int64_t>(tm) * GT_M, b_row0 = static_cast<int64_t>(tn) * GT_M;
     const uint16_t* src[4] = {g.a_hi + z * g.a_img + a_row0 * Kp, g.a_lo + z * g.a_img + a_row0 * Kp,
                               g.b_hi + z * g.b_img + b_row0 * Kp, g.b_lo + z * g.b_img + b_row0 * Kp};
-    const int lrow = tid >> 2, lseg = (tid & 3) * 8;
-    u32x4 pre[2][8];
-    auto gload = [&](u32x4 (&r)[8], int k0) {
+    // Each operand slice (GT_M rows x 64 bytes) is 16 blocks of 1 KB (16 rows); wave w loads
+    // blocks 2w and 2w + 1 of each, lane l filling the block's 16-byte slot l = (row l / 4,
+    // stored chunk l % 4), i.e. reading logical chunk (l % 4) ^ lds_swz(row).
+    static_assert(GEMM_THREADS / 64 * 2 * 16 == GT_M, "two 16-row blocks per wave and operand");
+    int64_t goff[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int row = 16 * (2 * w + h) + (lane >> 2);
+        goff[h] = static_cast<int64_t>(row) * Kp + 8 * ((lane & 3) ^ lds_swz(row));
+    }
+    auto dload = [&](int buf, int k0) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
             for (int h = 0; h < 2; ++h)
-                r[2 * a + h] = *reinterpret_cast<const u32x4*>(src[a] + static_cast<int64_t>(lrow + 64 * h) * Kp + k0 + lseg);
-        }
-    };
-    auto sstore = [&](const u32x4 (&r)[8], int buf) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) *reinterpret_cast<u32x4*>(&sm[buf][a][lrow + 64 * h][lseg]) = r[2 * a + h];
+                __builtin_amdgcn_global_load_lds((global_void_ptr)(src[a] + goff[h] + k0),
+                                                 (lds_void_ptr)(&sm[buf][a][16 * (2 * w + h)][0]), 16, 0, 0);
         }
     };
 
-    f32x4 acc[4][4];
+    f32x4 acc[4][8];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    const int nk = Kp / GT_K;  // even: Kp is a multiple of K_ALIGN = 2 GT_K
-    gload(pre[0], 0);
-    gload(pre[1], GT_K);
-    sstore(pre[0], 0);
+    const int nk = Kp / GT_K;
+    dload(0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    // step kt: the loads of step kt + 2 go to register set kt % 2 (its data, step kt, is in
-    // LDS since the end of step kt - 1); set (kt + 1) % 2, loaded during step kt - 1, is
-    // stored at the end of the step.  Two steps per loop trip keep the set indices static.
-    // The loads and stores are unconditional (past the end they repeat the last slice into
-    // the buffer nobody reads again), so that the wait before each store only covers the
-    // older register set.
-    auto step = [&](int kt, u32x4 (&rnow)[8], u32x4 (&rnext)[8]) {
+    for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
-        gload(rnow, (kt + 2 < nk ? kt + 2 : nk - 1) * GT_K);
-        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the step's work
-        u32x4 ah[4], al[4], bh[4], bl[4];
+        // buffer buf ^ 1 was last read in step kt - 1, which ended with a barrier
+        if (kt + 1 < nk) dload(buf ^ 1, (kt + 1) * GT_K);
+        u32x4 ah[4], al[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            ah[i] = *reinterpret_cast<const u32x4*>(&sm[buf][0][wm * 64 + i * 16 + fr][fk]);
-            al[i] = *reinterpret_cast<const u32x4*>(&sm[buf][1][wm * 64 + i * 16 + fr][fk]);
-            bh[i] = *reinterpret_cast<const u32x4*>(&sm[buf][2][wn * 64 + i * 16 + fr][fk]);
-            bl[i] = *reinterpret_cast<const u32x4*>(&sm[buf][3][wn * 64 + i * 16 + fr][fk]);
+            const int ra = wm * 64 + i * 16 + fr;
+            const int ca = fk ^ (8 * lds_swz(ra));
+            ah[i] = *reinterpret_cast<const u32x4*>(&sm[buf][0][ra][ca]);
+            al[i] = *reinterpret_cast<const u32x4*>(&sm[buf][1][ra][ca]);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int hb = 0; hb < 2; ++hb) {
+            u32x4 bh[4], bl[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma16<PREC>(ah[i], bh[j], acc[i][j]);
+            for (int j = 0; j < 4; ++j) {
+                const int rb = wn * 128 + (hb * 4 + j) * 16 + fr;
+                const int cb = fk ^ (8 * lds_swz(rb));
+                bh[j] = *reinterpret_cast<const u32x4*>(&sm[buf][2][rb][cb]);
+                bl[j] = *reinterpret_cast<const u32x4*>(&sm[buf][3][rb][cb]);
+            }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma16<PREC>(ah[i], bl[j], acc[i][j]);
+                for (int j = 0; j < 4; ++j) acc[i][hb * 4 + j] = mfma16<PREC>(ah[i], bh[j], acc[i][hb * 4 + j]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma16<PREC>(al[i], bh[j], acc[i][j]);
-        sstore(rnext, buf ^ 1);
+                for (int j = 0; j < 4; ++j) acc[i][hb * 4 + j] = mfma16<PREC>(ah[i], bl[j], acc[i][hb * 4 + j]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][hb * 4 + j] = mfma16<PREC>(al[i], bh[j], acc[i][hb * 4 + j]);
+        }
+        // this wave's loads of step kt + 1 have landed; the barrier makes every wave's visible
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-    };
-    for (int kt = 0; kt < nk; kt += 2) {
-        step(kt, pre[0], pre[1]);
-        step(kt + 1, pre[1], pre[0]);
     }
 
     // epilogue (float64)
     const float* sa = g.a_scale + z * g.a_simg;
     const float* sb = g.b_scale + z * g.b_simg;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int n = tn * GT_M + wn * 64 + j * 16 + fr;
+    for (int j = 0; j < 8; ++j) {
+        const int n = tn * GT_M + wn * 128 + j * 16 + fr;
         if (n >= g.n_lim) continue;
         const double sbn = static_cast<double>(sb[n]);
 #pragma unroll
@@ -834,7 +848,7 @@ static ht_status run_gemm(GemmSplitArgs g, hipStream_t s) {
     const int64_t nb = static_cast<int64_t>(g.tiles_m) * g.tiles_n * g.nz;
     if (nb <= 0) return HT_OK;
     if (nb > 0x7fffffffLL) return fail(HT_ERR_INVALID_ARG, "GEMM grid too large");
-    hipLaunchKernelGGL((k_gemm_split<PREC>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_gemm_split<PREC>), dim3(static_cast<unsigned>(nb)), dim3(GEMM_THREADS), 0, s, g);
     return check_hip(hipGetLastError(), "GEMM launch");
 }
 
