@@ -535,29 +535,67 @@ __global__ __launch_bounds__(GEMM_THREADS) __attribute__((amdgpu_waves_per_eu(2,
         __syncthreads();
     }
 
-    // epilogue (float64)
-    const float* sa = g.a_scale + z * g.a_simg;
-    const float* sb = g.b_scale + z * g.b_simg;
+    // epilogue (float64): for each 16-row group i, the row terms (scale, rank-2 and cross
+    // factors of the lane's four rows) are loaded once, then every column tile j; the inputs
+    // are read through restrict-qualified pointers so that the stores do not force reloads
+    const float* __restrict__ sa = g.a_scale + z * g.a_simg;
+    const float* __restrict__ sb = g.b_scale + z * g.b_simg;
+    const double* __restrict__ e1 = g.e1;
+    const double* __restrict__ e2 = g.e2;
+    const double* __restrict__ xb = g.xb ? g.xb + z * g.xb_img : nullptr;
+    const double* __restrict__ zc = g.cross.zc ? g.cross.zc + 2 * (z * g.cross.zc_img + g.zc_off) : nullptr;
+    const double* __restrict__ w0 = g.cross.w0;
+    const double* __restrict__ w1 = g.cross.w1;
+    double* __restrict__ out = g.out + z * g.o_img + g.o_off;
+    const bool pos_m = g.pos_is_m != 0;
+    const int m0 = tm * GT_M + wm * 64 + (lane >> 4) * 4;
+    const int n0 = tn * GT_M + wn * 128 + fr;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int n = tn * GT_M + wn * 128 + j * 16 + fr;
-        if (n >= g.n_lim) continue;
-        const double sbn = static_cast<double>(sb[n]);
+    for (int i = 0; i < 4; ++i) {
+        double rs[4], r1[4], r2[4], c0[4], c1[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int e = 0; e < 4; ++e) {
+            const int m = m0 + i * 16 + e;
+            const bool ok = m < g.m_lim;
+            rs[e] = ok ? static_cast<double>(sa[m]) : 0.0;
+            // rank-2 factors that depend on the row: e1/e2 at position m, or x_1/x_n of vector m
+            r1[e] = r2[e] = 0.0;
+            if (ok && e1) {
+                if (pos_m) {
+                    r1[e] = e1[m];
+                    r2[e] = e2[m];
+                } else {
+                    r1[e] = xb[static_cast<int64_t>(m) * g.xb_vs];
+                    r2[e] = xb[static_cast<int64_t>(m) * g.xb_vs + g.xb_last];
+                }
+            }
+            c0[e] = (ok && zc) ? zc[2 * m] : 0.0;
+            c1[e] = (ok && zc) ? zc[2 * m + 1] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int n = n0 + j * 16;
+            if (n >= g.n_lim) continue;
+            const double sbn = static_cast<double>(sb[n]);
+            double q1 = 0.0, q2 = 0.0;
+            if (e1) {
+                if (pos_m) {
+                    q1 = xb[static_cast<int64_t>(n) * g.xb_vs];
+                    q2 = xb[static_cast<int64_t>(n) * g.xb_vs + g.xb_last];
+                } else {
+                    q1 = e1[n];
+                    q2 = e2[n];
+                }
+            }
+            const double wa = zc ? w0[n] : 0.0, wb = zc ? w1[n] : 0.0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int m = tm * GT_M + wm * 64 + i * 16 + (lane >> 4) * 4 + e;
+                const int m = m0 + i * 16 + e;
                 if (m >= g.m_lim) continue;
-                double v = static_cast<double>(acc[i][j][e]) * (static_cast<double>(sa[m]) * sbn);
-                if (g.e1) {
-                    const int pos = g.pos_is_m ? m : n;
-                    const int64_t vec = g.pos_is_m ? n : m;
-                    const double* xp = g.xb + z * g.xb_img + vec * g.xb_vs;
-                    v = fma(g.e1[pos], xp[0], fma(g.e2[pos], xp[g.xb_last], v));
-                }
-                v += cross_at(g.cross, z * g.cross.zc_img + m + g.zc_off, n);
-                g.out[z * g.o_img + static_cast<int64_t>(m) * g.o_ldm + n + g.o_off] = v;
+                double v = static_cast<double>(acc[i][j][e]) * (rs[e] * sbn);
+                if (e1) v = fma(r1[e], q1, fma(r2[e], q2, v));
+                if (zc) v += fma(c0[e], wa, c1[e] * wb);
+                out[static_cast<int64_t>(m) * g.o_ldm + n] = v;
             }
         }
     }
