@@ -269,7 +269,7 @@ ht_status ht_gcv_scan_exact_static(const ht_plan* plan, const void* coeff, const
 
 /* ht_plan_reserve_exact_gcv -- size the workspace of ht_gcv_scan_exact on a 2D plan for
  * grids of up to max_k values (1..1024): row-pass outputs for a chunk of images (at most
- * 64 MiB, at least one image: n0 max_k 22 doubles per image), column-pass partials for
+ * 256 MiB, at least one image: n0 max_k 22 doubles per image), column-pass partials for
  * the same chunk and max_k doubles of G per image.  ht_plan_create reserves max_k = 128;
  * a call with a larger K than reserved returns HT_ERR_INVALID_ARG.  Set-up call:
  * synchronises the device; no-op for 1D plans, the comparators and a max_k already

@@ -301,7 +301,7 @@ __device__ __forceinline__ void gcv_pair_sums(const double2* stage, int len, int
 // parts are added in order: the result does not depend on scheduling.
 __device__ void gcv_accumulate(const Spec& sp, const void* coeff, int64_t b, int64_t e_begin,
                                int64_t e_end, const double* mus, int K, double2* part_out,
-                               double2* stage, double2* red) {
+                               double2* stage, double2* red, int chunk_cap = GCV_CHUNK) {
     const int tid = threadIdx.x;
     const int Kh = (K + 1) / 2;
     const int Kb = Kh < GCV_THREADS ? Kh : GCV_THREADS;
@@ -313,8 +313,8 @@ __device__ void gcv_accumulate(const Spec& sp, const void* coeff, int64_t b, int
         const int ka = 2 * kk, kb2 = ka + 1 < K ? ka + 1 : ka;
         const double mua = active ? mus[ka] : 1.0, mub = active ? mus[kb2] : 1.0;
         double Nat = 0.0, Dat = 0.0, Nbt = 0.0, Dbt = 0.0;
-        for (int64_t c0 = e_begin; c0 < e_end; c0 += GCV_CHUNK) {
-            const int len = static_cast<int>((e_end - c0) < GCV_CHUNK ? (e_end - c0) : GCV_CHUNK);
+        for (int64_t c0 = e_begin; c0 < e_end; c0 += chunk_cap) {
+            const int len = static_cast<int>((e_end - c0) < chunk_cap ? (e_end - c0) : chunk_cap);
             __syncthreads();
             for (int i = tid; i < len; i += GCV_THREADS) {
                 const int64_t e = c0 + i;
@@ -420,29 +420,45 @@ struct GcvOut {
     double* mubest;
 };
 
-__global__ __launch_bounds__(GCV_THREADS) void k_gcv_single(Spec sp, const void* __restrict__ coeff, GcvOut o) {
-    __shared__ double2 stage[GCV_CHUNK];
+// One block per item.  LDS sized to the item (dynamic): the staged elements of one chunk
+// (min(per_item, GCV_CHUNK) pairs), the K sums and G values, so that short items at small K
+// keep several blocks per CU; the staging chunk equals the static bound whenever an item
+// needs more than one, so the summation order does not depend on the sizing.
+inline size_t gcv_single_lds(int64_t per_item, int K, int* chunk_cap) {
+    const int cap = static_cast<int>(per_item < GCV_CHUNK ? (per_item < 1 ? 1 : per_item) : GCV_CHUNK);
+    *chunk_cap = cap;
+    return sizeof(double2) * (static_cast<size_t>(cap) + K) + sizeof(double) * K;
+}
+
+__global__ __launch_bounds__(GCV_THREADS) void k_gcv_single(Spec sp, const void* __restrict__ coeff, GcvOut o,
+                                                            int chunk_cap) {
+    extern __shared__ double2 dyn[];
     __shared__ double2 red[2 * GCV_THREADS];
-    __shared__ double2 sums[1024];
-    __shared__ double Gs[1024];
     __shared__ int kshared;
+    double2* stage = dyn;
+    double2* sums = dyn + chunk_cap;
+    double* Gs = reinterpret_cast<double*>(sums + o.K);
     const int64_t b = blockIdx.x;
     const double* mus = o.mus + b * o.mu_stride;
-    gcv_accumulate(sp, coeff, b, 0, sp.per_item, mus, o.K, sums, stage, red);
+    gcv_accumulate(sp, coeff, b, 0, sp.per_item, mus, o.K, sums, stage, red, chunk_cap);
     gcv_finish(sums, o.K, mus, o.G ? o.G + b * o.K : nullptr, o.kbest + b,
                o.mubest ? o.mubest + b : nullptr, Gs, &kshared);
 }
 
+// Partial sums over a span of a large item: staging chunks of GCV_PART_CHUNK pairs keep the
+// block at 32 KiB of LDS, five blocks per CU (the register bound) instead of four.
+constexpr int GCV_PART_CHUNK = 1536;
+
 __global__ __launch_bounds__(GCV_THREADS) void k_gcv_partial(Spec sp, const void* __restrict__ coeff, GcvOut o,
                                                              int64_t span, double2* part) {
-    __shared__ double2 stage[GCV_CHUNK];
+    __shared__ double2 stage[GCV_PART_CHUNK];
     __shared__ double2 red[2 * GCV_THREADS];
     const int64_t w = blockIdx.x, b = blockIdx.y;
     const int64_t e0 = w * span;
     int64_t e1 = e0 + span;
     if (e1 > sp.per_item) e1 = sp.per_item;
     const double* mus = o.mus + b * o.mu_stride;
-    gcv_accumulate(sp, coeff, b, e0, e1, mus, o.K, part + (b * gridDim.x + w) * o.K, stage, red);
+    gcv_accumulate(sp, coeff, b, e0, e1, mus, o.K, part + (b * gridDim.x + w) * o.K, stage, red, GCV_PART_CHUNK);
 }
 
 // Sum of the partial (N, D) of every grid value over the parts: block (group of 8 grid
@@ -1025,7 +1041,10 @@ extern "C" ht_status ht_gcv_scan(const ht_plan* plan, const void* coeff, const v
     const Spec sp = make_spec(plan, d, s, eig_batch, layout);
     GcvOut o{mu_grid, grid_per_item ? static_cast<int64_t>(K) : 0, K, G, k_best, mu_best};
     if (plan->ndim == 1) {
-        hipLaunchKernelGGL(k_gcv_single, dim3(static_cast<unsigned>(batch)), dim3(GCV_THREADS), 0, stream, sp, coeff, o);
+        int cap = 0;
+        const size_t lds = gcv_single_lds(sp.per_item, K, &cap);
+        hipLaunchKernelGGL(k_gcv_single, dim3(static_cast<unsigned>(batch)), dim3(GCV_THREADS), lds, stream, sp, coeff,
+                           o, cap);
         return check_hip(hipGetLastError(), "ht_gcv_scan launch");
     }
     if (batch > plan->max_batch) return fail(HT_ERR_INVALID_ARG, "ht_gcv_scan: batch exceeds the plan's max_batch");
@@ -1073,10 +1092,10 @@ static int64_t xg2_part_per_img(const ht_plan* p, int K) {
 
 namespace ht {
 // Reserve the plan's 2D exact GCV workspace for grids of up to max_k values: row-pass
-// outputs for a chunk of images (at most 64 MiB, at least one image), partials for the
-// same chunk, G for max_batch images.
+// outputs for a chunk of images (at most 256 MiB, at least one image: fewer, larger chunks
+// keep the column pass's grid wide), partials for the same chunk, G for max_batch images.
 ht_status reserve_exact_gcv_2d(ht_plan* p, int max_k) {
-    const int64_t cap = int64_t{1} << 23;  // doubles: 64 MiB
+    const int64_t cap = int64_t{1} << 25;  // doubles: 256 MiB
     const int64_t ri = xg2_rows_per_img(p, max_k);
     int64_t chunk = cap / ri;
     chunk = chunk < 1 ? 1 : (chunk > p->max_batch ? p->max_batch : chunk);

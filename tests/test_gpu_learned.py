@@ -13,7 +13,7 @@ from oracle import tikhonov as tk
 from oracle import transforms as tr
 from paper_0906_2704_amd import synth
 
-from parity import rel_normwise
+from parity import record, rel_normwise
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -145,6 +145,59 @@ def test_features_and_certified_restore_match_oracle(ht):
         assert kb[b] == kc and bool(fb[b]) == fell, (b, kb[b], kc, fb[b], fell)
         fr = tr.forward(kind, tk.tikhonov_filter(ghat, d, s, rb.mus[b][kc])).real
         assert rel_normwise(out[rb.offsets[b]:rb.offsets[b + 1]], fr) < 1e-12
+
+
+# (n, degree) covering every core form in several size classes: the half-output cosine
+# core (odd N where a chirp-z DFT of length N keeping (N+1)/2 outputs fits a smaller FFT),
+# the half-length cores of an even real-DFT length, and the chirp-z core
+CORE_FORM_ITEMS = [(2501, 2), (1101, 2), (259, 2), (600, 2), (257, 2), (3001, 2), (4097, 2),
+                   (2501, 1), (2500, 1), (700, 1), (1201, 3), (1200, 3)]
+
+
+def test_learned_passes_every_core_form(ht):
+    """Feature pass and certified pass (with and without the feature pass's spectrum) on
+    signals of every core form against the oracle."""
+    from paper_0906_2704_amd import learned
+    nv = [n for n, _ in CORE_FORM_ITEMS]
+    rb = synth.ragged_batch(len(nv), config=4, first_item=2100, sort_desc=False, n_values=nv, grid=(-8.0, 1.0))
+    rb.degree[:] = [d for _, d in CORE_FORM_ITEMS]
+    bt = ht.Batch(rb.n, rb.degree, np.diff(rb.psf_offsets), rb.psf_center)
+    g = torch.tensor(rb.g, device=DEV)
+    psf = torch.tensor(rb.psf_flat, device=DEV)
+    mus = torch.tensor(rb.mus, device=DEV)
+    spec = torch.empty_like(g)
+    coeff, feats = ht.ht_batch_features(bt, g, psf, spectrum=spec)
+    coeff_h, feats_h, spec_h = coeff.cpu().numpy(), feats.cpu().numpy(), spec.cpu().numpy()
+    _, _, kscan, _ = ht.ht_batch_restore(bt, g, psf, "D2", mus)
+    kscan = kscan.cpu().numpy()
+    lm = np.log10(rb.mus[0])
+    shifts = np.array([0, 3, -5, 1, 12, -2, 0, 9, -1, 2, -3, 0])
+    kh = np.clip(kscan + shifts, 0, learned.GRID_K - 1)
+    pred = torch.tensor(lm[kh].astype(np.float32), device=DEV)
+    coeff_rc = coeff.clone()
+    out, kb, _, fb = ht.ht_batch_restore_learned(bt, coeff, psf, "D2", mus, pred, cert_half=8, spectrum=spec)
+    out, kb, fb = out.cpu().numpy(), kb.cpu().numpy(), fb.cpu().numpy()
+    out_rc, kb_rc, _, fb_rc = ht.ht_batch_restore_learned(bt, coeff_rc, psf, "D2", mus, pred, cert_half=8)
+    assert np.array_equal(kb_rc.cpu().numpy(), kb) and np.array_equal(fb_rc.cpu().numpy(), fb)
+    out_rc = out_rc.cpu().numpy()
+    for b in range(len(nv)):
+        kind, d, s, ghat = _oracle_item(rb, b)
+        o0, o1 = rb.offsets[b], rb.offsets[b + 1]
+        what = "learned %s n=%d" % (kind, nv[b])
+        record("coeff " + what, rel_normwise(coeff_h[o0:o1], ghat), 1e-12)
+        assert rel_normwise(coeff_h[o0:o1], ghat) < 1e-12, what
+        assert rel_normwise(spec_h[o0:o1], d) < 1e-12, what
+        fw = olearned.features(ghat, d)
+        assert np.max(np.abs(feats_h[b] - fw)) < 1e-5 * max(1.0, np.max(np.abs(fw))), what
+        Gw, _, _ = tk.gcv_scan(ghat, d, s, rb.mus[b])
+        khat = olearned.nearest_index(rb.mus[b], float(np.float32(lm[kh[b]])))
+        kc, fell = olearned.certify(Gw, khat, half=8)
+        assert kb[b] == kc and bool(fb[b]) == fell, (what, kb[b], kc, fb[b], fell)
+        fr = tr.forward(kind, tk.tikhonov_filter(ghat, d, s, rb.mus[b][kc])).real
+        err = rel_normwise(out[o0:o1], fr)
+        record("restore " + what, err, 1e-12)
+        assert err < 1e-12, what
+        assert rel_normwise(out_rc[o0:o1], fr) < 1e-12, what
 
 
 def test_features_every_size_class(ht):
