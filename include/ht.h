@@ -290,7 +290,11 @@ typedef struct ht_batch ht_batch;
  * degree[b] / psf_symmetric[b] resolved per `family` as for ht_plan_create, and the
  * shape of each PSF mask (psf_len[b], psf_center[b]; 2m+1 <= n-2).  Builds the tables of
  * every distinct (n, kind) once.  Signals are concatenated in item order (offsets are
- * the prefix sums of n), masks likewise (prefix sums of psf_len).                    */
+ * the prefix sums of n), masks likewise (prefix sums of psf_len).  A signal's size class
+ * is the smallest FFT length (a power of two >= 512) its core transform needs: N + 2 for
+ * a half-length real core (core real-DFT length even: N for T_C, N + 1 for the sine
+ * cores), N + (N+1)/2 - 1 for the half-output cosine core (N odd), 2N - 1 for the
+ * chirp-z core, whichever is shortest (N = n - 2).                                    */
 ht_status ht_batch_create(int64_t count, const int64_t* n, const int* degree,
                           const int* psf_symmetric, int family, const int64_t* psf_len,
                           const int64_t* psf_center, ht_batch** out);
