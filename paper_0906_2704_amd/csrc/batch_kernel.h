@@ -491,6 +491,7 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
     __shared__ int s_item, s_kbest;
     __shared__ float s_pred;
     __shared__ double s_wsum[16];  // wave totals of the half sine core's prefix sums
+    __shared__ double2 s_spread[2 * (BLOCK / 64)];  // per-wave sums of a spread GCV pair
     const int tid = threadIdx.x;
     double* scratch = a.scratch + static_cast<int64_t>(blockIdx.x) * MAX_N;
     // Classes of 4096 points and more take their next queue entry while the current signal
@@ -882,9 +883,16 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             }
             constexpr int NW = BLOCK / 64;
             const int wv = tid >> 6, lane = tid & 63;
-            for (int k0 = 0; k0 < Kh; k0 += NW) {
+            // whole rounds of one pair per wave; a short remainder (at most a quarter of
+            // the waves' worth of pairs, after at least one whole round) is not left to a
+            // few waves while the rest wait: every wave takes a share of its elements
+            // (certificate brackets only: the scan's grids fill whole rounds)
+            const int full = Kh / NW * NW, rem = Kh - full;
+            const bool spread = CERT && full > 0 && rem > 0 && 4 * rem <= NW;
+            const int kwhole = spread ? full : Kh;
+            for (int k0 = 0; k0 < kwhole; k0 += NW) {
                 const int kk = k0 + wv;
-                if (kk < Kh) {  // uniform across the wave
+                if (kk < kwhole) {  // uniform across the wave
                     const int ka = klo + 2 * kk, kb2 = ka + 1 <= khi ? ka + 1 : ka;
                     double Na, Da, Nb, Db;
                     gcv_two(stage, n, lane, 64, mus[ka], mus[kb2], Na, Da, Nb, Db);
@@ -903,6 +911,42 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
                             if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka + 1] = Gs[ka + 1];
                         }
                     }
+                }
+            }
+            if (spread) {
+                for (int q = 0; q < rem; ++q) {
+                    const int ka = klo + 2 * (full + q), kb2 = ka + 1 <= khi ? ka + 1 : ka;
+                    double Na, Da, Nb, Db;
+                    // elements 64 wv + lane, + BLOCK, ...: lanes, then waves, added in order
+                    gcv_two(stage, n, tid, BLOCK, mus[ka], mus[kb2], Na, Da, Nb, Db);
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) {
+                        Na += __shfl_xor(Na, o, 64);
+                        Da += __shfl_xor(Da, o, 64);
+                        Nb += __shfl_xor(Nb, o, 64);
+                        Db += __shfl_xor(Db, o, 64);
+                    }
+                    if (lane == 0) {
+                        s_spread[2 * wv] = make_double2(Na, Da);
+                        s_spread[2 * wv + 1] = make_double2(Nb, Db);
+                    }
+                    __syncthreads();
+                    if (tid == 0) {
+                        double2 A = s_spread[0], B = s_spread[1];
+                        for (int w = 1; w < NW; ++w) {
+                            A.x += s_spread[2 * w].x;
+                            A.y += s_spread[2 * w].y;
+                            B.x += s_spread[2 * w + 1].x;
+                            B.y += s_spread[2 * w + 1].y;
+                        }
+                        Gs[ka] = A.x / (A.y * A.y);
+                        if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka] = Gs[ka];
+                        if (ka + 1 <= khi) {
+                            Gs[ka + 1] = B.x / (B.y * B.y);
+                            if (a.G) a.G[static_cast<int64_t>(sg.item) * K + ka + 1] = Gs[ka + 1];
+                        }
+                    }
+                    __syncthreads();
                 }
             }
             __syncthreads();

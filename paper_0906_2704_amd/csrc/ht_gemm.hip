@@ -298,17 +298,26 @@ __global__ __launch_bounds__(256) void k_prep_cols(Axis ax, PrepCols p) {
     __shared__ double tile[64][65];
     __shared__ double sx1[64], sxn[64];
     __shared__ double smax[4][64];
-    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    // ty (the wave) is uniform across a wave: the per-row terms (row[0], row[n1 - 1], c[k],
+    // c'[k]) then go through scalar loads
+    const int tid = threadIdx.x, tx = tid & 63, ty = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = ax.n, N = ax.N;
     const int64_t z = blockIdx.y;
     const int j = blockIdx.x * 64 + tx;
     const bool ok = j < p.ncols;
-    const double* base = p.in + z * p.img;
+    const double* __restrict__ base = p.in + z * p.img;
+    const double* __restrict__ c0 = p.c;
+    const double* __restrict__ cj0 = p.cj;
+    const double* __restrict__ c1 = p.c1;
+    const double* __restrict__ cj1 = p.cj1;
+    // COL_FWD: the column's axis-1 factors, loaded once
+    const bool fwd = p.mode == COL_FWD;
+    const double c1j = (fwd && ok) ? c1[j] : 0.0, cj1j = (fwd && ok) ? cj1[j] : 0.0;
     // entry i of this thread's column (ok threads only)
     auto col = [&](int i) {
-        const double* row = base + i * p.ld;
-        if (p.mode == COL_INV) return row[j];
-        return fma(row[0], p.c1[j], fma(row[p.n1 - 1], p.cj1[j], row[1 + j]));
+        const double* __restrict__ row = base + i * p.ld;
+        if (!fwd) return row[j];
+        return fma(row[0], c1j, fma(row[p.n1 - 1], cj1j, row[1 + j]));
     };
     // blockIdx.z: a range of the contraction (the bfloat16 parts need no per-row scale, so
     // their rows are split over several blocks); the first range writes the per-column data
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(256) void k_prep_cols(Axis ax, PrepCols p) {
     const double x1 = sx1[tx], xn = sxn[tx];
     auto r_at = [&](int k) {
         double r = col(k + 1);
-        if (p.mode == COL_FWD) r = fma(x1, p.c[k], fma(xn, p.cj[k], r));
+        if (fwd) r = fma(x1, c0[k], fma(xn, cj0[k], r));
         return r;
     };
     double s = 1.0;
