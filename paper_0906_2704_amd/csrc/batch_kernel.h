@@ -81,6 +81,7 @@ enum BatchMode {
 };
 constexpr int MLP_H = 256;  // hidden width of the network
 constexpr int NFEAT_G = 64, NFEAT_D = 8, NFEAT = NFEAT_G + NFEAT_D;
+constexpr int HS_MAX = 64;  // centred masks up to this half-width get their tap pairs staged in LDS
 constexpr double CERT_SLACK = 1.05;   // G(predicted) may exceed the bracket minimum by 5%
 constexpr float LOG10_2F = 0.30102999566398120f;
 
@@ -492,6 +493,7 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
     __shared__ float s_pred;
     __shared__ double s_wsum[16];  // wave totals of the half sine core's prefix sums
     __shared__ double2 s_spread[2 * (BLOCK / 64)];  // per-wave sums of a spread GCV pair
+    __shared__ double s_hs[HS_MAX + 1];              // tap pairs of a centred mask
     const int tid = threadIdx.x;
     double* scratch = a.scratch + static_cast<int64_t>(blockIdx.x) * MAX_N;
     // Classes of 4096 points and more take their next queue entry while the current signal
@@ -578,11 +580,29 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             bool done = false;
             if constexpr (S == 1) {
                 if (ax.half) {  // uniform per signal
-                    auto xr = [&](int j) { return g[j + 1] - ax.q[j + 1] * x1 - ax.q[N - j] * xn; };
-                    if (kind == HT_KIND_C)
-                        half_dct2<LOGP, SL>(c, ax, lds, tw, xr);
-                    else
-                        half_dst<LOGP, SL>(c, ax, lds, tw, xr, s_wsum);
+                    auto xg = [&](int j) { return g[j + 1] - ax.q[j + 1] * x1 - ax.q[N - j] * xn; };
+                    if constexpr (MODE == MODE_FEATURES || MODE == MODE_FUSED) {
+                        // the corrected interior goes through LDS: coalesced reads of g and q
+                        // here, the cores' reordered reads from LDS (measured faster in
+                        // these modes, slower in the scan mode, which reads g directly)
+                        double* rs = reinterpret_cast<double*>(lds);
+#pragma unroll
+                        for (int k = 0; k < SL; ++k) {
+                            const int j = tid + k * BLOCK;
+                            if (j < N) rs[j] = xg(j);
+                        }
+                        __syncthreads();
+                        auto xr = [&](int j) { return rs[j]; };
+                        if (kind == HT_KIND_C)
+                            half_dct2<LOGP, SL>(c, ax, lds, tw, xr);
+                        else
+                            half_dst<LOGP, SL>(c, ax, lds, tw, xr, s_wsum);
+                    } else {
+                        if (kind == HT_KIND_C)
+                            half_dct2<LOGP, SL>(c, ax, lds, tw, xg);
+                        else
+                            half_dst<LOGP, SL>(c, ax, lds, tw, xg, s_wsum);
+                    }
                     done = true;
                 }
             }
@@ -627,9 +647,16 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
         // and skips the staging)
         const bool staged = !LEAN;
         double* ctab = reinterpret_cast<double*>(lds);
+        // centred masks up to HS_MAX taps per side: the tap pairs h_t + h_{-t} staged in LDS
+        // (the same sums as in the loop below: results do not change)
+        const bool hstage = staged && 2 * sg.psf_center + 1 == sg.psf_len && sg.psf_center <= HS_MAX;
         if (staged) {
             __syncthreads();
             for (int r = tid; r <= den; r += BLOCK) ctab[r] = ax.tcos[r];
+            if (hstage) {
+                const int pc0 = sg.psf_center;
+                for (int t = tid; t <= pc0; t += BLOCK) s_hs[t] = t == 0 ? h[pc0] : h[pc0 + t] + h[pc0 - t];
+            }
             __syncthreads();
         }
         double z0 = 0.0;
@@ -663,6 +690,24 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
                     // d and s are read where they are used (lean_ds)
                 } else if (follow) {
                     // d_j arrives from the owner of mj below
+                } else if (centred && hstage) {
+                    double ev = s_hs[0], od = 0.0;
+                    int r = 0, t = 1;
+                    for (; t + 1 <= pc; t += 2) {
+                        r += num;
+                        if (r >= per) r -= per;
+                        od = fma(s_hs[t], ctab[r <= den ? r : per - r], od);
+                        r += num;
+                        if (r >= per) r -= per;
+                        ev = fma(s_hs[t + 1], ctab[r <= den ? r : per - r], ev);
+                    }
+                    if (t <= pc) {
+                        r += num;
+                        if (r >= per) r -= per;
+                        od = fma(s_hs[t], ctab[r <= den ? r : per - r], od);
+                    }
+                    acc = ev + od;
+                    if (lead) dmir[mj] = ev - od;
                 } else if (centred) {
                     // Re z = h_0 + sum_{t>0} (h_t + h_{-t}) cos(t theta), even and odd t apart
                     double ev = h[pc], od = 0.0;
