@@ -206,7 +206,7 @@ template <int LOGP, int SL>
 __device__ __forceinline__ void chirp_slots(double2 (&v)[SL], const Chirp& ch, int nin, int nout, double2* lds,
                                             const double2* __restrict__ tw) {
     constexpr int BLOCK = (1 << LOGP) / SL;
-    const int tid = threadIdx.x;
+    const int tid = local_tid();
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;
@@ -241,7 +241,7 @@ template <int LOGP, int SL, class X>
 __device__ __forceinline__ void half_dct2(double (&out)[SL], const Axis& ax, double2* lds,
                                           const double2* __restrict__ tw, X x) {
     constexpr int BLOCK = (1 << LOGP) / SL;
-    const int tid = threadIdx.x, N = ax.N, H = ax.H;
+    const int tid = local_tid(), N = ax.N, H = ax.H;
     auto vsrc = [&](int p) { return p < (N + 1) / 2 ? 2 * p : 2 * N - 2 * p - 1; };  // Makhoul order
     double2 v[SL];
     if (ax.half == 2) {  // N odd: V_k (k < H = (N+1)/2) of the real v, by chirp-z of length N
@@ -305,7 +305,7 @@ template <int LOGP, int SL, class Y>
 __device__ __forceinline__ void half_dct3(double (&out)[SL], const Axis& ax, double2* lds,
                                           const double2* __restrict__ tw, Y y) {
     constexpr int BLOCK = (1 << LOGP) / SL;
-    const int tid = threadIdx.x, N = ax.N, H = ax.H;
+    const int tid = local_tid(), N = ax.N, H = ax.H;
     auto wy = [&](int j) { return j < N ? (j == 0 ? ax.hw[0] : ax.hw[1]) * y(j) : 0.0; };
     // V_k = e^{i pi k/(2N)} (Y_k - i Y_{N-k}) for 0 < k <= H, and V_0 = 2 Y_0 (the k = 0
     // term has no mirror partner in v_p = sum_k V_k e^{2 pi i kp/N} / 2)
@@ -379,7 +379,7 @@ template <int LOGP, int SL, class X>
 __device__ __forceinline__ void half_dst(double (&out)[SL], const Axis& ax, double2* lds,
                                          const double2* __restrict__ tw, X x, double* wsum) {
     constexpr int BLOCK = (1 << LOGP) / SL;
-    const int tid = threadIdx.x, N = ax.N, H = ax.H, L = 2 * H;
+    const int tid = local_tid(), N = ax.N, H = ax.H, L = 2 * H;
     auto xs = [&](int t) { return t >= 1 && t <= N ? x(t - 1) : 0.0; };
     auto ys = [&](int t) {  // y_t = sin(pi t/L) (x_t + x_{L-t}) + (x_t - x_{L-t}) / 2
         const double sn = tload(ax.htw, H + 1 + (t <= H ? t : L - t)).x;
@@ -535,6 +535,8 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
         __syncthreads();
         if (qi >= count) break;
         if (PREFETCH && tid == 0) nxt = next_item();
+        // per signal: nothing derived from the thread index is held across signals
+        const int tid = local_tid();
         const RSig sg = uniform_load(a.sigs + start + qi);
         const Axis ax = uniform_load(a.axes + sg.axis);
         // read per signal so that no twiddle address is hoisted out of the queue loop
@@ -573,14 +575,14 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
         }
         {
             auto in_inv = [&](int, int j) {
-                return make_double2(g[j + 1] - ax.q[j + 1] * x1 - ax.q[N - j] * xn, 0.0);
+                return make_double2(g[j + 1] - dtab(ax.q, j + 1) * x1 - dtab(ax.q, N - j) * xn, 0.0);
             };
             auto park = [&](int j, double y) { f[j + 1] = y; };
             auto unpark = [&](int j) { return f[j + 1]; };
             bool done = false;
             if constexpr (S == 1) {
                 if (ax.half) {  // uniform per signal
-                    auto xg = [&](int j) { return g[j + 1] - ax.q[j + 1] * x1 - ax.q[N - j] * xn; };
+                    auto xg = [&](int j) { return g[j + 1] - dtab(ax.q, j + 1) * x1 - dtab(ax.q, N - j) * xn; };
                     if constexpr (MODE == MODE_FEATURES || MODE == MODE_FUSED) {
                         // the corrected interior goes through LDS: coalesced reads of g and q
                         // here, the cores' reordered reads from LDS (measured faster in
@@ -618,8 +620,8 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             for (int k = 0; k < SL; ++k) {
                 const int j = tid + k * BLOCK;
                 if (j < N) {
-                    c[k] -= ax.U[j] * a0;
-                    if (rank > 1) c[k] -= ax.U[N + j] * a1;
+                    c[k] -= dtab(ax.U, j) * a0;
+                    if (rank > 1) c[k] -= dtab(ax.U, N + j) * a1;
                 }
             }
         }
@@ -652,7 +654,7 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
         const bool hstage = staged && 2 * sg.psf_center + 1 == sg.psf_len && sg.psf_center <= HS_MAX;
         if (staged) {
             __syncthreads();
-            for (int r = tid; r <= den; r += BLOCK) ctab[r] = ax.tcos[r];
+            for (int r = tid; r <= den; r += BLOCK) ctab[r] = dtab(ax.tcos, r);
             if (hstage) {
                 const int pc0 = sg.psf_center;
                 for (int t = tid; t <= pc0; t += BLOCK) s_hs[t] = t == 0 ? h[pc0] : h[pc0 + t] + h[pc0 - t];
@@ -739,7 +741,7 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
                 dj[k] = acc;
                 const int rn = num % per;
                 const int rc = rn <= den ? rn : per - rn;
-                sj[k] = ident ? 1.0 : 2.0 - 2.0 * (staged ? ctab[rc] : ax.tcos[rc]);
+                sj[k] = ident ? 1.0 : 2.0 - 2.0 * (staged ? ctab[rc] : dtab(ax.tcos, rc));
             }
         }
         __syncthreads();
@@ -850,7 +852,7 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
                 sv = s_poly;
             } else {
                 const int rn = (kind == HT_KIND_C ? j : j + 1) % per;
-                sv = ident ? 1.0 : 2.0 - 2.0 * ax.tcos[rn <= den ? rn : per - rn];
+                sv = ident ? 1.0 : 2.0 - 2.0 * dtab(ax.tcos, rn <= den ? rn : per - rn);
             }
         };
         auto stage_fill = [&]() {
@@ -1143,9 +1145,9 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
             for (int k = 0; k < SL; ++k) {
                 const int j = tid + k * BLOCK;
                 if (j < N) {
-                    double y = u[k] + ax.q[j + 1] * fx1 + ax.q[N - j] * fxn;
-                    if (rank > 0) y += ax.bub[j] * beta0;
-                    if (rank > 1) y += ax.bub[N + j] * beta1;
+                    double y = u[k] + dtab(ax.q, j + 1) * fx1 + dtab(ax.q, N - j) * fxn;
+                    if (rank > 0) y += dtab(ax.bub, j) * beta0;
+                    if (rank > 1) y += dtab(ax.bub, N + j) * beta1;
                     f[j + 1] = y;
                     if (kind == HT_KIND_C) {
                         if (j == 0) f[0] = q1 * fx1 + u[k];

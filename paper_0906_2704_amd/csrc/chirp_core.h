@@ -29,7 +29,7 @@ __device__ __forceinline__ void chirp_core(OutT (&out)[SL], const ChirpT<C>& ch,
                                            const C* __restrict__ tw, In in, Park park, Unpark unpark) {
     constexpr int BLOCK = (1 << LOGP) / SL;
     constexpr bool REAL = sizeof(OutT) == sizeof(double);
-    const int tid = threadIdx.x;
+    const int tid = local_tid();
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         C v[SL];

@@ -48,13 +48,35 @@ __device__ __forceinline__ float2 cmake<float2>(double re, double im) {
     return make_float2(static_cast<float>(re), static_cast<float>(im));
 }
 
-// Table read with a 32-bit unsigned element index: lets the compiler address the table
-// as scalar base + 32-bit lane offset instead of a 64-bit address per lane.
+// Table read with a 32-bit unsigned element index through a global-memory pointer: the
+// tables are device allocations whose addresses reach the kernels inside records, so the
+// compiler cannot infer their address space and would emit flat loads (64-bit address per
+// lane, counted against the LDS wait counter too).  As a global pointer with a uniform
+// base the load is scalar base + 32-bit lane offset.
+typedef double gdbl2_t __attribute__((ext_vector_type(2)));
+typedef float gflt2_t __attribute__((ext_vector_type(2)));
+#define HT_GLOBAL __attribute__((address_space(1)))
+// element i >= 0 of a float64 device table
+__device__ __forceinline__ double dtab(const double* __restrict__ base, int i) {
+    return *(const HT_GLOBAL double*)((const HT_GLOBAL char*)base + (static_cast<unsigned>(i) << 3));
+}
 __device__ __forceinline__ double2 tload(const double2* __restrict__ base, unsigned idx) {
-    return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + (idx << 4));
+    const gdbl2_t v = *(const HT_GLOBAL gdbl2_t*)((const HT_GLOBAL char*)base + (idx << 4));
+    return make_double2(v.x, v.y);
 }
 __device__ __forceinline__ float2 tload(const float2* __restrict__ base, unsigned idx) {
-    return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base) + (idx << 3));
+    const gflt2_t v = *(const HT_GLOBAL gflt2_t*)((const HT_GLOBAL char*)base + (idx << 3));
+    return make_float2(v.x, v.y);
+}
+
+// threadIdx.x as a value the compiler cannot equate with other reads of it.  Addresses
+// and table offsets derived from it are then computed where they are used: otherwise they
+// are hoisted out of the persistent kernels' queue loops, held across a whole signal and,
+// under a register cap, spilled and reloaded before every use.
+__device__ __forceinline__ int local_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
 }
 
 // multiply by exp(DIR * i pi / 2): -i for the forward direction, +i for the inverse
@@ -148,7 +170,7 @@ template <int R, int DIR, int BLOCK, int SLOTS, bool LAST, class C, bool FIRST =
 __device__ __forceinline__ void stockham_pass(C (&v)[SLOTS], C* lds, const C* __restrict__ tw, int Ns) {
     static_assert(!FIRST || (R == 8 && !LAST && BLOCK % 64 == 0), "permuted first pass: radix 8, 64-aligned");
     constexpr int NB = SLOTS / R;  // butterflies per thread
-    const int tid = threadIdx.x;
+    const int tid = local_tid();
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         const int t = tid + c * BLOCK;
