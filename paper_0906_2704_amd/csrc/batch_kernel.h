@@ -206,7 +206,8 @@ template <int LOGP, int SL>
 __device__ __forceinline__ void chirp_slots(double2 (&v)[SL], const Chirp& ch, int nin, int nout, double2* lds,
                                             const double2* __restrict__ tw) {
     constexpr int BLOCK = (1 << LOGP) / SL;
-    const int tid = local_tid();
+    // a fresh thread index per phase: no lane offset is held across the FFTs
+    int tid = local_tid();
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;
@@ -215,11 +216,13 @@ __device__ __forceinline__ void chirp_slots(double2 (&v)[SL], const Chirp& ch, i
     __builtin_amdgcn_sched_barrier(0);
     fft_slots<LOGP, -1, SL>(v, lds, tw);
     __builtin_amdgcn_sched_barrier(0);
+    tid = local_tid();
 #pragma unroll
     for (int k = 0; k < SL; ++k) v[k] = cmul(v[k], tload(ch.B, static_cast<unsigned>(tid + k * BLOCK)));
     __builtin_amdgcn_sched_barrier(0);
     fft_slots<LOGP, 1, SL>(v, lds, tw);
     __builtin_amdgcn_sched_barrier(0);
+    tid = local_tid();
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int j = tid + k * BLOCK;
@@ -241,7 +244,8 @@ template <int LOGP, int SL, class X>
 __device__ __forceinline__ void half_dct2(double (&out)[SL], const Axis& ax, double2* lds,
                                           const double2* __restrict__ tw, X x) {
     constexpr int BLOCK = (1 << LOGP) / SL;
-    const int tid = local_tid(), N = ax.N, H = ax.H;
+    int tid = local_tid();
+    const int N = ax.N, H = ax.H;
     auto vsrc = [&](int p) { return p < (N + 1) / 2 ? 2 * p : 2 * N - 2 * p - 1; };  // Makhoul order
     double2 v[SL];
     if (ax.half == 2) {  // N odd: V_k (k < H = (N+1)/2) of the real v, by chirp-z of length N
@@ -252,6 +256,7 @@ __device__ __forceinline__ void half_dct2(double (&out)[SL], const Axis& ax, dou
         }
         __syncthreads();
         chirp_slots<LOGP, SL>(v, ax.ana, N, H, lds, tw);
+        tid = local_tid();
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
             const int m = tid + k * BLOCK;
@@ -278,6 +283,7 @@ __device__ __forceinline__ void half_dct2(double (&out)[SL], const Axis& ax, dou
     }
     __syncthreads();
     chirp_slots<LOGP, SL>(v, ax.ana, H, H, lds, tw);
+    tid = local_tid();
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int m = tid + k * BLOCK;
@@ -305,7 +311,8 @@ template <int LOGP, int SL, class Y>
 __device__ __forceinline__ void half_dct3(double (&out)[SL], const Axis& ax, double2* lds,
                                           const double2* __restrict__ tw, Y y) {
     constexpr int BLOCK = (1 << LOGP) / SL;
-    const int tid = local_tid(), N = ax.N, H = ax.H;
+    int tid = local_tid();
+    const int N = ax.N, H = ax.H;
     auto wy = [&](int j) { return j < N ? (j == 0 ? ax.hw[0] : ax.hw[1]) * y(j) : 0.0; };
     // V_k = e^{i pi k/(2N)} (Y_k - i Y_{N-k}) for 0 < k <= H, and V_0 = 2 Y_0 (the k = 0
     // term has no mirror partner in v_p = sum_k V_k e^{2 pi i kp/N} / 2)
@@ -326,6 +333,7 @@ __device__ __forceinline__ void half_dct3(double (&out)[SL], const Axis& ax, dou
         }
         __syncthreads();
         chirp_slots<LOGP, SL>(v, ax.syn, H, N, lds, tw);
+        tid = local_tid();
         double* ur = reinterpret_cast<double*>(lds);
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
@@ -355,6 +363,7 @@ __device__ __forceinline__ void half_dct3(double (&out)[SL], const Axis& ax, dou
     }
     __syncthreads();
     chirp_slots<LOGP, SL>(v, ax.syn, H, H, lds, tw);
+    tid = local_tid();
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int m = tid + k * BLOCK;
@@ -379,7 +388,8 @@ template <int LOGP, int SL, class X>
 __device__ __forceinline__ void half_dst(double (&out)[SL], const Axis& ax, double2* lds,
                                          const double2* __restrict__ tw, X x, double* wsum) {
     constexpr int BLOCK = (1 << LOGP) / SL;
-    const int tid = local_tid(), N = ax.N, H = ax.H, L = 2 * H;
+    int tid = local_tid();
+    const int N = ax.N, H = ax.H, L = 2 * H;
     auto xs = [&](int t) { return t >= 1 && t <= N ? x(t - 1) : 0.0; };
     auto ys = [&](int t) {  // y_t = sin(pi t/L) (x_t + x_{L-t}) + (x_t - x_{L-t}) / 2
         const double sn = tload(ax.htw, H + 1 + (t <= H ? t : L - t)).x;
@@ -394,6 +404,7 @@ __device__ __forceinline__ void half_dst(double (&out)[SL], const Axis& ax, doub
     }
     __syncthreads();
     chirp_slots<LOGP, SL>(v, ax.ana, H, H, lds, tw);
+    tid = local_tid();
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int m = tid + k * BLOCK;

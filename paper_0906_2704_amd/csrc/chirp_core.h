@@ -29,9 +29,10 @@ __device__ __forceinline__ void chirp_core(OutT (&out)[SL], const ChirpT<C>& ch,
                                            const C* __restrict__ tw, In in, Park park, Unpark unpark) {
     constexpr int BLOCK = (1 << LOGP) / SL;
     constexpr bool REAL = sizeof(OutT) == sizeof(double);
-    const int tid = local_tid();
 #pragma unroll
     for (int s = 0; s < S; ++s) {
+        // a fresh thread index per phase: no lane offset is held across the FFTs
+        int tid = local_tid();
         C v[SL];
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
@@ -47,11 +48,13 @@ __device__ __forceinline__ void chirp_core(OutT (&out)[SL], const ChirpT<C>& ch,
         __builtin_amdgcn_sched_barrier(0);
         fft_slots<LOGP, -1, SL>(v, lds, tw);
         __builtin_amdgcn_sched_barrier(0);
+        tid = local_tid();
 #pragma unroll
         for (int k = 0; k < SL; ++k) v[k] = cmul(v[k], tload(ch.B, static_cast<unsigned>(s * (1 << LOGP) + tid + k * BLOCK)));
         __builtin_amdgcn_sched_barrier(0);
         fft_slots<LOGP, 1, SL>(v, lds, tw);
         __builtin_amdgcn_sched_barrier(0);
+        tid = local_tid();
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
             const int j = tid + k * BLOCK;

@@ -147,6 +147,31 @@ def test_features_and_certified_restore_match_oracle(ht):
         assert rel_normwise(out[rb.offsets[b]:rb.offsets[b + 1]], fr) < 1e-12
 
 
+def test_certified_pass_with_and_without_spectrum_agree_on_many_signals(ht):
+    """The certified pass that takes d from the feature pass and the one that recomputes it
+    give the same choices and restorations to rounding on 256 signals (every size class, the
+    8192-point chirp-z class with one to four filled slots per thread among them)."""
+    from paper_0906_2704_amd import learned
+    rb, bt, g, psf, mus = _small_batch(ht, 256, first_item=1000)
+    spec = torch.empty_like(g)
+    coeff, _ = ht.ht_batch_features(bt, g, psf, spectrum=spec)
+    _, _, kscan, _ = ht.ht_batch_restore(bt, g, psf, "D2", mus)
+    lm = np.log10(rb.mus[0])
+    shifts = np.resize(np.array([0, 1, -2, 3, 8, -9, 0, 2, -1, 20, 4, -4]), 256)
+    kh = np.clip(kscan.cpu().numpy() + shifts, 0, learned.GRID_K - 1)
+    pred = torch.tensor(lm[kh].astype(np.float32), device=DEV)
+    coeff_rc = coeff.clone()
+    out, kb, _, fb = ht.ht_batch_restore_learned(bt, coeff, psf, "D2", mus, pred, cert_half=8, spectrum=spec)
+    out_rc, kb_rc, _, fb_rc = ht.ht_batch_restore_learned(bt, coeff_rc, psf, "D2", mus, pred, cert_half=8)
+    assert np.array_equal(kb_rc.cpu().numpy(), kb.cpu().numpy())
+    assert np.array_equal(fb_rc.cpu().numpy(), fb.cpu().numpy())
+    out, out_rc = out.cpu().numpy(), out_rc.cpu().numpy()
+    worst = max(rel_normwise(out_rc[rb.offsets[b]:rb.offsets[b + 1]], out[rb.offsets[b]:rb.offsets[b + 1]])
+                for b in range(rb.n.size))
+    record("certified pass with / without spectrum, 256 signals", worst, 1e-13)
+    assert worst < 1e-13
+
+
 # (n, degree) covering every core form in several size classes: the half-output cosine
 # core (odd N where a chirp-z DFT of length N keeping (N+1)/2 outputs fits a smaller FFT),
 # the half-length cores of an even real-DFT length, and the chirp-z core
