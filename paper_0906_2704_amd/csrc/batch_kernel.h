@@ -214,13 +214,13 @@ __device__ __forceinline__ void chirp_slots(double2 (&v)[SL], const Chirp& ch, i
         v[k] = j < nin ? cmul(v[k], tload(ch.pre, j)) : make_double2(0.0, 0.0);
     }
     __builtin_amdgcn_sched_barrier(0);
-    fft_slots<LOGP, -1, SL>(v, lds, tw);
+    fft_slots<LOGP, -1, SL, true>(v, lds, tw);
     __builtin_amdgcn_sched_barrier(0);
     tid = local_tid();
 #pragma unroll
     for (int k = 0; k < SL; ++k) v[k] = cmul(v[k], tload(ch.B, static_cast<unsigned>(tid + k * BLOCK)));
     __builtin_amdgcn_sched_barrier(0);
-    fft_slots<LOGP, 1, SL>(v, lds, tw);
+    fft_slots<LOGP, 1, SL, true>(v, lds, tw);
     __builtin_amdgcn_sched_barrier(0);
     tid = local_tid();
 #pragma unroll
@@ -619,7 +619,7 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
                     done = true;
                 }
             }
-            if (!done) chirp_core<LOGP, S, SL>(c, ax.ana, ax.ana.mode, N, lds, tw, in_inv, park, unpark);
+            if (!done) chirp_core<LOGP, S, SL, true>(c, ax.ana, ax.ana.mode, N, lds, tw, in_inv, park, unpark);
         }
         if (rank > 0) {  // DST family correction x_mid -= U (E^T K)^{-1} E^T x_mid
             if (tid < rank) bc[tid].x = c[0];
@@ -1151,7 +1151,7 @@ void k_restore(RaggedArgs a, int cls, int start, int count) {
                     done = true;
                 }
             }
-            if (!done) chirp_core<LOGP, S, SL>(u, ax.syn, ax.syn.mode, N, lds, tw, in_fwd, park, unpark);
+            if (!done) chirp_core<LOGP, S, SL, true>(u, ax.syn, ax.syn.mode, N, lds, tw, in_fwd, park, unpark);
 #pragma unroll
             for (int k = 0; k < SL; ++k) {
                 const int j = tid + k * BLOCK;

@@ -24,15 +24,16 @@ __device__ __forceinline__ double2 select_out(double2 y, int mode) {
 // in(k, j) returns x_j for the slot k holding j = tid + k * BLOCK < N; the result goes to
 // out[k].  OutT = double2 keeps the complex result (selected by `mode`), OutT = double the
 // real or imaginary part only.  The workgroup has 2^LOGP / SL threads.
-template <int LOGP, int S, int SL, class OutT, class In, class Park, class Unpark, class C>
+template <int LOGP, int S, int SL, bool FRESH = false, class OutT, class In, class Park, class Unpark, class C>
 __device__ __forceinline__ void chirp_core(OutT (&out)[SL], const ChirpT<C>& ch, int mode, int N, C* lds,
                                            const C* __restrict__ tw, In in, Park park, Unpark unpark) {
     constexpr int BLOCK = (1 << LOGP) / SL;
     constexpr bool REAL = sizeof(OutT) == sizeof(double);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        // a fresh thread index per phase: no lane offset is held across the FFTs
-        int tid = local_tid();
+        // FRESH (persistent kernels): a fresh thread index per phase, so that no lane offset
+        // is held across the FFTs
+        int tid = FRESH ? local_tid() : static_cast<int>(threadIdx.x);
         C v[SL];
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
@@ -46,15 +47,15 @@ __device__ __forceinline__ void chirp_core(OutT (&out)[SL], const ChirpT<C>& ch,
             if (s == 1) v[k] = cmul(v[k], tload(tw, j * (TWN >> (LOGP + 1))));  // exp(-2 pi i j / M)
         }
         __builtin_amdgcn_sched_barrier(0);
-        fft_slots<LOGP, -1, SL>(v, lds, tw);
+        fft_slots<LOGP, -1, SL, FRESH>(v, lds, tw);
         __builtin_amdgcn_sched_barrier(0);
-        tid = local_tid();
+        if (FRESH) tid = local_tid();
 #pragma unroll
         for (int k = 0; k < SL; ++k) v[k] = cmul(v[k], tload(ch.B, static_cast<unsigned>(s * (1 << LOGP) + tid + k * BLOCK)));
         __builtin_amdgcn_sched_barrier(0);
-        fft_slots<LOGP, 1, SL>(v, lds, tw);
+        fft_slots<LOGP, 1, SL, FRESH>(v, lds, tw);
         __builtin_amdgcn_sched_barrier(0);
-        tid = local_tid();
+        if (FRESH) tid = local_tid();
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
             const int j = tid + k * BLOCK;

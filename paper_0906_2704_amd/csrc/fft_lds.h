@@ -166,11 +166,14 @@ __host__ __device__ constexpr int fft_block_for(int logp) { return (1 << logp) /
 // that puts the eight lanes of a 128-byte row in eight different 16-byte bank groups --
 // and its read-back applies the same permutation (BLOCK is a multiple of 64, so every
 // read element tid + s * BLOCK has (e >> 3) & 7 = (tid >> 3) & 7).
-template <int R, int DIR, int BLOCK, int SLOTS, bool LAST, class C, bool FIRST = false>
+//
+// FRESH: the pass takes its own copy of the thread index (local_tid) -- for the persistent
+// kernels, whose loop-invariant offsets would otherwise be held (and spilled) across signals.
+template <int R, int DIR, int BLOCK, int SLOTS, bool LAST, class C, bool FIRST = false, bool FRESH = false>
 __device__ __forceinline__ void stockham_pass(C (&v)[SLOTS], C* lds, const C* __restrict__ tw, int Ns) {
     static_assert(!FIRST || (R == 8 && !LAST && BLOCK % 64 == 0), "permuted first pass: radix 8, 64-aligned");
     constexpr int NB = SLOTS / R;  // butterflies per thread
-    const int tid = local_tid();
+    const int tid = FRESH ? local_tid() : static_cast<int>(threadIdx.x);
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         const int t = tid + c * BLOCK;
@@ -230,7 +233,7 @@ __device__ __forceinline__ void stockham_pass(C (&v)[SLOTS], C* lds, const C* __
 // Full FFT of length P = 2^LOGP on the slots v (natural order in, natural order out),
 // SL points per thread, P / SL threads.  The radix-8 passes run as a loop that is not
 // unrolled, so only one pass's addresses are live at a time.
-template <int LOGP, int DIR, int SL = fft_slots_for(LOGP), class C>
+template <int LOGP, int DIR, int SL = fft_slots_for(LOGP), bool FRESH = false, class C>
 __device__ __forceinline__ void fft_slots(C (&v)[SL], C* lds, const C* __restrict__ tw) {
     constexpr int BL = (1 << LOGP) / SL;
     static_assert(SL == 8 || SL == 16, "8 or 16 points per thread");
@@ -239,17 +242,17 @@ __device__ __forceinline__ void fft_slots(C (&v)[SL], C* lds, const C* __restric
     constexpr int REM = LOGP % 3;
     constexpr int NMID = REM ? NR8 : NR8 - 1;  // radix-8 passes that go through LDS
     static_assert(NMID >= 1, "the first pass goes through LDS");
-    stockham_pass<8, DIR, BL, SL, false, C, true>(v, lds, tw, 1);
+    stockham_pass<8, DIR, BL, SL, false, C, true, FRESH>(v, lds, tw, 1);
     int Ns = 8;
 #pragma unroll 1
     for (int p = 1; p < NMID; ++p) {
-        stockham_pass<8, DIR, BL, SL, false>(v, lds, tw, Ns);
+        stockham_pass<8, DIR, BL, SL, false, C, false, FRESH>(v, lds, tw, Ns);
         Ns *= 8;
     }
     if constexpr (REM == 0)
-        stockham_pass<8, DIR, BL, SL, true>(v, lds, tw, Ns);
+        stockham_pass<8, DIR, BL, SL, true, C, false, FRESH>(v, lds, tw, Ns);
     else
-        stockham_pass<(1 << REM), DIR, BL, SL, true>(v, lds, tw, Ns);
+        stockham_pass<(1 << REM), DIR, BL, SL, true, C, false, FRESH>(v, lds, tw, Ns);
 }
 
 }  // namespace ht
